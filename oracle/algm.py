@@ -1,0 +1,167 @@
+"""Algorithm M of the paper, inner loop only (oracle, FP64, CPU).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Follows section 3 in its own order, with n_org = 1 (orthonormalise every step,
+as in Table 1 and Table 2) and subspace diagonalisation switched off:
+
+  * start: W^(0) = Orth(U^(0)) (Algorithm B step 1 asks for orthonormal
+    data; the raw start is orthonormalised first), C^(0) = E(W^(0)), Q^(0) = 1;
+  * search direction (section 3.2): z_i = H w_i - sigma_ii w_i with
+    sigma_ii = <H w_i, w_i>, H = H(rho(W));
+  * step size (section 3.2): the Barzilai-Borwein values
+        tau1 = tr<S^T S> / |tr<S^T Y>|,   tau2 = |tr<S^T Y>| / tr<Y^T Y>,
+    S = W^(l) - W^(l-1), Y = Z^(l) - Z^(l-1); one tau for every orbital;
+  * backtracking (eq. "ene-de"): tau = tau_BB delta^s with s the smallest
+    non-negative integer for which
+        E(Orth(W - tau Z)) <= C^(l) - rho1 tau ||Z||_F^2,
+    then Q^(l+1) = eta Q^(l) + 1, C^(l+1) = (eta Q^(l) C^(l) + E^(l+1)) / Q^(l+1);
+  * the relative energy change df^(l) = |E^(l-1) - E^(l)| / (|E^(l-1)| + 1)
+    (section 4.2) and its 3-step mean as the stopping rule.
+
+Readings where the paper leaves a choice open (each is also listed with the
+design notes of the build):
+  * tau1 versus tau2: `bb_mode` 1 or 2 picks one; 0 alternates, tau1 on odd l,
+    tau2 on even l.
+  * l = 0 has no S, Y: tau_BB = tau_init, by default 1 / lambda_max(K).
+  * |tr<S^T Y>| is the absolute value of the trace.
+  * ||Z||_F^2 = sum_i <z_i, z_i> in the grid inner product.
+  * the Armijo test evaluates the orthonormalised trial Orth(W - tau Z).
+  * s is capped at s_max; if no s <= s_max passes, the s_max trial is taken
+    and the step is flagged as not accepted.
+  * a non-finite or non-positive BB value falls back to tau_init.
+
+Parity: trajectory values have no published reference (the paper prints none
+for a reproducible system): "parity unpinned" for the tau / s / E sequences
+themselves.  The converged results are pinned by closed forms and dense
+diagonalisation, and every step is checked against the invariants of
+eq. "ene-de" (tests/test_oracle_algm.py).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import ks
+from .orth import orth
+
+
+@dataclasses.dataclass
+class Params:
+    rho1: float = 1e-4
+    delta: float = 0.1
+    eta: float = 0.85
+    bb_mode: int = 0
+    tau_init: float = 0.0     # <= 0: 1 / lambda_max(K)
+    s_max: int = 10
+
+
+def lambda_max_kinetic(h):
+    """Largest eigenvalue of K = -1/2 Delta_h (the 1-D symbol peaks at theta = pi)."""
+    s = ks.FD8[0] + 2.0 * sum(ks.FD8[m] * (-1.0) ** m for m in range(1, 5))
+    return 0.5 * 3.0 * (-s) / (h * h)
+
+
+@dataclasses.dataclass
+class StepRecord:
+    l: int
+    s: int
+    accepted: bool
+    E: float
+    tau_bb: float
+    tau: float
+    zz: float
+    df: float
+    C: float
+    Q: float
+    trials: list
+
+
+class AlgorithmM:
+    """Stateful runner; `step()` performs one accepted iteration."""
+
+    def __init__(self, U0, sys: ks.System, params: Params | None = None, vext=None,
+                 orthonormalize_start=True):
+        self.sys = sys
+        self.p = params or Params()
+        self.h = sys.h
+        self.vext = vext
+        if self.vext is None:
+            self.vext = (ks.external_potential(sys) if sys.terms & ks.TERM_EXT
+                         else np.zeros((sys.n,) * 3))
+        self.tau_init = self.p.tau_init if self.p.tau_init > 0 else 1.0 / lambda_max_kinetic(self.h)
+        W = orth(U0, self.h)[0] if orthonormalize_start else np.array(U0, dtype=np.float64)
+        self.W = W
+        self.terms, self.HW, self.sig = ks.energy_and_h(W, sys, self.vext)
+        self.E = self.terms.E
+        self.C = self.E
+        self.Q = 1.0
+        self.l = 0
+        self.Wp = None
+        self.Zp = None
+        self.df_hist = []
+
+    def _dot(self, a, b):
+        return float(np.sum(ks.inner(a, b, self.h)))
+
+    def direction(self):
+        return self.HW - self.sig[:, None, None, None] * self.W
+
+    def bb_step(self, Z):
+        p = self.p
+        if self.l == 0 or self.Wp is None:
+            return self.tau_init
+        S = self.W - self.Wp
+        Y = Z - self.Zp
+        ss = self._dot(S, S)
+        sy = abs(self._dot(S, Y))
+        yy = self._dot(Y, Y)
+        mode = p.bb_mode if p.bb_mode in (1, 2) else (1 if self.l % 2 == 1 else 2)
+        try:
+            tau = ss / sy if mode == 1 else sy / yy
+        except ZeroDivisionError:
+            tau = float("nan")
+        if not math.isfinite(tau) or tau <= 0.0:
+            tau = self.tau_init
+        return tau
+
+    def step(self) -> StepRecord:
+        p = self.p
+        Z = self.direction()
+        zz = self._dot(Z, Z)
+        tau_bb = self.bb_step(Z)
+        trials = []
+        accepted = False
+        for s in range(p.s_max + 1):
+            tau = tau_bb * p.delta ** s
+            Wt, _ = orth(self.W - tau * Z, self.h)
+            terms, HWt, sigt = ks.energy_and_h(Wt, self.sys, self.vext)
+            trials.append((tau, terms.E))
+            if terms.E <= self.C - p.rho1 * tau * zz:
+                accepted = True
+                break
+        E_old = self.E
+        self.Wp, self.Zp = self.W, Z
+        self.W, self.HW, self.sig, self.terms = Wt, HWt, sigt, terms
+        self.E = terms.E
+        Qn = p.eta * self.Q + 1.0
+        self.C = (p.eta * self.Q * self.C + self.E) / Qn
+        self.Q = Qn
+        df = abs(E_old - self.E) / (abs(E_old) + 1.0)
+        self.df_hist.append(df)
+        rec = StepRecord(self.l, s, accepted, self.E, tau_bb, tau, zz, df, self.C, self.Q, trials)
+        self.l += 1
+        return rec
+
+    def converged(self, tol):
+        return len(self.df_hist) >= 3 and float(np.mean(self.df_hist[-3:])) < tol
+
+    def run(self, n_iter, tol=None):
+        hist = []
+        for _ in range(n_iter):
+            hist.append(self.step())
+            if tol is not None and self.converged(tol):
+                break
+        return hist

@@ -1,0 +1,197 @@
+"""Pins of the oracle's discrete Kohn-Sham model (CPU only).
+
+Each test checks the oracle against something other than itself: a continuum
+limit, an independent solver, a textbook constant, finite differences, or an
+invariant that the paper states (section 2.2: E(UP) = E(U)).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+import synth
+from oracle import ks, cg
+from oracle.orth import orth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _smooth_field(n, L):
+    a = 2 * np.pi / L
+    x = (L / n) * np.arange(n)
+    X = x[None, None, :]
+    Y = x[None, :, None]
+    Zc = x[:, None, None]
+    fx = np.exp(np.sin(a * X))
+    fy = np.exp(np.cos(a * Y))
+    fz = 1.0 + 0.5 * np.sin(a * Zc)
+    fxx = a * a * (np.cos(a * X) ** 2 - np.sin(a * X)) * fx
+    fyy = a * a * (np.sin(a * Y) ** 2 - np.cos(a * Y)) * fy
+    fzz = -0.5 * a * a * np.sin(a * Zc)
+    f = fx * fy * fz
+    lap = fxx * fy * fz + fx * fyy * fz + fx * fy * fzz
+    return f, lap
+
+
+def test_fd8_converges_at_eighth_order():
+    """Continuum limit: error of Delta_h on a smooth periodic field falls as h^8."""
+    L = 7.0
+    errs = []
+    for n in (32, 64):
+        f, lap = _smooth_field(n, L)
+        errs.append(np.max(np.abs(ks.laplacian(f, L / n) - lap)))
+    order = np.log2(errs[0] / errs[1])
+    assert order > 7.6, (errs, order)   # a 2nd- or 4th-order slip gives <= 4.2
+    assert errs[1] < 1e-6 * np.max(np.abs(lap))
+
+
+def test_fd8_tiny_grid_wraps_coincident_neighbours():
+    """On n < 9 the wrap adds coincident offsets: still exact on constants and
+    symmetric (a self-adjoint operator)."""
+    rng = np.random.default_rng(0)
+    for n in (3, 5, 8):
+        h = 0.7
+        assert np.max(np.abs(ks.laplacian(np.ones((n, n, n)), h))) < 1e-12
+        a = rng.standard_normal((n, n, n))
+        b = rng.standard_normal((n, n, n))
+        assert abs(np.sum(a * ks.laplacian(b, h)) - np.sum(b * ks.laplacian(a, h))) < 1e-9
+
+
+def test_poisson_fft_matches_independent_cg():
+    rng = np.random.default_rng(1)
+    n, h = 12, 0.45
+    f = rng.standard_normal((n, n, n))
+    V_fft = ks.poisson(f, h)
+    V_cg, it = cg.poisson_cg(f, h, rtol=1e-14)
+    assert it > 10
+    assert np.max(np.abs(V_fft - V_cg)) < 1e-11 * np.max(np.abs(V_fft))
+    assert abs(np.mean(V_fft)) < 1e-13
+
+
+def test_poisson_continuum_limit_plane_wave():
+    """f = cos(2 pi x / L): the continuum solution is 4 pi cos / k^2."""
+    L, n = 9.0, 64
+    k = 2 * np.pi / L
+    x = (L / n) * np.arange(n)
+    f = np.broadcast_to(np.cos(k * x)[None, None, :], (n, n, n)).copy()
+    V = ks.poisson(f + 3.0, L / n)          # the constant is removed by the background
+    assert np.max(np.abs(V - 4 * np.pi * f / k ** 2)) < 1e-9 * 4 * np.pi / k ** 2
+
+
+def test_ion_density_normalised():
+    cfg = synth.custom("t", 40, 10.0, 3, 2.0, 0.5, 1)
+    R, Z, s = synth.atoms(cfg)
+    sys_ = ks.System(cfg.n, cfg.L, R, Z, s, np.array([2.0]))
+    rho = ks.ion_density(sys_)
+    assert abs(sys_.dv * rho.sum() - Z.sum()) < 1e-10
+
+
+def test_external_potential_is_periodic_smeared_coulomb():
+    """Near one ion, V_ext = -Z erf(r/s)/r - (2 pi/3) Z r^2 / L^3 + const + O(r^4/L^5).
+
+    The r^2 term is the neutralising background (a uniform charge -Z/L^3 has
+    potential +(2 pi/3)(Z/L^3) r^2, and V_ext carries the opposite sign of the
+    potential of the ionic charge); cubic symmetry removes the
+    image quadratic term.  Compared as differences against the point r = 0.
+    """
+    L, n, Zv, s = 16.0, 128, 3.0, 0.8
+    R = np.array([[0.0, 0.0, 0.0]])
+    sys_ = ks.System(n, L, R, np.array([Zv]), np.array([s]), np.array([2.0]))
+    V = ks.external_potential(sys_)
+    h = L / n
+    idx = np.arange(1, 13)
+    r = idx * h
+    free = -Zv * erf(r / s) / r
+    free0 = -Zv * 2.0 / (s * np.sqrt(np.pi))
+    model = free - free0 - (2 * np.pi / 3) * Zv * r ** 2 / L ** 3
+    got = V[0, 0, idx] - V[0, 0, 0]
+    assert np.max(np.abs(got - model)) < 2e-5 * abs(free0)
+
+
+def test_exchange_uniform_density_and_dirac_constant():
+    cx = json.load(open(os.path.join(GOLD, "dirac_exchange.json")))["C_x"]
+    assert abs(ks.CX - cx) < 1e-15
+    n, L, c = 6, 5.0, 0.37
+    ex, vx = ks.exchange(np.full((n, n, n), c), L / n)
+    assert abs(ex - (-cx * c ** (4 / 3) * L ** 3)) < 1e-12 * abs(ex)
+    # v_x is the derivative of the exchange energy density: d(-C_x rho^4/3)/d rho
+    assert np.allclose(vx, -(4.0 / 3.0) * cx * c ** (1 / 3), rtol=1e-14)
+
+
+def _small_system(n=10, L=6.0, N=2, M=2, seed=5, terms=ks.TERM_ALL):
+    cfg = synth.custom("t", n, L, M, (1.0, 2.0), (0.45, 0.7), N, seed_id=seed)
+    R, Z, s = synth.atoms(cfg)
+    return ks.System(n, L, R, Z, s, synth.occupations(cfg), terms), cfg
+
+
+def test_energy_gradient_matches_central_differences():
+    sys_, cfg = _small_system()
+    U = synth.orbitals(cfg) * 0.05
+    G = ks.energy_gradient(U, sys_)
+    for seed in (11, 12):
+        D = synth.random_direction(U.shape, seed)
+        eps = 1e-5
+        Ep = ks.energy(U + eps * D, sys_).E
+        Em = ks.energy(U - eps * D, sys_).E
+        fd = (Ep - Em) / (2 * eps)
+        an = float(np.sum(G * D))
+        assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (fd, an)
+
+
+def test_energy_terms_gradient_each_term():
+    """Each term's gradient alone (drops a wrong factor in any single term)."""
+    for terms in (ks.TERM_KIN, ks.TERM_EXT, ks.TERM_HARTREE, ks.TERM_XC):
+        sys_, cfg = _small_system(terms=terms)
+        U = synth.orbitals(cfg) * 0.05
+        G = ks.energy_gradient(U, sys_)
+        D = synth.random_direction(U.shape, 21)
+        eps = 1e-5
+        fd = (ks.energy(U + eps * D, sys_).E - ks.energy(U - eps * D, sys_).E) / (2 * eps)
+        an = float(np.sum(G * D))
+        assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (terms, fd, an)
+
+
+def test_forces_match_central_differences():
+    sys_, cfg = _small_system(n=16, L=7.0, M=3, N=2, seed=8)
+    U = orth(synth.orbitals(cfg), sys_.h)[0]
+    dR, ds = ks.forces(U, sys_)
+    hstep = 1e-4
+    for I in range(3):
+        for a in range(3):
+            Rp = sys_.R.copy(); Rp[I, a] += hstep
+            Rm = sys_.R.copy(); Rm[I, a] -= hstep
+            Ep = ks.energy(U, ks.System(sys_.n, sys_.L, Rp, sys_.Z, sys_.sigma, sys_.occ)).E
+            Em = ks.energy(U, ks.System(sys_.n, sys_.L, Rm, sys_.Z, sys_.sigma, sys_.occ)).E
+            fd = (Ep - Em) / (2 * hstep)
+            assert abs(fd - dR[I, a]) < 1e-6 * max(1.0, abs(fd)), (I, a, fd, dR[I, a])
+        sp = sys_.sigma.copy(); sp[I] += hstep
+        sm = sys_.sigma.copy(); sm[I] -= hstep
+        Ep = ks.energy(U, ks.System(sys_.n, sys_.L, sys_.R, sys_.Z, sp, sys_.occ)).E
+        Em = ks.energy(U, ks.System(sys_.n, sys_.L, sys_.R, sys_.Z, sm, sys_.occ)).E
+        fd = (Ep - Em) / (2 * hstep)
+        assert abs(fd - ds[I]) < 1e-6 * max(1.0, abs(fd)), (I, fd, ds[I])
+
+
+def test_rotation_invariance_and_charge():
+    """E(WP) = E(W) for orthogonal P (section 2.2); h^3 sum rho = sum f."""
+    sys_, cfg = _small_system(N=3, M=2)
+    W = orth(synth.orbitals(cfg), sys_.h)[0]
+    P, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((3, 3)))
+    WP = np.einsum("ij,i...->j...", P, W)
+    assert abs(ks.energy(W, sys_).E - ks.energy(WP, sys_).E) < 1e-11
+    rho = ks.density(W, sys_.occ)
+    assert abs(sys_.dv * rho.sum() - sys_.occ.sum()) < 1e-12
+
+
+def test_energy_terms_free_box_plane_wave():
+    """Kinetic energy of a normalised plane wave approaches k^2/2 per electron."""
+    n, L = 48, 8.0
+    k = 2 * np.pi / L
+    x = (L / n) * np.arange(n)
+    u = np.broadcast_to(np.cos(k * x)[None, None, :], (n, n, n)).copy()
+    u /= np.sqrt(ks.inner(u, u, L / n))
+    sys_ = ks.System(n, L, np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.array([2.0]), ks.TERM_KIN)
+    E = ks.energy(u[None], sys_).E
+    assert abs(E - 2 * 0.5 * k * k) < 1e-9
