@@ -1,0 +1,294 @@
+"""Python binding of libpou.so, the MI355X library for the parallel
+orbital-updating optimisation of Kohn-Sham DFT (arXiv 1510.07230).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI declared in include/pou.h.  PyTorch supplies device memory
+and the stream.  There is no fallback: if the library is missing or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpou.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pou.h")
+
+POU_OK = 0
+STATUS = {0: "POU_OK", -1: "POU_ERR_ARG", -2: "POU_ERR_STATE", -3: "POU_ERR_HIP",
+          -4: "POU_ERR_OOM", -5: "POU_ERR_NOT_SPD", -6: "POU_ERR_CG_NO_CONV",
+          -7: "POU_ERR_NONFINITE"}
+FP64, MIXED = 0, 1
+TERM_KIN, TERM_EXT, TERM_HARTREE, TERM_XC, TERM_ALL = 1, 2, 4, 8, 15
+
+
+class PouError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("L", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("rho1", ctypes.c_double), ("delta", ctypes.c_double), ("eta", ctypes.c_double),
+                ("bb_mode", ctypes.c_int), ("tau_init", ctypes.c_double), ("s_max", ctypes.c_int),
+                ("orth_passes", ctypes.c_int), ("cg_rtol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int), ("cg_precond", ctypes.c_int),
+                ("terms", ctypes.c_uint)]
+
+
+class EnergyTerms(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("E_kin", ctypes.c_double), ("E_ext", ctypes.c_double),
+                ("E_H", ctypes.c_double), ("E_x", ctypes.c_double), ("cg_iters", ctypes.c_int)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("l", ctypes.c_int), ("s", ctypes.c_int), ("accepted", ctypes.c_int),
+                ("cg_iters", ctypes.c_int), ("E", ctypes.c_double), ("tau_bb", ctypes.c_double),
+                ("tau", ctypes.c_double), ("zz", ctypes.c_double), ("df", ctypes.c_double),
+                ("C", ctypes.c_double), ("Q", ctypes.c_double), ("gram_dev", ctypes.c_double)]
+
+
+_LIB = None
+_vp, _dp, _i, _d = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double
+
+_SIGNATURES = {
+    "pou_default_params": (None, [ctypes.POINTER(Params)]),
+    "pou_create": (_i, [ctypes.POINTER(_vp), _i, _vp]),
+    "pou_destroy": (_i, [_vp]),
+    "pou_last_error": (ctypes.c_char_p, [_vp]),
+    "pou_set_system": (_i, [_vp, ctypes.POINTER(Grid), _i, _dp, _dp, _dp, _i, _dp, _i,
+                            ctypes.POINTER(Params)]),
+    "pou_energy": (_i, [_vp, _vp, ctypes.POINTER(EnergyTerms)]),
+    "pou_orthonormalize": (_i, [_vp, _vp, _dp]),
+    "pou_orbital_update_step": (_i, [_vp, _vp, ctypes.POINTER(StepInfo)]),
+    "pou_energy_backward": (_i, [_vp, _vp, _d, _vp, _vp, _vp]),
+    "pou_hamiltonian_apply": (_i, [_vp, _vp, _vp, _dp]),
+    "pou_get_fields": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "pou_gram": (_i, [_vp, _vp, _dp]),
+    "pou_convert": (_i, [_vp, _vp, _i, _vp, _i, ctypes.c_longlong]),
+    "pou_reset_history": (_i, [_vp]),
+}
+
+
+def header_symbols(path=HEADER):
+    """Names of the functions declared in include/pou.h."""
+    txt = open(path).read()
+    return sorted(set(re.findall(r"\b(pou_[a-z_]+)\s*\(", txt)))
+
+
+def lib():
+    """Load libpou.so (built by paper_1510_07230_amd.build); raise if missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1510_07230_amd.build")
+        # Load torch's HIP runtime first: libpou then binds to that same copy
+        # (matching soname) instead of pulling in a second runtime.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().pou_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+class System:
+    """One context: grid, ions, occupations, precision and parameters.
+
+    Orbital blocks are torch tensors on the context's device, shape
+    [N, n, n, n], float64 (precision "fp64") or float32 ("mixed").
+    """
+
+    def __init__(self, n, L, R, Z, sigma, occ, precision="fp64", params=None, device=0,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.n, self.L = int(n), float(L)
+        self.N = len(occ)
+        self.M = len(Z)
+        self.prec = FP64 if precision in ("fp64", FP64) else MIXED
+        self.dtype = torch.float64 if self.prec == FP64 else torch.float32
+        self.params = params if params is not None else default_params()
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = self._stream_handle()
+        rc = lib().pou_create(ctypes.byref(h), int(device), st)
+        if rc != POU_OK:
+            raise PouError(rc, "pou_create failed")
+        self._h = h
+        self.set_system(R, Z, sigma, occ)
+
+    def _stream_handle(self):
+        torch = self.torch
+        s = self._stream if self._stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _check(self, rc):
+        if rc != POU_OK:
+            msg = lib().pou_last_error(self._h)
+            raise PouError(rc, msg.decode() if msg else "")
+
+    def set_system(self, R, Z, sigma, occ):
+        R = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(-1, 3))
+        Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float64))
+        sigma = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64))
+        occ = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        self.R, self.Z, self.sigma, self.occ = R, Z, sigma, occ
+        self.M = len(Z)
+        self.N = len(occ)
+        g = Grid(self.n, self.L)
+        self._check(lib().pou_set_system(self._h, ctypes.byref(g), self.M, _dptr(R), _dptr(Z),
+                                         _dptr(sigma), self.N, _dptr(occ), self.prec,
+                                         ctypes.byref(self.params)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pou_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_block(self, data=None):
+        """Device block [N, n, n, n] of this system's dtype (copy of `data` if given)."""
+        torch = self.torch
+        shape = (self.N, self.n, self.n, self.n)
+        if data is None:
+            return torch.zeros(shape, dtype=self.dtype, device=self.device)
+        t = torch.as_tensor(np.asarray(data)).to(self.device, self.dtype)
+        if tuple(t.shape) != shape:
+            t = t.reshape(shape)
+        return t.contiguous()
+
+    def _block(self, U):
+        if U.device != self.device or U.dtype != self.dtype or not U.is_contiguous():
+            raise ValueError(f"block must be contiguous {self.dtype} on {self.device}")
+        if U.numel() != self.N * self.n ** 3:
+            raise ValueError("block has the wrong number of elements")
+        return ctypes.c_void_p(U.data_ptr())
+
+    def energy(self, U):
+        t = EnergyTerms()
+        self._check(lib().pou_energy(self._h, self._block(U), ctypes.byref(t)))
+        return {"E": t.E, "E_kin": t.E_kin, "E_ext": t.E_ext, "E_H": t.E_H, "E_x": t.E_x,
+                "cg_iters": t.cg_iters}
+
+    def orthonormalize_(self, U):
+        err = ctypes.c_double(0.0)
+        self._check(lib().pou_orthonormalize(self._h, self._block(U), ctypes.byref(err)))
+        return err.value
+
+    def step_(self, U):
+        info = StepInfo()
+        self._check(lib().pou_orbital_update_step(self._h, self._block(U), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in StepInfo._fields_}
+
+    def hamiltonian(self, U):
+        HU = self.torch.empty_like(U)
+        sig = np.zeros(self.N)
+        self._check(lib().pou_hamiltonian_apply(self._h, self._block(U), self._block(HU),
+                                                _dptr(sig)))
+        return HU, sig
+
+    def fields(self):
+        torch = self.torch
+        out = {k: torch.empty((self.n,) * 3, dtype=torch.float64, device=self.device)
+               for k in ("rho", "vh", "veff", "vext")}
+        self._check(lib().pou_get_fields(self._h, *[ctypes.c_void_p(out[k].data_ptr())
+                                                    for k in ("rho", "vh", "veff", "vext")]))
+        return out
+
+    def gram(self, U):
+        G = np.zeros((self.N, self.N))
+        self._check(lib().pou_gram(self._h, self._block(U), _dptr(G)))
+        return G
+
+    def backward(self, U, gE=1.0, want_dU=True, want_forces=True):
+        torch = self.torch
+        dU = torch.empty_like(U) if want_dU else None
+        dR = torch.empty((self.M, 3), dtype=torch.float64, device=self.device) if want_forces else None
+        ds = torch.empty((self.M,), dtype=torch.float64, device=self.device) if want_forces else None
+        p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        self._check(lib().pou_energy_backward(self._h, self._block(U), float(gE), p(dU), p(dR),
+                                              p(ds)))
+        return dU, dR, ds
+
+    def convert(self, src, dst):
+        pr = lambda t: FP64 if t.dtype == self.torch.float64 else MIXED
+        if src.numel() != dst.numel():
+            raise ValueError("size mismatch")
+        self._check(lib().pou_convert(self._h, ctypes.c_void_p(src.data_ptr()), pr(src),
+                                      ctypes.c_void_p(dst.data_ptr()), pr(dst), src.numel()))
+        return dst
+
+    def reset_history(self):
+        self._check(lib().pou_reset_history(self._h))
+
+
+def _energy_fn():
+    import torch
+
+    class EnergyFn(torch.autograd.Function):
+        """E(U; R, sigma) with gradients dE/dU = 2 f_i h^3 H u_i and the forces
+        dE/dR, dE/dsigma from pou_energy_backward."""
+
+        @staticmethod
+        def forward(ctx, U, R, sigma, system):
+            Rn = R.detach().cpu().numpy()
+            sn = sigma.detach().cpu().numpy()
+            if not (np.array_equal(Rn, system.R) and np.array_equal(sn, system.sigma)):
+                system.set_system(Rn, system.Z, sn, system.occ)
+            e = system.energy(U.detach())
+            ctx.system = system
+            ctx.rdev = (R.device, R.dtype, sigma.device, sigma.dtype)
+            ctx.save_for_backward(U)
+            return torch.tensor(e["E"], dtype=torch.float64, device=U.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            (U,) = ctx.saved_tensors
+            dU, dR, ds = ctx.system.backward(U.detach(), float(g.item()),
+                                             want_dU=ctx.needs_input_grad[0],
+                                             want_forces=(ctx.needs_input_grad[1]
+                                                          or ctx.needs_input_grad[2]))
+            if dR is not None:
+                dR = dR.to(ctx.rdev[0], ctx.rdev[1])
+                ds = ds.to(ctx.rdev[2], ctx.rdev[3])
+            return dU, dR, ds, None
+
+    return EnergyFn
+
+
+def __getattr__(name):
+    if name == "EnergyFn":
+        return _energy_fn()
+    raise AttributeError(name)

@@ -1,0 +1,814 @@
+// Host engine behind the C ABI of include/pou.h.
+//
+// Owns the device workspace of one system and drives the inner loop of
+// Algorithm M (section 3.3, n_org = 1): per step the search direction
+// z_i = H w_i - sigma_ii w_i (section 3.2) is never stored; the trial point
+// W - tau Z is formed by one elementwise kernel, orthonormalised by Cholesky QR
+// through the Gram matrix (section 3.2), its energy (eq. "energy") evaluated,
+// and the non-monotone Armijo test of eq. "ene-de" decides on the host.  On
+// acceptance one kernel writes the new iterate into the caller's block and
+// forms the per-orbital dot products that the next Barzilai-Borwein step
+// needs, so no copy of the previous iterate is kept.
+#include "pou_internal.h"
+#include "../../include/pou.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using pou::i64;
+
+namespace {
+
+struct Report {
+  // device layout of one evaluation report: [sigma N | kin N | e3 | info 2*kMaxPass]
+  static constexpr int kMaxPass = 4;
+  static int size(int N) { return 2 * N + 3 + 2 * kMaxPass; }
+};
+
+double lambda1(int n, double h, int k) {
+  // eigenvalue of -D2 (periodic 8th-order) on Fourier mode k: -(c0 + 2 sum c_m cos m theta)/h^2
+  const double c[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+  const double th = 2.0 * M_PI * (double)k / (double)n;
+  double s = c[0];
+  for (int m = 1; m <= 4; ++m) s += 2.0 * c[m] * std::cos(m * th);
+  return -s / (h * h);
+}
+
+}  // namespace
+
+struct pou_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool have_system = false;
+
+  // system
+  int n = 0;
+  double L = 0, h = 0, dv = 0;
+  i64 ng = 0;
+  int N = 0;
+  int M = 0;
+  pou_precision prec = POU_FP64;
+  pou_params p{};
+  std::vector<double> occ, atoms;  // atoms: [M][5]
+  size_t es = 8;                   // element size of blocks
+
+  // launch shapes
+  pou::StencilArgs st{};
+  int nblk_field = 0;   // blocks of field reductions
+  int nblk_orb = 0;     // blocks per orbital for block reductions
+  int nsplit = 0;       // Gram K splits
+  int npairs = 0;
+
+  // device buffers
+  double *d_occ = nullptr, *d_atoms = nullptr;
+  double *d_rho = nullptr, *d_vh = nullptr, *d_vext = nullptr, *d_veff = nullptr;
+  float *d_veff32 = nullptr;
+  double *d_rhoion = nullptr, *d_lam1 = nullptr;
+  double *d_cg_r = nullptr, *d_cg_p = nullptr, *d_cg_q = nullptr, *d_cg_z = nullptr;
+  double2 *d_fft0 = nullptr, *d_fft1 = nullptr;
+  double *d_sc = nullptr;      // CG scalars
+  double *d_part = nullptr;    // generic partial sums
+  size_t part_len = 0;
+  double *d_gpart = nullptr;   // Gram partials
+  double *d_G = nullptr, *d_Minv = nullptr, *d_Minv2 = nullptr, *d_Mcomb = nullptr;
+  double *d_red = nullptr;     // small reduction outputs
+  double *d_rep[2] = {nullptr, nullptr};  // evaluation reports (current, trial)
+  void *d_HW = nullptr, *d_HWt = nullptr, *d_Wt = nullptr, *d_W1 = nullptr, *d_W2 = nullptr;
+  std::vector<void *> allocs;
+
+  // iteration state
+  const void *last_U = nullptr;  // block the step cache belongs to
+  bool cur_valid = false;        // d_HW / d_rep[0] hold H W, sigma of last_U
+  bool hist = false;             // BB history available
+  int l = 0;
+  double E = 0, C = 0, Q = 1;
+  double zz_next = 0, ss = 0, sy = 0, yy = 0;
+  // last evaluation (pou_energy / step) for backward and diagnostics
+  const void *eval_ptr = nullptr;
+  void *eval_HU = nullptr;
+  int last_cg_iters = 0;
+  std::vector<double> rep_host;
+};
+
+namespace {
+
+pou_status fail(pou_ctx *c, pou_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, POU_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename P>
+pou_status dalloc(pou_ctx *c, P **ptr, size_t bytes) {
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes ? bytes : 8);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, POU_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(p);
+  *ptr = (P *)p;
+  return POU_OK;
+}
+
+void free_all(pou_ctx *c) {
+  for (void *p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  c->d_occ = c->d_atoms = c->d_rho = c->d_vh = c->d_vext = c->d_veff = nullptr;
+  c->d_veff32 = nullptr;
+  c->d_rhoion = c->d_lam1 = nullptr;
+  c->d_cg_r = c->d_cg_p = c->d_cg_q = c->d_cg_z = nullptr;
+  c->d_fft0 = c->d_fft1 = nullptr;
+  c->d_sc = c->d_part = c->d_gpart = c->d_G = c->d_Minv = c->d_Minv2 = c->d_Mcomb = nullptr;
+  c->d_red = nullptr;
+  c->d_rep[0] = c->d_rep[1] = nullptr;
+  c->d_HW = c->d_HWt = c->d_Wt = c->d_W1 = c->d_W2 = nullptr;
+  c->have_system = false;
+}
+
+#define CHK(expr)                       \
+  do {                                  \
+    pou_status s_ = (expr);             \
+    if (s_ != POU_OK) return s_;        \
+  } while (0)
+
+pou_status sync_read(pou_ctx *c, void *host, const void *dev, size_t bytes) {
+  HIPCHK(c, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return POU_OK;
+}
+
+// ------------------------------------------------------------------ Poisson
+
+// Solve -Lap x = 4 pi (f - mean f) by conjugate gradients, warm-started from x,
+// optionally preconditioned by the exact spectral inverse of -Lap.
+pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxit,
+                   bool precond, int *iters) {
+  hipStream_t s = c->stream;
+  const i64 ng = c->ng;
+  const int nb = c->nblk_field;
+  const double ih2 = 1.0 / (c->h * c->h);
+  double *sc = c->d_sc;  // [0] rz new, [1] rz old, [2] pq, [3] rr, [4] bb, [5] sum
+  HIPCHK(c, pou::launch_dot2(f, nullptr, c->d_part, ng, nb, s));
+  HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
+  HIPCHK(c, pou::launch_neg_lap(x, c->d_cg_q, nullptr, c->n, ih2, nb, s));
+  HIPCHK(c, pou::launch_cg_rhs_residual(f, sc + 5, c->d_cg_q, c->d_cg_r, c->d_part, ng, nb, s));
+  HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 2, 1.0, s));
+  double rb[2];
+  CHK(sync_read(c, rb, sc + 3, sizeof(rb)));
+  const double bb = rb[1];
+  double rr = rb[0];
+  if (!std::isfinite(bb) || !std::isfinite(rr))
+    return fail(c, POU_ERR_NONFINITE, "Poisson right-hand side or residual is not finite");
+  int it = 0;
+  const int check = precond ? 1 : 8;
+  bool conv = !(rr > rtol * rtol * bb);
+  while (!conv && it < maxit) {
+    const double *z = c->d_cg_r;
+    if (precond) {
+      HIPCHK(c, pou::launch_spectral_inverse(c->d_cg_r, c->d_cg_z, c->d_fft0, c->d_fft1,
+                                             c->d_lam1, c->n, s));
+      z = c->d_cg_z;
+    }
+    HIPCHK(c, pou::launch_dot2(c->d_cg_r, z, c->d_part, ng, nb, s));
+    HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 0, 1, nb, 1, 1.0, s));
+    HIPCHK(c, pou::launch_cg_update_p(c->d_cg_p, z, sc + 0, sc + 1, it == 0, ng, s));
+    HIPCHK(c, pou::launch_neg_lap(c->d_cg_p, c->d_cg_q, c->d_part, c->n, ih2, nb, s));
+    HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 2, 1, nb, 1, 1.0, s));
+    HIPCHK(c, pou::launch_cg_update_xr(x, c->d_cg_r, c->d_cg_p, c->d_cg_q, sc + 0, sc + 2,
+                                       c->d_part, ng, nb, s));
+    HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 1, 1.0, s));
+    HIPCHK(c, hipMemcpyAsync(sc + 1, sc + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
+    ++it;
+    if (it % check == 0 || it == maxit) {
+      CHK(sync_read(c, &rr, sc + 3, sizeof(double)));
+      if (!std::isfinite(rr)) return fail(c, POU_ERR_NONFINITE, "Poisson CG residual is not finite");
+      conv = !(rr > rtol * rtol * bb);
+    }
+  }
+  // fix the gauge: zero mean
+  HIPCHK(c, pou::launch_dot2(x, nullptr, c->d_part, ng, nb, s));
+  HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
+  HIPCHK(c, pou::launch_remove_mean(x, sc + 5, ng, s));
+  if (iters) *iters = it;
+  if (!conv)
+    return fail(c, POU_ERR_CG_NO_CONV,
+                "Poisson CG did not reach rtol " + std::to_string(rtol) + " in " +
+                    std::to_string(maxit) + " iterations");
+  return POU_OK;
+}
+
+// ------------------------------------------------------------------ energy
+
+// Evaluate rho (unless already formed), V_H, V_eff, H W and the energy terms
+// of W; report (sigma, kin, energy sums) lands in rep on the device.
+template <typename T>
+pou_status evaluate(pou_ctx *c, const T *W, T *HWout, double *rep, bool rho_ready,
+                    int *cg_iters) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  if (!rho_ready) HIPCHK(c, pou::launch_density<T>(W, c->d_occ, c->d_rho, N, c->ng, s));
+  int it = 0;
+  if (c->p.terms & POU_TERM_HARTREE) {
+    CHK(poisson(c, c->d_rho, c->d_vh, c->p.cg_rtol, c->p.cg_maxit, c->p.cg_precond != 0, &it));
+  }
+  c->last_cg_iters = it;
+  if (cg_iters) *cg_iters = it;
+  HIPCHK(c, pou::launch_xc_veff(c->d_rho, c->d_vh, c->d_vext, c->d_veff,
+                                sizeof(T) == 4 ? c->d_veff32 : nullptr, c->d_part, c->ng,
+                                c->p.terms, c->nblk_field, s));
+  HIPCHK(c, pou::launch_segment_sum(c->d_part, rep + 2 * N, 1, c->nblk_field, 3, c->dv, s));
+  const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
+  HIPCHK(c, pou::launch_hamiltonian<T>(W, veff, HWout, c->d_part, N, c->st, s));
+  HIPCHK(c, pou::launch_segment_sum(c->d_part, rep, N, c->st.ntile * c->st.nzc, 2, c->dv, s));
+  return POU_OK;
+}
+
+void terms_from_report(const pou_ctx *c, const double *rep, pou_energy_terms *t) {
+  const int N = c->N;
+  double ekin = 0.0;
+  for (int i = 0; i < N; ++i) ekin += c->occ[i] * rep[N + i];
+  if (!(c->p.terms & POU_TERM_KIN)) ekin = 0.0;
+  const double cx = 0.73855876638202240;  // 3/4 (3/pi)^(1/3)
+  const double ex = -cx * rep[2 * N + 0];
+  const double eext = rep[2 * N + 1];
+  const double eh = 0.5 * rep[2 * N + 2];
+  t->E_kin = ekin;
+  t->E_x = (c->p.terms & POU_TERM_XC) ? ex : 0.0;
+  t->E_ext = (c->p.terms & POU_TERM_EXT) ? eext : 0.0;
+  t->E_H = (c->p.terms & POU_TERM_HARTREE) ? eh : 0.0;
+  t->E = t->E_kin + t->E_x + t->E_ext + t->E_H;
+  t->cg_iters = c->last_cg_iters;
+}
+
+// ------------------------------------------------------------------ orth
+
+template <typename T>
+pou_status gram(pou_ctx *c, const T *X, bool bf16) {
+  hipStream_t s = c->stream;
+  if (bf16 && sizeof(T) == 4)
+    HIPCHK(c, pou::launch_gram_partial_bf16((const float *)X, c->N, c->ng, c->nsplit,
+                                            c->d_gpart, s));
+  else
+    HIPCHK(c, pou::launch_gram_partial<T>(X, c->N, c->ng, c->nsplit, c->d_gpart, s));
+  HIPCHK(c, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+  return POU_OK;
+}
+
+// Cholesky-QR passes of X into out (X and out distinct, both not aliasing d_W1).
+// info[2p], info[2p+1] = (not-SPD flag, max|G-I|) of pass p.  The last apply
+// also forms rho when rho != nullptr and the fused path is available.
+template <typename T>
+pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info, bool want_rho,
+                       bool *rho_done) {
+  hipStream_t s = c->stream;
+  const bool mixed = sizeof(T) == 4;
+  const T *cur = X;
+  const bool fused_ok = ((c->N + 15) / 16 + 7) / 8 == 1;
+  *rho_done = false;
+  for (int p = 0; p < passes; ++p) {
+    CHK(gram<T>(c, cur, mixed && p == 0));
+    HIPCHK(c, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->N, info + 2 * p, s));
+    const bool last = (p == passes - 1);
+    T *dst = last ? out : (T *)c->d_W1;
+    if (cur == dst) return fail(c, POU_ERR_ARG, "internal: aliasing orth buffers");
+    double *rho = (last && want_rho && fused_ok) ? c->d_rho : nullptr;
+    HIPCHK(c, pou::launch_apply_lower<T>(c->d_Minv, cur, dst, c->N, c->ng, c->d_occ, rho, s));
+    if (rho) *rho_done = true;
+    cur = dst;
+  }
+  return POU_OK;
+}
+
+// ------------------------------------------------------------------ step
+
+template <typename T>
+pou_status restart(pou_ctx *c, const T *W) {
+  int it = 0;
+  CHK(evaluate<T>(c, W, (T *)c->d_HW, c->d_rep[0], false, &it));
+  std::vector<double> &r = c->rep_host;
+  r.resize(Report::size(c->N));
+  CHK(sync_read(c, r.data(), c->d_rep[0], sizeof(double) * Report::size(c->N)));
+  pou_energy_terms t;
+  terms_from_report(c, r.data(), &t);
+  if (!std::isfinite(t.E)) return fail(c, POU_ERR_NONFINITE, "energy of U is not finite");
+  c->E = t.E;
+  c->C = t.E;
+  c->Q = 1.0;
+  c->l = 0;
+  c->hist = false;
+  c->last_U = W;
+  c->cur_valid = true;
+  c->eval_ptr = W;
+  c->eval_HU = c->d_HW;
+  return POU_OK;
+}
+
+template <typename T>
+pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  if (W != c->last_U || !c->cur_valid) CHK(restart<T>(c, W));
+  double zz;
+  if (!c->hist) {
+    HIPCHK(c, pou::launch_zz<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_part, N, c->ng,
+                                c->nblk_orb, s));
+    HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
+    std::vector<double> z(N);
+    CHK(sync_read(c, z.data(), c->d_red, sizeof(double) * N));
+    zz = 0.0;
+    for (double v : z) zz += v;
+  } else {
+    zz = c->zz_next;
+  }
+  // Barzilai-Borwein step (section 3.2): tau1 = ss/|sy|, tau2 = |sy|/yy
+  double tau_bb = c->p.tau_init;
+  if (c->hist) {
+    const double asy = std::fabs(c->sy);
+    const int mode = (c->p.bb_mode == 1 || c->p.bb_mode == 2) ? c->p.bb_mode
+                                                               : ((c->l % 2 == 1) ? 1 : 2);
+    const double t = (mode == 1) ? c->ss / asy : asy / c->yy;
+    if (std::isfinite(t) && t > 0.0) tau_bb = t;
+  }
+  const int passes = c->p.orth_passes;
+  pou_energy_terms et{};
+  double tau = tau_bb;
+  int s_acc = 0, cg_total = 0;
+  bool accepted = false;
+  double gram_dev = 0.0;
+  std::vector<double> &r = c->rep_host;
+  r.resize(Report::size(N));
+  for (int sidx = 0; sidx <= c->p.s_max; ++sidx) {
+    tau = tau_bb * std::pow(c->p.delta, sidx);
+    s_acc = sidx;
+    HIPCHK(c, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt, N,
+                                   c->ng, s));
+    bool rho_done = false;
+    double *rep_t = c->d_rep[1];
+    CHK(orth_passes<T>(c, (const T *)c->d_Wt, (T *)c->d_W2, passes, rep_t + 2 * N + 3, true,
+                       &rho_done));
+    int it = 0;
+    CHK(evaluate<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, rho_done, &it));
+    cg_total += it;
+    CHK(sync_read(c, r.data(), rep_t, sizeof(double) * Report::size(N)));
+    for (int p = 0; p < passes; ++p)
+      if (r[2 * N + 3 + 2 * p] != 0.0)
+        return fail(c, POU_ERR_NOT_SPD, "trial Gram matrix is not positive definite (pass " +
+                                             std::to_string(p) + ")");
+    gram_dev = r[2 * N + 4];
+    terms_from_report(c, r.data(), &et);
+    if (!std::isfinite(et.E)) return fail(c, POU_ERR_NONFINITE, "trial energy is not finite");
+    // eq. "ene-de": E(W(tau)) <= C - rho1 tau ||Z||_F^2
+    if (et.E <= c->C - c->p.rho1 * tau * zz) {
+      accepted = true;
+      break;
+    }
+  }
+  // accept: U <- W2 and the dot products for the next BB step
+  HIPCHK(c, pou::launch_commit<T>(W, (const T *)c->d_HW, c->d_rep[0], (const T *)c->d_W2,
+                                  (const T *)c->d_HWt, c->d_rep[1], c->d_part, N, c->ng,
+                                  c->nblk_orb, s));
+  HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 4, c->dv, s));
+  std::vector<double> d(4 * N);
+  CHK(sync_read(c, d.data(), c->d_red, sizeof(double) * 4 * N));
+  double ss = 0, sy = 0, yy = 0, zn = 0;
+  for (int i = 0; i < N; ++i) {
+    ss += d[0 * N + i];
+    sy += d[1 * N + i];
+    yy += d[2 * N + i];
+    zn += d[3 * N + i];
+  }
+  c->ss = ss;
+  c->sy = sy;
+  c->yy = yy;
+  c->zz_next = zn;
+  std::swap(c->d_HW, c->d_HWt);
+  std::swap(c->d_rep[0], c->d_rep[1]);
+  const double E_old = c->E;
+  c->E = et.E;
+  const double Qn = c->p.eta * c->Q + 1.0;
+  c->C = (c->p.eta * c->Q * c->C + c->E) / Qn;
+  c->Q = Qn;
+  c->hist = true;
+  c->eval_ptr = W;
+  c->eval_HU = c->d_HW;
+  if (info) {
+    info->l = c->l;
+    info->s = s_acc;
+    info->accepted = accepted ? 1 : 0;
+    info->cg_iters = cg_total;
+    info->E = c->E;
+    info->tau_bb = tau_bb;
+    info->tau = tau;
+    info->zz = zz;
+    info->df = std::fabs(E_old - c->E) / (std::fabs(E_old) + 1.0);
+    info->C = c->C;
+    info->Q = c->Q;
+    info->gram_dev = gram_dev;
+  }
+  c->l += 1;
+  return POU_OK;
+}
+
+template <typename T>
+pou_status orthonormalize_impl(pou_ctx *c, T *U, double *orth_err) {
+  hipStream_t s = c->stream;
+  const size_t bytes = (size_t)c->N * c->ng * sizeof(T);
+  const double thr = sizeof(T) == 8 ? 1e-8 : 1e-4;
+  // strong guarantee: work on copies, write U only at the end
+  HIPCHK(c, hipMemcpyAsync(c->d_Wt, U, bytes, hipMemcpyDeviceToDevice, s));
+  double info[2];
+  T *src = (T *)c->d_Wt, *dst = (T *)c->d_W2;
+  bool done = false;
+  for (int p = 0; p < 3 && !done; ++p) {
+    CHK(gram<T>(c, src, false));
+    HIPCHK(c, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->N, c->d_red, s));
+    HIPCHK(c, pou::launch_apply_lower<T>(c->d_Minv, src, dst, c->N, c->ng, nullptr, nullptr, s));
+    CHK(sync_read(c, info, c->d_red, sizeof(info)));
+    if (!std::isfinite(info[1])) return fail(c, POU_ERR_NONFINITE, "U is not finite");
+    if (info[0] != 0.0)
+      return fail(c, POU_ERR_NOT_SPD, "Gram matrix of U is not positive definite");
+    done = info[1] < thr && p > 0;
+    if (info[1] < thr * 1e-4) done = true;
+    std::swap(src, dst);
+  }
+  HIPCHK(c, hipMemcpyAsync(U, src, bytes, hipMemcpyDeviceToDevice, s));
+  if (orth_err) {
+    CHK(gram<T>(c, U, false));
+    std::vector<double> G((size_t)c->N * c->N);
+    CHK(sync_read(c, G.data(), c->d_G, sizeof(double) * G.size()));
+    double m = 0.0;
+    for (int i = 0; i < c->N; ++i)
+      for (int j = 0; j < c->N; ++j)
+        m = std::max(m, std::fabs(G[(size_t)i * c->N + j] - (i == j ? 1.0 : 0.0)));
+    *orth_err = m;
+  } else {
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+  if (c->last_U == U) c->cur_valid = false;
+  if (c->eval_ptr == U) c->eval_ptr = nullptr;
+  c->hist = false;
+  return POU_OK;
+}
+
+template <typename T>
+pou_status energy_impl(pou_ctx *c, const T *U, pou_energy_terms *out) {
+  T *hu = (T *)((c->last_U == U && c->cur_valid) ? c->d_HW : c->d_HWt);
+  double *rep = (hu == (T *)c->d_HW) ? c->d_rep[0] : c->d_rep[1];
+  int it = 0;
+  CHK(evaluate<T>(c, U, hu, rep, false, &it));
+  std::vector<double> &r = c->rep_host;
+  r.resize(Report::size(c->N));
+  CHK(sync_read(c, r.data(), rep, sizeof(double) * Report::size(c->N)));
+  pou_energy_terms t;
+  terms_from_report(c, r.data(), &t);
+  t.cg_iters = it;
+  if (!std::isfinite(t.E)) return fail(c, POU_ERR_NONFINITE, "energy of U is not finite");
+  if (out) *out = t;
+  c->eval_ptr = U;
+  c->eval_HU = hu;
+  return POU_OK;
+}
+
+template <typename T>
+pou_status backward_impl(pou_ctx *c, const T *U, double gE, T *dU, double *dR, double *dsig) {
+  hipStream_t s = c->stream;
+  if (c->eval_ptr != U) CHK(energy_impl<T>(c, U, nullptr));
+  if (dU)
+    HIPCHK(c, pou::launch_backward_scale<T>((const T *)c->eval_HU, c->d_occ, gE * 2.0 * c->dv,
+                                            dU, c->N, c->ng, s));
+  if ((dR || dsig) && c->M > 0) {
+    const int nb = std::min(256, c->nblk_field);
+    HIPCHK(c, pou::launch_ion_forces(c->d_atoms, c->M, c->d_vh, c->d_part, c->n, c->L, nb, s));
+    HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, c->M, nb, 4, -gE * c->dv, s));
+    std::vector<double> f(4 * c->M);
+    CHK(sync_read(c, f.data(), c->d_red, sizeof(double) * f.size()));
+    std::vector<double> R(3 * c->M), S(c->M);
+    for (int I = 0; I < c->M; ++I) {
+      for (int a = 0; a < 3; ++a) R[3 * I + a] = f[a * c->M + I];
+      S[I] = f[3 * c->M + I];
+    }
+    if (dR) HIPCHK(c, hipMemcpyAsync(dR, R.data(), sizeof(double) * R.size(),
+                                     hipMemcpyHostToDevice, s));
+    if (dsig) HIPCHK(c, hipMemcpyAsync(dsig, S.data(), sizeof(double) * S.size(),
+                                       hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  return POU_OK;
+}
+
+template <typename T>
+pou_status hamiltonian_impl(pou_ctx *c, const T *U, T *HU, double *sigma) {
+  hipStream_t s = c->stream;
+  const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
+  HIPCHK(c, pou::launch_hamiltonian<T>(U, veff, HU, c->d_part, c->N, c->st, s));
+  HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, c->N, c->st.ntile * c->st.nzc, 2,
+                                    c->dv, s));
+  if (sigma) CHK(sync_read(c, sigma, c->d_red, sizeof(double) * c->N));
+  else HIPCHK(c, hipStreamSynchronize(s));
+  return POU_OK;
+}
+
+template <typename T>
+pou_status gram_impl(pou_ctx *c, const T *U, double *G) {
+  CHK(gram<T>(c, U, false));
+  CHK(sync_read(c, G, c->d_G, sizeof(double) * c->N * c->N));
+  return POU_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void pou_default_params(pou_params *p) {
+  if (!p) return;
+  p->rho1 = 1e-4;
+  p->delta = 0.1;
+  p->eta = 0.85;
+  p->bb_mode = 0;
+  p->tau_init = 0.0;
+  p->s_max = 10;
+  p->orth_passes = 0;
+  p->cg_rtol = 0.0;
+  p->cg_maxit = 0;
+  p->cg_precond = 1;
+  p->terms = POU_TERM_ALL;
+}
+
+pou_status pou_create(pou_ctx **out, int device, void *hip_stream) {
+  if (!out) return POU_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return POU_ERR_ARG;
+  }
+  pou_ctx *c = new pou_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return POU_ERR_HIP;
+  }
+  *out = c;
+  return POU_OK;
+}
+
+pou_status pou_destroy(pou_ctx *c) {
+  if (!c) return POU_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+  return POU_OK;
+}
+
+const char *pou_last_error(const pou_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const double *R,
+                          const double *Z, const double *sigma, int norb, const double *occ,
+                          pou_precision prec, const pou_params *params) {
+  if (!c) return POU_ERR_ARG;
+  if (!grid || !occ) return fail(c, POU_ERR_ARG, "null grid or occupation pointer");
+  if (grid->n < 9 || grid->n > 1024) return fail(c, POU_ERR_ARG, "grid n must be in [9, 1024]");
+  if (!(grid->L > 0.0) || !std::isfinite(grid->L)) return fail(c, POU_ERR_ARG, "box side L must be > 0");
+  const i64 ng = (i64)grid->n * grid->n * grid->n;
+  if (norb < 1 || norb > 512 || (i64)norb > ng)
+    return fail(c, POU_ERR_ARG, "norb must be in [1, min(512, n^3)]");
+  if (natoms < 0 || (natoms > 0 && (!R || !Z || !sigma)))
+    return fail(c, POU_ERR_ARG, "bad atom arrays");
+  if (prec != POU_FP64 && prec != POU_MIXED) return fail(c, POU_ERR_ARG, "bad precision");
+  for (int I = 0; I < natoms; ++I) {
+    if (!(sigma[I] > 0.0) || !std::isfinite(sigma[I]) || !std::isfinite(Z[I]) ||
+        !std::isfinite(R[3 * I]) || !std::isfinite(R[3 * I + 1]) || !std::isfinite(R[3 * I + 2]))
+      return fail(c, POU_ERR_ARG, "atom " + std::to_string(I) + ": bad position, charge or width");
+  }
+  for (int i = 0; i < norb; ++i)
+    if (!(occ[i] >= 0.0) || !std::isfinite(occ[i]))
+      return fail(c, POU_ERR_ARG, "occupations must be finite and >= 0");
+  pou_params p;
+  if (params) p = *params;
+  else pou_default_params(&p);
+  const double h = grid->L / grid->n;
+  if (p.tau_init <= 0.0) {
+    // 1 / lambda_max(K): K = -1/2 Lap has its largest eigenvalue at theta = pi on every axis
+    p.tau_init = 1.0 / (1.5 * lambda1(2, h, 1));  // lambda1(2, h, 1) is the symbol at theta = pi
+  }
+  if (p.orth_passes <= 0) p.orth_passes = (prec == POU_FP64) ? 1 : 2;
+  if (p.cg_rtol <= 0.0) p.cg_rtol = 1e-12;
+  if (p.cg_maxit <= 0) p.cg_maxit = 2000;
+  if (!(p.delta > 0.0 && p.delta < 1.0) || !(p.rho1 >= 0.0) || !(p.eta >= 0.0 && p.eta <= 1.0) ||
+      p.s_max < 0 || p.s_max > 60 || p.orth_passes > 2 || p.bb_mode < 0 || p.bb_mode > 2 ||
+      !std::isfinite(p.tau_init))
+    return fail(c, POU_ERR_ARG, "bad algorithm parameters");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, POU_ERR_HIP, "hipSetDevice failed");
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+
+  c->n = grid->n;
+  c->L = grid->L;
+  c->h = h;
+  c->dv = h * h * h;
+  c->ng = ng;
+  c->N = norb;
+  c->M = natoms;
+  c->prec = prec;
+  c->p = p;
+  c->es = (prec == POU_FP64) ? 8 : 4;
+  c->occ.assign(occ, occ + norb);
+  c->atoms.assign(5 * (size_t)natoms, 0.0);
+  for (int I = 0; I < natoms; ++I) {
+    for (int a = 0; a < 3; ++a) c->atoms[5 * I + a] = R[3 * I + a];
+    c->atoms[5 * I + 3] = Z[I];
+    c->atoms[5 * I + 4] = sigma[I];
+  }
+  // launch shapes
+  const int tiles = (c->n + pou::kTX - 1) / pou::kTX;
+  c->st.n = c->n;
+  c->st.inv_h2 = 1.0 / (h * h);
+  c->st.ntile = tiles * tiles;
+  int nzc = (int)std::ceil(2048.0 / ((double)c->st.ntile * norb));
+  nzc = std::max(1, std::min(nzc, c->n / 8));
+  c->st.zlen = (c->n + nzc - 1) / nzc;
+  c->st.nzc = (c->n + c->st.zlen - 1) / c->st.zlen;
+  c->nblk_field = (int)std::min<i64>(1024, (ng + 255) / 256);
+  c->nblk_orb = (int)std::max<i64>(1, std::min<i64>(64, ng / 16384));
+  const int nb64 = (norb + 63) / 64;
+  c->npairs = nb64 * (nb64 + 1) / 2;
+  c->nsplit = (int)std::max<i64>(1, std::min<i64>(std::max(1, 1024 / c->npairs), (ng + 31) / 32));
+
+  const size_t fbytes = sizeof(double) * (size_t)ng;
+  const size_t bbytes = c->es * (size_t)ng * norb;
+  CHK(dalloc(c, &c->d_occ, sizeof(double) * norb));
+  CHK(dalloc(c, &c->d_atoms, sizeof(double) * std::max<size_t>(1, c->atoms.size())));
+  CHK(dalloc(c, &c->d_rho, fbytes));
+  CHK(dalloc(c, &c->d_vh, fbytes));
+  CHK(dalloc(c, &c->d_vext, fbytes));
+  CHK(dalloc(c, &c->d_veff, fbytes));
+  CHK(dalloc(c, &c->d_veff32, sizeof(float) * (size_t)ng));
+  CHK(dalloc(c, &c->d_rhoion, fbytes));
+  CHK(dalloc(c, &c->d_lam1, sizeof(double) * c->n));
+  CHK(dalloc(c, &c->d_cg_r, fbytes));
+  CHK(dalloc(c, &c->d_cg_p, fbytes));
+  CHK(dalloc(c, &c->d_cg_q, fbytes));
+  CHK(dalloc(c, &c->d_cg_z, fbytes));
+  CHK(dalloc(c, &c->d_fft0, 2 * fbytes));
+  CHK(dalloc(c, &c->d_fft1, 2 * fbytes));
+  CHK(dalloc(c, &c->d_sc, sizeof(double) * 16));
+  c->part_len = std::max<size_t>({(size_t)2 * norb * c->st.ntile * c->st.nzc,
+                                  (size_t)3 * c->nblk_field, (size_t)4 * norb * c->nblk_orb,
+                                  (size_t)4 * std::max(1, natoms) * 256, (size_t)16});
+  CHK(dalloc(c, &c->d_part, sizeof(double) * c->part_len));
+  CHK(dalloc(c, &c->d_gpart, sizeof(double) * (size_t)c->nsplit * c->npairs * 64 * 64));
+  CHK(dalloc(c, &c->d_G, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_Minv, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_Minv2, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_Mcomb, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_red, sizeof(double) * (size_t)std::max(4 * norb, 4 * std::max(1, natoms)) + 64));
+  CHK(dalloc(c, &c->d_rep[0], sizeof(double) * Report::size(norb)));
+  CHK(dalloc(c, &c->d_rep[1], sizeof(double) * Report::size(norb)));
+  CHK(dalloc(c, &c->d_HW, bbytes));
+  CHK(dalloc(c, &c->d_HWt, bbytes));
+  CHK(dalloc(c, &c->d_Wt, bbytes));
+  CHK(dalloc(c, &c->d_W1, bbytes));
+  CHK(dalloc(c, &c->d_W2, bbytes));
+
+  hipStream_t s = c->stream;
+  std::vector<double> lam(c->n);
+  for (int k = 0; k < c->n; ++k) lam[k] = lambda1(c->n, h, k);
+  HIPCHK(c, hipMemcpyAsync(c->d_lam1, lam.data(), sizeof(double) * c->n, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_occ, c->occ.data(), sizeof(double) * norb, hipMemcpyHostToDevice, s));
+  if (natoms > 0)
+    HIPCHK(c, hipMemcpyAsync(c->d_atoms, c->atoms.data(), sizeof(double) * c->atoms.size(),
+                             hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemsetAsync(c->d_vh, 0, fbytes, s));
+  HIPCHK(c, hipMemsetAsync(c->d_vext, 0, fbytes, s));
+  HIPCHK(c, hipMemsetAsync(c->d_rep[0], 0, sizeof(double) * Report::size(norb), s));
+  HIPCHK(c, hipMemsetAsync(c->d_rep[1], 0, sizeof(double) * Report::size(norb), s));
+  // V_ext = -P[rho_ion]: the periodic, background-neutralised potential of the
+  // Gaussian ion charges
+  if (natoms > 0 && (p.terms & POU_TERM_EXT)) {
+    HIPCHK(c, pou::launch_ion_density(c->d_atoms, natoms, c->d_rhoion, c->n, c->L, s));
+    int it = 0;
+    CHK(poisson(c, c->d_rhoion, c->d_vext, 1e-13, std::max(p.cg_maxit, 4000), p.cg_precond != 0,
+                &it));
+    HIPCHK(c, pou::launch_scale(c->d_vext, -1.0, ng, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->have_system = true;
+  c->last_U = nullptr;
+  c->cur_valid = false;
+  c->hist = false;
+  c->eval_ptr = nullptr;
+  c->l = 0;
+  return POU_OK;
+}
+
+#define NEED_SYSTEM(c)                                                        \
+  do {                                                                        \
+    if (!(c)) return POU_ERR_ARG;                                             \
+    if (!(c)->have_system) return fail((c), POU_ERR_STATE, "call pou_set_system first"); \
+    if (hipSetDevice((c)->device) != hipSuccess) return fail((c), POU_ERR_HIP, "hipSetDevice failed"); \
+  } while (0)
+
+pou_status pou_energy(pou_ctx *c, const void *U, pou_energy_terms *out) {
+  NEED_SYSTEM(c);
+  if (!U) return fail(c, POU_ERR_ARG, "null U");
+  if (c->prec == POU_FP64) return energy_impl<double>(c, (const double *)U, out);
+  return energy_impl<float>(c, (const float *)U, out);
+}
+
+pou_status pou_orthonormalize(pou_ctx *c, void *U, double *orth_err) {
+  NEED_SYSTEM(c);
+  if (!U) return fail(c, POU_ERR_ARG, "null U");
+  if (c->prec == POU_FP64) return orthonormalize_impl<double>(c, (double *)U, orth_err);
+  return orthonormalize_impl<float>(c, (float *)U, orth_err);
+}
+
+pou_status pou_orbital_update_step(pou_ctx *c, void *U, pou_step_info *out) {
+  NEED_SYSTEM(c);
+  if (!U) return fail(c, POU_ERR_ARG, "null U");
+  if (c->prec == POU_FP64) return step_impl<double>(c, (double *)U, out);
+  return step_impl<float>(c, (float *)U, out);
+}
+
+pou_status pou_energy_backward(pou_ctx *c, const void *U, double gE, void *dU, double *dR,
+                               double *dsigma) {
+  NEED_SYSTEM(c);
+  if (!U) return fail(c, POU_ERR_ARG, "null U");
+  if (!std::isfinite(gE)) return fail(c, POU_ERR_ARG, "gE must be finite");
+  if (c->prec == POU_FP64)
+    return backward_impl<double>(c, (const double *)U, gE, (double *)dU, dR, dsigma);
+  return backward_impl<float>(c, (const float *)U, gE, (float *)dU, dR, dsigma);
+}
+
+pou_status pou_hamiltonian_apply(pou_ctx *c, const void *U, void *HU, double *sigma) {
+  NEED_SYSTEM(c);
+  if (!U || !HU) return fail(c, POU_ERR_ARG, "null U or HU");
+  if (c->eval_ptr == nullptr && !c->cur_valid)
+    return fail(c, POU_ERR_STATE, "no potentials yet: call pou_energy first");
+  if (c->prec == POU_FP64) return hamiltonian_impl<double>(c, (const double *)U, (double *)HU, sigma);
+  return hamiltonian_impl<float>(c, (const float *)U, (float *)HU, sigma);
+}
+
+pou_status pou_get_fields(pou_ctx *c, double *rho, double *vh, double *veff, double *vext) {
+  NEED_SYSTEM(c);
+  const size_t b = sizeof(double) * (size_t)c->ng;
+  if (rho) HIPCHK(c, hipMemcpyAsync(rho, c->d_rho, b, hipMemcpyDeviceToDevice, c->stream));
+  if (vh) HIPCHK(c, hipMemcpyAsync(vh, c->d_vh, b, hipMemcpyDeviceToDevice, c->stream));
+  if (veff) HIPCHK(c, hipMemcpyAsync(veff, c->d_veff, b, hipMemcpyDeviceToDevice, c->stream));
+  if (vext) HIPCHK(c, hipMemcpyAsync(vext, c->d_vext, b, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return POU_OK;
+}
+
+pou_status pou_gram(pou_ctx *c, const void *U, double *G) {
+  NEED_SYSTEM(c);
+  if (!U || !G) return fail(c, POU_ERR_ARG, "null U or G");
+  if (c->prec == POU_FP64) return gram_impl<double>(c, (const double *)U, G);
+  return gram_impl<float>(c, (const float *)U, G);
+}
+
+pou_status pou_convert(pou_ctx *c, const void *src, int src_prec, void *dst, int dst_prec,
+                       long long count) {
+  if (!c) return POU_ERR_ARG;
+  if (!src || !dst || count < 0) return fail(c, POU_ERR_ARG, "bad convert arguments");
+  if ((src_prec != POU_FP64 && src_prec != POU_MIXED) || (dst_prec != POU_FP64 && dst_prec != POU_MIXED))
+    return fail(c, POU_ERR_ARG, "bad precision code");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, POU_ERR_HIP, "hipSetDevice failed");
+  hipStream_t s = c->stream;
+  if (src_prec == POU_MIXED && dst_prec == POU_FP64)
+    HIPCHK(c, (pou::launch_convert<float, double>((const float *)src, (double *)dst, count, s)));
+  else if (src_prec == POU_FP64 && dst_prec == POU_MIXED)
+    HIPCHK(c, (pou::launch_convert<double, float>((const double *)src, (float *)dst, count, s)));
+  else if (src_prec == POU_FP64)
+    HIPCHK(c, (pou::launch_convert<double, double>((const double *)src, (double *)dst, count, s)));
+  else
+    HIPCHK(c, (pou::launch_convert<float, float>((const float *)src, (float *)dst, count, s)));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return POU_OK;
+}
+
+pou_status pou_reset_history(pou_ctx *c) {
+  if (!c) return POU_ERR_ARG;
+  c->hist = false;
+  c->cur_valid = false;
+  c->l = 0;
+  return POU_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,917 @@
+// Grid kernels: the Hamiltonian stencil sweep over all orbitals, the density,
+// exchange and effective potential, the Poisson CG building blocks with the
+// FFT-based spectral inverse, the ionic charge and forces, and the per-orbital
+// elementwise steps of Algorithm M (trial point, accept/BB dot products).
+#include "pou_internal.h"
+
+#include <cmath>
+
+namespace pou {
+
+namespace {
+
+constexpr int kNB = 4;  // y points per thread in the stencil tile (kTY / 8 rows)
+
+__host__ __device__ inline int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// ----------------------------------------------------------------- stencil
+
+// H u = -1/2 Lap_h u + V_eff u on the periodic grid (section 2.1 H(rho), with
+// the 8th-order finite-difference Laplacian), one orbital per blockIdx.z.
+// Each workgroup owns a 32x32 x-y tile and marches over a chunk of z planes;
+// the current plane with its radius-4 x/y halo is staged in LDS and the z
+// neighbours live in a per-thread register queue (2.5-D blocking).  The
+// second differences are formed as sums of (u_{+m} - u_0) + (u_{-m} - u_0),
+// which is exact in real arithmetic because the weights sum to zero and
+// keeps FP32 cancellation small.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
+                                                        const T *__restrict__ veff,
+                                                        T *__restrict__ HU,
+                                                        double *__restrict__ part,
+                                                        StencilArgs a) {
+  __shared__ T s[kTY + 2 * kRad][kTX + 2 * kRad + 1];
+  __shared__ double red[4 * 2];
+  const int n = a.n;
+  const i64 ng = (i64)n * n * n;
+  const int tiles_x = (n + kTX - 1) / kTX;
+  const int tile = blockIdx.x;
+  const int zc = blockIdx.y;
+  const int orb = blockIdx.z;
+  const int x0 = (tile % tiles_x) * kTX;
+  const int y0 = (tile / tiles_x) * kTY;
+  const int tx = threadIdx.x & 31;
+  const int trow = threadIdx.x >> 5;  // 0..7
+  const T *u = U + (i64)orb * ng;
+  T *hu = HU + (i64)orb * ng;
+
+  const int gx = x0 + tx;
+  const bool vx = gx < n;
+  const int gxw = wrap(gx, n);
+  int gyw[kNB];
+  bool valid[kNB];
+#pragma unroll
+  for (int r = 0; r < kNB; ++r) {
+    const int gy = y0 + trow + 8 * r;
+    gyw[r] = wrap(gy, n);
+    valid[r] = vx && gy < n;
+  }
+  // halo assignments (independent of z)
+  const int hx_row = threadIdx.x >> 3;  // 0..31
+  const int hx_c = threadIdx.x & 7;     // 0..7
+  const int hx_lc = hx_c < 4 ? hx_c - 4 : kTX + hx_c - 4;
+  const int hx_gx = wrap(x0 + hx_lc, n);
+  const int hx_gy = wrap(y0 + hx_row, n);
+  const int hy_col = threadIdx.x & 31;
+  const int hy_r = threadIdx.x >> 5;  // 0..7
+  const int hy_lr = hy_r < 4 ? hy_r - 4 : kTY + hy_r - 4;
+  const int hy_gy = wrap(y0 + hy_lr, n);
+  const int hy_gx = wrap(x0 + hy_col, n);
+
+  const int z0 = zc * a.zlen;
+  const int z1 = min(n, z0 + a.zlen);
+
+  T q[kNB][2 * kRad + 1];
+#pragma unroll
+  for (int m = 0; m < 2 * kRad; ++m) {
+    const int zz = wrap(z0 - kRad + m, n);
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) q[r][m] = u[((i64)zz * n + gyw[r]) * n + gxw];
+  }
+  const double c[5] = {0.0, FD8::c1, FD8::c2, FD8::c3, FD8::c4};
+  const T ih2 = (T)a.inv_h2;
+  double acc_sig = 0.0, acc_kin = 0.0;
+
+  for (int z = z0; z < z1; ++z) {
+    const int zn = wrap(z + kRad, n);
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) q[r][2 * kRad] = u[((i64)zn * n + gyw[r]) * n + gxw];
+    const i64 plane = (i64)z * n;
+    // stage plane z
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) s[trow + 8 * r + kRad][tx + kRad] = q[r][kRad];
+    s[hx_row + kRad][hx_lc + kRad] = u[(plane + hx_gy) * n + hx_gx];
+    s[hy_lr + kRad][hy_col + kRad] = u[(plane + hy_gy) * n + hy_gx];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) {
+      const int ly = trow + 8 * r + kRad;
+      const int lx = tx + kRad;
+      const T c0 = q[r][kRad];
+      T lap = (T)0;
+#pragma unroll
+      for (int m = 1; m <= kRad; ++m) {
+        const T dxm = (s[ly][lx + m] - c0) + (s[ly][lx - m] - c0);
+        const T dym = (s[ly + m][lx] - c0) + (s[ly - m][lx] - c0);
+        const T dzm = (q[r][kRad + m] - c0) + (q[r][kRad - m] - c0);
+        lap += (T)c[m] * ((dxm + dym) + dzm);
+      }
+      const T ku = (T)(-0.5) * lap * ih2;
+      if (valid[r]) {
+        const i64 g = (plane + gyw[r]) * n + gxw;
+        const T h = ku + veff[g] * c0;
+        hu[g] = h;
+        acc_sig += (double)c0 * (double)h;
+        acc_kin += (double)c0 * (double)ku;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 2 * kRad; ++m) {
+#pragma unroll
+      for (int r = 0; r < kNB; ++r) q[r][m] = q[r][m + 1];
+    }
+  }
+  double v[2] = {acc_sig, acc_kin};
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    const int nb = a.ntile * a.nzc;
+    const i64 idx = (i64)orb * nb + (i64)tile * a.nzc + zc;
+    part[2 * idx + 0] = v[0];
+    part[2 * idx + 1] = v[1];
+  }
+}
+
+// ----------------------------------------------------------------- density
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_density(const T *__restrict__ U,
+                                                    const double *__restrict__ occ,
+                                                    double *__restrict__ rho, int N, i64 ng) {
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    int i = 0;
+    for (; i + 4 <= N; i += 4) {
+      const double u0 = (double)U[(i64)i * ng + g];
+      const double u1 = (double)U[(i64)(i + 1) * ng + g];
+      const double u2 = (double)U[(i64)(i + 2) * ng + g];
+      const double u3 = (double)U[(i64)(i + 3) * ng + g];
+      acc += occ[i] * u0 * u0 + occ[i + 1] * u1 * u1 + occ[i + 2] * u2 * u2 +
+             occ[i + 3] * u3 * u3;
+    }
+    for (; i < N; ++i) {
+      const double u0 = (double)U[(i64)i * ng + g];
+      acc += occ[i] * u0 * u0;
+    }
+    rho[g] = acc;
+  }
+}
+
+// ------------------------------------------------------- exchange and V_eff
+
+// LDA exchange (section 2.1 v_xc, exchange part only):
+//   e_x density = -C_x rho^(4/3), v_x = -(3/pi)^(1/3) rho^(1/3).
+__global__ __launch_bounds__(kBlock) void k_xc_veff(const double *__restrict__ rho,
+                                                    const double *__restrict__ vh,
+                                                    const double *__restrict__ vext,
+                                                    double *__restrict__ veff,
+                                                    float *__restrict__ veff32,
+                                                    double *__restrict__ part, i64 ng,
+                                                    unsigned terms) {
+  __shared__ double red[4 * 3];
+  const double kv = 0.98474502184269640;  // (3/pi)^(1/3)
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    const double r = rho[g];
+    const double r13 = cbrt(fmax(r, 0.0));
+    double v = 0.0;
+    if (terms & 8u) {
+      v -= kv * r13;
+      a0 += r * r13;
+    }
+    if (terms & 4u) {
+      v += vh[g];
+      a2 += r * vh[g];
+    }
+    if (terms & 2u) {
+      v += vext[g];
+      a1 += r * vext[g];
+    }
+    veff[g] = v;
+    if (veff32) veff32[g] = (float)v;
+  }
+  double vals[3] = {a0, a1, a2};
+  block_sum<3>(vals, red);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 0] = vals[0];
+    part[3 * blockIdx.x + 1] = vals[1];
+    part[3 * blockIdx.x + 2] = vals[2];
+  }
+}
+
+// out[k*nseg + seg] = sum_j part[(seg*len + j)*K + k]
+__global__ __launch_bounds__(kBlock) void k_segment_sum(const double *__restrict__ part,
+                                                        double *__restrict__ out, int nseg,
+                                                        int len, int K, double scale) {
+  __shared__ double red[4];
+  const int seg = blockIdx.x;
+  for (int k = 0; k < K; ++k) {
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < len; j += blockDim.x)
+      acc += part[((i64)seg * len + j) * K + k];
+    double v[1] = {acc};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) out[(i64)k * nseg + seg] = scale * v[0];
+  }
+}
+
+// ----------------------------------------------------------------- Poisson
+
+__global__ __launch_bounds__(kBlock) void k_neg_lap(const double *__restrict__ p,
+                                                    double *__restrict__ q,
+                                                    double *__restrict__ part, int n,
+                                                    double inv_h2) {
+  __shared__ double red[4];
+  const i64 ng = (i64)n * n * n;
+  const double c[5] = {0.0, FD8::c1, FD8::c2, FD8::c3, FD8::c4};
+  double acc = 0.0;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    const int x = (int)(g % n);
+    const int y = (int)((g / n) % n);
+    const int z = (int)(g / ((i64)n * n));
+    const double c0 = p[g];
+    double lap = 0.0;
+#pragma unroll
+    for (int m = 1; m <= kRad; ++m) {
+      const double dx = (p[((i64)z * n + y) * n + wrap(x + m, n)] - c0) +
+                        (p[((i64)z * n + y) * n + wrap(x - m, n)] - c0);
+      const double dy = (p[((i64)z * n + wrap(y + m, n)) * n + x] - c0) +
+                        (p[((i64)z * n + wrap(y - m, n)) * n + x] - c0);
+      const double dz = (p[((i64)wrap(z + m, n) * n + y) * n + x] - c0) +
+                        (p[((i64)wrap(z - m, n) * n + y) * n + x] - c0);
+      lap += c[m] * ((dx + dy) + dz);
+    }
+    const double v = -lap * inv_h2;
+    q[g] = v;
+    acc += c0 * v;
+  }
+  if (part) {
+    double v[1] = {acc};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_rhs_residual(const double *__restrict__ rho,
+                                                            const double *__restrict__ dsum,
+                                                            const double *__restrict__ q,
+                                                            double *__restrict__ r,
+                                                            double *__restrict__ part, i64 ng) {
+  __shared__ double red[4 * 2];
+  const double mean = dsum[0] / (double)ng;
+  const double fourpi = 12.566370614359172954;
+  double a0 = 0.0, a1 = 0.0;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    const double b = fourpi * (rho[g] - mean);
+    const double rr = b - q[g];
+    r[g] = rr;
+    a0 += rr * rr;
+    a1 += b * b;
+  }
+  double v[2] = {a0, a1};
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = v[1];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot2(const double *__restrict__ a,
+                                                 const double *__restrict__ b,
+                                                 double *__restrict__ part, i64 ng) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x)
+    acc += a[g] * (b ? b[g] : 1.0);
+  double v[1] = {acc};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update_p(double *__restrict__ p,
+                                                        const double *__restrict__ z,
+                                                        const double *__restrict__ num,
+                                                        const double *__restrict__ den,
+                                                        int first, i64 ng) {
+  const double beta = first ? 0.0 : num[0] / den[0];
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x)
+    p[g] = z[g] + beta * (first ? 0.0 : p[g]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update_xr(double *__restrict__ x,
+                                                         double *__restrict__ r,
+                                                         const double *__restrict__ p,
+                                                         const double *__restrict__ q,
+                                                         const double *__restrict__ num,
+                                                         const double *__restrict__ den,
+                                                         double *__restrict__ part, i64 ng) {
+  __shared__ double red[4];
+  const double alpha = num[0] / den[0];
+  double acc = 0.0;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    x[g] += alpha * p[g];
+    const double rr = r[g] - alpha * q[g];
+    r[g] = rr;
+    acc += rr * rr;
+  }
+  double v[1] = {acc};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(double *__restrict__ x, double a, i64 ng) {
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x)
+    x[g] *= a;
+}
+
+__global__ __launch_bounds__(kBlock) void k_remove_mean(double *__restrict__ x,
+                                                        const double *__restrict__ dsum,
+                                                        i64 ng) {
+  const double mean = dsum[0] / (double)ng;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x)
+    x[g] -= mean;
+}
+
+// ----------------------------------------------------------------- FFT
+// Batched 1-D complex FFTs of length n held in LDS, mixed radix (4, 2, 3, 5,
+// any leftover factor by direct DFT), self-sorting (Stockham) stages.  A
+// workgroup transforms `lb` lines; lines along x are contiguous, lines along
+// y and z are strided and the batch takes consecutive x so global accesses of
+// one element index stay contiguous.
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by sign*i
+__device__ inline double2 cmuli(double2 a, double sign) { return make_double2(-sign * a.y, sign * a.x); }
+
+struct Radices {
+  int nr;
+  int r[16];
+};
+
+__host__ inline Radices factorize(int n) {
+  Radices f{};
+  f.nr = 0;
+  int m = n;
+  while (m % 4 == 0) { f.r[f.nr++] = 4; m /= 4; }
+  while (m % 2 == 0) { f.r[f.nr++] = 2; m /= 2; }
+  while (m % 3 == 0) { f.r[f.nr++] = 3; m /= 3; }
+  while (m % 5 == 0) { f.r[f.nr++] = 5; m /= 5; }
+  for (int p = 7; p * p <= m; p += 2)
+    while (m % p == 0) { f.r[f.nr++] = p; m /= p; }
+  if (m > 1) f.r[f.nr++] = m;
+  return f;
+}
+
+// One Stockham stage over all lines: a -> b.
+__device__ inline void fft_stage(const double2 *a, double2 *b, int n, int lb, int R, int Ns,
+                                 double sign) {
+  const int nbf = n / R;  // butterflies per line
+  for (int t = threadIdx.x; t < lb * nbf; t += blockDim.x) {
+    const int line = t / nbf;
+    const int j = t - line * nbf;
+    const double2 *src = a + line * n;
+    double2 *dst = b + line * n;
+    const int k = j % Ns;
+    const int base = (j / Ns) * Ns * R + k;
+    const double ang = sign * 2.0 * (double)k / (double)(Ns * R);  // in units of pi
+    if (R == 4) {
+      double2 x0 = src[j], x1 = src[j + nbf], x2 = src[j + 2 * nbf], x3 = src[j + 3 * nbf];
+      if (k) {
+        double sv, cv;
+        sincospi(ang, &sv, &cv);
+        const double2 w1 = make_double2(cv, sv);
+        const double2 w2 = cmul(w1, w1);
+        const double2 w3 = cmul(w2, w1);
+        x1 = cmul(x1, w1);
+        x2 = cmul(x2, w2);
+        x3 = cmul(x3, w3);
+      }
+      const double2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
+      const double2 s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3), sign);
+      dst[base] = cadd(s02, s13);
+      dst[base + Ns] = cadd(d02, d13);
+      dst[base + 2 * Ns] = csub(s02, s13);
+      dst[base + 3 * Ns] = csub(d02, d13);
+    } else if (R == 2) {
+      double2 x0 = src[j], x1 = src[j + nbf];
+      if (k) {
+        double sv, cv;
+        sincospi(ang, &sv, &cv);
+        x1 = cmul(x1, make_double2(cv, sv));
+      }
+      dst[base] = cadd(x0, x1);
+      dst[base + Ns] = csub(x0, x1);
+    } else if (R == 3) {
+      double2 x0 = src[j], x1 = src[j + nbf], x2 = src[j + 2 * nbf];
+      if (k) {
+        double sv, cv;
+        sincospi(ang, &sv, &cv);
+        const double2 w1 = make_double2(cv, sv);
+        x1 = cmul(x1, w1);
+        x2 = cmul(x2, cmul(w1, w1));
+      }
+      const double2 t1 = cadd(x1, x2);
+      const double2 t2 = cmuli(csub(x1, x2), sign * 0.86602540378443864676);
+      const double2 m = make_double2(x0.x - 0.5 * t1.x, x0.y - 0.5 * t1.y);
+      dst[base] = cadd(x0, t1);
+      dst[base + Ns] = cadd(m, t2);
+      dst[base + 2 * Ns] = csub(m, t2);
+    } else {
+      // generic radix: twiddle, then a direct DFT of length R
+      for (int s = 0; s < R; ++s) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int tt = 0; tt < R; ++tt) {
+          double2 x = src[j + tt * nbf];
+          // total phase: twiddle tt*k/(Ns R) plus DFT s*tt/R, both times 2 sign
+          const double ph = sign * 2.0 * ((double)tt * k / (double)(Ns * R) +
+                                          (double)((s * tt) % R) / (double)R);
+          double sv, cv;
+          sincospi(ph, &sv, &cv);
+          acc = cadd(acc, cmul(x, make_double2(cv, sv)));
+        }
+        dst[base + s * Ns] = acc;
+      }
+    }
+  }
+}
+
+// Transform lb lines in LDS buffers a/b; returns the buffer holding the result.
+__device__ inline double2 *fft_lines(double2 *a, double2 *b, int n, int lb, Radices f,
+                                     double sign) {
+  int Ns = 1;
+  for (int st = 0; st < f.nr; ++st) {
+    fft_stage(a, b, n, lb, f.r[st], Ns, sign);
+    __syncthreads();
+    double2 *t = a;
+    a = b;
+    b = t;
+    Ns *= f.r[st];
+  }
+  return a;
+}
+
+// mode 0: complex -> complex forward; 1: real input, forward; 2: inverse, real
+// output scaled by `scale`; 3: forward, multiply by scale / (Laplacian symbol),
+// inverse (z lines only); 4: complex -> complex inverse.  axis: 0 = x, 1 = y, 2 = z.
+__global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
+                                                void *__restrict__ out, int n, int axis,
+                                                int lb, int mode, Radices f,
+                                                const double *__restrict__ lam1,
+                                                double scale) {
+  extern __shared__ double2 lds[];
+  double2 *a = lds;
+  double2 *b = lds + lb * n;
+  const i64 n2 = (i64)n * n;
+  // batch decoding: for x lines the batch is lb consecutive y rows of one z;
+  // for y and z lines the batch is lb consecutive x of one (z) or (y).
+  const int groups_per_row = (n + lb - 1) / lb;
+  const int grp = blockIdx.x % groups_per_row;
+  const int outer = blockIdx.x / groups_per_row;  // z for x/y lines, y for z lines
+  const int first = grp * lb;
+  const int nl = min(lb, n - first);
+  i64 stride, base0, lstride;
+  if (axis == 0) {  // element stride 1, line stride n, lines = y rows
+    stride = 1;
+    lstride = n;
+    base0 = (i64)outer * n2 + (i64)first * n;
+  } else if (axis == 1) {  // element stride n, lines = consecutive x
+    stride = n;
+    lstride = 1;
+    base0 = (i64)outer * n2 + first;
+  } else {  // element stride n^2, lines = consecutive x of row `outer` (y)
+    stride = n2;
+    lstride = 1;
+    base0 = (i64)outer * n + first;
+  }
+  const double sign = (mode == 2 || mode == 4) ? 1.0 : -1.0;
+  // load: element index e over lines, consecutive threads take consecutive lines
+  for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
+    int line, e;
+    if (axis == 0) { line = t / n; e = t % n; } else { e = t / lb; line = t % lb; }
+    double2 v = make_double2(0.0, 0.0);
+    if (line < nl) {
+      const i64 gi = base0 + (i64)line * lstride + (i64)e * stride;
+      if (mode == 1) v = make_double2(((const double *)in)[gi], 0.0);
+      else v = ((const double2 *)in)[gi];
+    }
+    a[line * n + e] = v;
+  }
+  __syncthreads();
+  double2 *res = fft_lines(a, b, n, lb, f, sign);
+  if (mode == 3) {
+    // z lines: element e is kz; the line is (kx = first + line, ky = outer)
+    for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
+      const int line = t / n, e = t % n;
+      double2 v = res[t];
+      if (line < nl) {
+        const double lam = lam1[first + line] + lam1[outer] + lam1[e];
+        const double w = (first + line == 0 && outer == 0 && e == 0) ? 0.0 : scale / lam;
+        v = make_double2(v.x * w, v.y * w);
+      }
+      res[t] = v;
+    }
+    __syncthreads();
+    double2 *other = (res == a) ? b : a;
+    res = fft_lines(res, other, n, lb, f, 1.0);
+  }
+  for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
+    int line, e;
+    if (axis == 0) { line = t / n; e = t % n; } else { e = t / lb; line = t % lb; }
+    if (line < nl) {
+      const i64 gi = base0 + (i64)line * lstride + (i64)e * stride;
+      const double2 v = res[line * n + e];
+      if (mode == 2) ((double *)out)[gi] = v.x * scale;
+      else ((double2 *)out)[gi] = v;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- ions
+
+// atoms: [M][5] = (Rx, Ry, Rz, Z, sigma)
+__global__ __launch_bounds__(kBlock) void k_ion_density(const double *__restrict__ atoms,
+                                                        int M, double *__restrict__ rho,
+                                                        int n, double L) {
+  const i64 ng = (i64)n * n * n;
+  const double h = L / n;
+  const double pi = 3.14159265358979323846;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    const double x = h * (double)(g % n);
+    const double y = h * (double)((g / n) % n);
+    const double z = h * (double)(g / ((i64)n * n));
+    double acc = 0.0;
+    for (int I = 0; I < M; ++I) {
+      double dx = x - atoms[5 * I + 0];
+      double dy = y - atoms[5 * I + 1];
+      double dz = z - atoms[5 * I + 2];
+      dx -= L * rint(dx / L);
+      dy -= L * rint(dy / L);
+      dz -= L * rint(dz / L);
+      const double s = atoms[5 * I + 4];
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      acc += atoms[5 * I + 3] * exp(-d2 / (s * s)) / (s * s * s * pi * sqrt(pi));
+    }
+    rho[g] = acc;
+  }
+}
+
+// Partials of <V_H, d rho_I/dR_a> and <V_H, d rho_I/d sigma> (unscaled).
+__global__ __launch_bounds__(kBlock) void k_ion_forces(const double *__restrict__ atoms,
+                                                       const double *__restrict__ vh,
+                                                       double *__restrict__ part, int n,
+                                                       double L) {
+  __shared__ double red[4 * 4];
+  const int I = blockIdx.y;
+  const i64 ng = (i64)n * n * n;
+  const double h = L / n;
+  const double pi = 3.14159265358979323846;
+  const double Rx = atoms[5 * I + 0], Ry = atoms[5 * I + 1], Rz = atoms[5 * I + 2];
+  const double Zi = atoms[5 * I + 3], s = atoms[5 * I + 4];
+  const double norm = Zi / (s * s * s * pi * sqrt(pi));
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    double dx = h * (double)(g % n) - Rx;
+    double dy = h * (double)((g / n) % n) - Ry;
+    double dz = h * (double)(g / ((i64)n * n)) - Rz;
+    dx -= L * rint(dx / L);
+    dy -= L * rint(dy / L);
+    dz -= L * rint(dz / L);
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double gv = norm * exp(-d2 / (s * s)) * vh[g];
+    const double t = 2.0 / (s * s);
+    a[0] += gv * t * dx;
+    a[1] += gv * t * dy;
+    a[2] += gv * t * dz;
+    a[3] += gv * (2.0 * d2 / (s * s * s) - 3.0 / s);
+  }
+  block_sum<4>(a, red);
+  if (threadIdx.x == 0) {
+    const i64 idx = ((i64)I * gridDim.x + blockIdx.x) * 4;
+    part[idx + 0] = a[0];
+    part[idx + 1] = a[1];
+    part[idx + 2] = a[2];
+    part[idx + 3] = a[3];
+  }
+}
+
+// ----------------------------------------------------------------- block steps
+
+// Trial point of Algorithm M (section 3.2): W - tau z_i with
+// z_i = H w_i - sigma_ii w_i.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_trial(const T *__restrict__ W,
+                                                  const T *__restrict__ HW,
+                                                  const double *__restrict__ sig, double tau,
+                                                  T *__restrict__ Wt, i64 ng) {
+  const int orb = blockIdx.y;
+  const double a = 1.0 + tau * sig[orb];
+  const T ta = (T)a, tt = (T)tau;
+  const i64 off = (i64)orb * ng;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x)
+    Wt[off + g] = ta * W[off + g] - tt * HW[off + g];
+}
+
+// Accept the trial: U <- Wn, and per-orbital partial dot products for the
+// next Barzilai-Borwein step (S = Wn - W, Y = Zn - Z) and ||Zn||^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_commit(T *__restrict__ U, const T *__restrict__ HW,
+                                                   const double *__restrict__ sig,
+                                                   const T *__restrict__ Wn,
+                                                   const T *__restrict__ HWn,
+                                                   const double *__restrict__ sign,
+                                                   double *__restrict__ part, i64 ng) {
+  __shared__ double red[4 * 4];
+  const int orb = blockIdx.y;
+  const double so = sig[orb], sn = sign[orb];
+  const i64 off = (i64)orb * ng;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    const double wo = (double)U[off + g];
+    const double wn = (double)Wn[off + g];
+    const double zo = (double)HW[off + g] - so * wo;
+    const double zn = (double)HWn[off + g] - sn * wn;
+    const double s = wn - wo;
+    const double y = zn - zo;
+    a[0] += s * s;
+    a[1] += s * y;
+    a[2] += y * y;
+    a[3] += zn * zn;
+    U[off + g] = Wn[off + g];
+  }
+  block_sum<4>(a, red);
+  if (threadIdx.x == 0) {
+    const i64 idx = ((i64)orb * gridDim.x + blockIdx.x) * 4;
+    part[idx + 0] = a[0];
+    part[idx + 1] = a[1];
+    part[idx + 2] = a[2];
+    part[idx + 3] = a[3];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zz(const T *__restrict__ W, const T *__restrict__ HW,
+                                               const double *__restrict__ sig,
+                                               double *__restrict__ part, i64 ng) {
+  __shared__ double red[4];
+  const int orb = blockIdx.y;
+  const double so = sig[orb];
+  const i64 off = (i64)orb * ng;
+  double acc = 0.0;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    const double z = (double)HW[off + g] - so * (double)W[off + g];
+    acc += z * z;
+  }
+  double v[1] = {acc};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) part[(i64)orb * gridDim.x + blockIdx.x] = v[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_backward_scale(const T *__restrict__ HU,
+                                                           const double *__restrict__ occ,
+                                                           double scale, T *__restrict__ dU,
+                                                           i64 ng) {
+  const int orb = blockIdx.y;
+  const T f = (T)(scale * occ[orb]);
+  const i64 off = (i64)orb * ng;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x)
+    dU[off + g] = f * HU[off + g];
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_convert(const S *__restrict__ src,
+                                                    D *__restrict__ dst, i64 count) {
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < count;
+       g += (i64)gridDim.x * blockDim.x)
+    dst[g] = (D)src[g];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nonfinite(const T *__restrict__ x, i64 count,
+                                                      int *__restrict__ flag) {
+  bool bad = false;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < count;
+       g += (i64)gridDim.x * blockDim.x)
+    bad |= !isfinite((double)x[g]);
+  if (bad) flag[0] = 1;
+}
+
+inline int grid_for(i64 work, int cap = 4096) {
+  i64 b = (work + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+
+template <typename T>
+hipError_t launch_hamiltonian(const T *U, const T *veff, T *HU, double *part, int N,
+                              const StencilArgs &a, hipStream_t s) {
+  dim3 grid(a.ntile, a.nzc, N);
+  hipLaunchKernelGGL(k_hamiltonian<T>, grid, dim3(kBlock), 0, s, U, veff, HU, part, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_density(const T *U, const double *occ, double *rho, int N, i64 ng,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_density<T>, dim3(grid_for(ng, 8192)), dim3(kBlock), 0, s, U, occ, rho,
+                     N, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_xc_veff(const double *rho, const double *vh, const double *vext,
+                          double *veff, float *veff32, double *part, i64 ng, unsigned terms,
+                          int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_xc_veff, dim3(nblk), dim3(kBlock), 0, s, rho, vh, vext, veff, veff32,
+                     part, ng, terms);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_sum(const double *part, double *out, int nseg, int len, int K,
+                              double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_segment_sum, dim3(nseg), dim3(kBlock), 0, s, part, out, nseg, len, K,
+                     scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_neg_lap(const double *p, double *q, double *part, int n, double inv_h2,
+                          int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_neg_lap, dim3(nblk), dim3(kBlock), 0, s, p, q, part, n, inv_h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_rhs_residual(const double *rho, const double *dsum, const double *q,
+                                  double *r, double *part, i64 ng, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_rhs_residual, dim3(nblk), dim3(kBlock), 0, s, rho, dsum, q, r, part,
+                     ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2(const double *a, const double *b, double *part, i64 ng, int nblk,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2, dim3(nblk), dim3(kBlock), 0, s, a, b, part, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den,
+                              int first, i64 ng, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update_p, dim3(grid_for(ng)), dim3(kBlock), 0, s, p, z, num, den,
+                     first, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q,
+                               const double *num, const double *den, double *part, i64 ng,
+                               int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update_xr, dim3(nblk), dim3(kBlock), 0, s, x, r, p, q, num, den, part,
+                     ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double *x, double a, i64 ng, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(ng)), dim3(kBlock), 0, s, x, a, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_remove_mean(double *x, const double *dsum, i64 ng, hipStream_t s) {
+  hipLaunchKernelGGL(k_remove_mean, dim3(grid_for(ng)), dim3(kBlock), 0, s, x, dsum, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, double2 *w1,
+                                   const double *lam1, int n, hipStream_t s) {
+  const Radices f = factorize(n);
+  int lb = 1024 / n;  // two LDS buffers of lb*n complex doubles: at most 32 KiB
+  if (lb < 1) lb = 1;
+  if (lb > 16) lb = 16;
+  const size_t lds = (size_t)2 * lb * n * sizeof(double2);
+  const int groups = (n + lb - 1) / lb;
+  const dim3 grid(groups * n), block(kBlock);
+  const double invn3 = 1.0 / ((double)n * n * n);
+  // x forward (real in) -> y forward -> z forward, divide, z inverse -> y inverse -> x inverse
+  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)r, (void *)w0, n, 0, lb, 1, f,
+                     lam1, 1.0);
+  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 0, f,
+                     lam1, 1.0);
+  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w1, (void *)w0, n, 2, lb, 3, f,
+                     lam1, invn3);
+  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 4, f,
+                     lam1, 1.0);
+  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w1, (void *)out, n, 0, lb, 2, f,
+                     lam1, 1.0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_trial(const T *W, const T *HW, const double *sig, double tau, T *Wt, int N,
+                        i64 ng, hipStream_t s) {
+  dim3 grid(grid_for(ng, 1024), N);
+  hipLaunchKernelGGL(k_trial<T>, grid, dim3(kBlock), 0, s, W, HW, sig, tau, Wt, ng);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_commit(T *U, const T *HW, const double *sig, const T *Wn, const T *HWn,
+                         const double *sign, double *part, int N, i64 ng, int nblk,
+                         hipStream_t s) {
+  dim3 grid(nblk, N);
+  hipLaunchKernelGGL(k_commit<T>, grid, dim3(kBlock), 0, s, U, HW, sig, Wn, HWn, sign, part,
+                     ng);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zz(const T *W, const T *HW, const double *sig, double *part, int N, i64 ng,
+                     int nblk, hipStream_t s) {
+  dim3 grid(nblk, N);
+  hipLaunchKernelGGL(k_zz<T>, grid, dim3(kBlock), 0, s, W, HW, sig, part, ng);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_backward_scale(const T *HU, const double *occ, double scale, T *dU, int N,
+                                 i64 ng, hipStream_t s) {
+  dim3 grid(grid_for(ng, 1024), N);
+  hipLaunchKernelGGL(k_backward_scale<T>, grid, dim3(kBlock), 0, s, HU, occ, scale, dU, ng);
+  return hipGetLastError();
+}
+
+template <typename S, typename D>
+hipError_t launch_convert(const S *src, D *dst, i64 count, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<S, D>), dim3(grid_for(count, 16384)), dim3(kBlock), 0, s, src,
+                     dst, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_nonfinite(const T *x, i64 count, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_nonfinite<T>, dim3(grid_for(count, 16384)), dim3(kBlock), 0, s, x, count,
+                     flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_ion_density(const double *atoms, int M, double *rho_ion, int n, double L,
+                              hipStream_t s) {
+  const i64 ng = (i64)n * n * n;
+  hipLaunchKernelGGL(k_ion_density, dim3(grid_for(ng, 16384)), dim3(kBlock), 0, s, atoms, M,
+                     rho_ion, n, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_ion_forces(const double *atoms, int M, const double *vh, double *part, int n,
+                             double L, int nblk, hipStream_t s) {
+  dim3 grid(nblk, M);
+  hipLaunchKernelGGL(k_ion_forces, grid, dim3(kBlock), 0, s, atoms, vh, part, n, L);
+  return hipGetLastError();
+}
+
+#define POU_INST_T(T)                                                                       \
+  template hipError_t launch_hamiltonian<T>(const T *, const T *, T *, double *, int,       \
+                                            const StencilArgs &, hipStream_t);              \
+  template hipError_t launch_density<T>(const T *, const double *, double *, int, i64,      \
+                                        hipStream_t);                                       \
+  template hipError_t launch_trial<T>(const T *, const T *, const double *, double, T *,    \
+                                      int, i64, hipStream_t);                               \
+  template hipError_t launch_commit<T>(T *, const T *, const double *, const T *, const T *, \
+                                       const double *, double *, int, i64, int,             \
+                                       hipStream_t);                                        \
+  template hipError_t launch_zz<T>(const T *, const T *, const double *, double *, int, i64, \
+                                   int, hipStream_t);                                       \
+  template hipError_t launch_backward_scale<T>(const T *, const double *, double, T *, int, \
+                                               i64, hipStream_t);                           \
+  template hipError_t launch_nonfinite<T>(const T *, i64, int *, hipStream_t);
+
+POU_INST_T(double)
+POU_INST_T(float)
+template hipError_t launch_convert<float, double>(const float *, double *, i64, hipStream_t);
+template hipError_t launch_convert<double, float>(const double *, float *, i64, hipStream_t);
+template hipError_t launch_convert<double, double>(const double *, double *, i64, hipStream_t);
+template hipError_t launch_convert<float, float>(const float *, float *, i64, hipStream_t);
+
+}  // namespace pou

@@ -1,0 +1,190 @@
+// Internal declarations shared by the HIP sources of the library.
+// Kernels are launched through the host-side wrappers declared here; every
+// wrapper enqueues on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace pou {
+
+using i64 = long long;
+
+// Threads per workgroup used by the field / block kernels.
+constexpr int kBlock = 256;
+// Stencil tile: 32 (x) by 32 (y) points per workgroup, 8 thread rows each
+// handling 4 y points; radius-4 halo.
+constexpr int kTX = 32;
+constexpr int kTY = 32;
+constexpr int kRad = 4;
+
+struct FD8 {
+  // central 8th-order second-derivative weights for offsets 1..4 (offset 0
+  // weight is minus twice their sum, so the operator annihilates constants)
+  static constexpr double c1 = 8.0 / 5.0;
+  static constexpr double c2 = -1.0 / 5.0;
+  static constexpr double c3 = 8.0 / 315.0;
+  static constexpr double c4 = -1.0 / 560.0;
+};
+
+// ---------------------------------------------------------------- reductions
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline float wave_sum(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Sum of K values per thread over a 256-thread workgroup, deterministic order.
+// Result valid in thread 0 (out[k]).  scratch must hold 4*K doubles.
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double *scratch) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) scratch[wave * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += scratch[w * K + k];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- launchers
+// Grid / block kernels (grid_kernels.hip)
+
+struct StencilArgs {
+  int n;          // points per axis
+  double inv_h2;  // 1 / h^2
+  int ntile;      // tiles per plane = ceil(n/32)^2
+  int nzc;        // z chunks per orbital
+  int zlen;       // planes per chunk
+};
+
+// HU = -1/2 Lap U + veff * U for N orbitals; per (orbital, tile, zchunk)
+// partial sums of <u, H u> and <u, K u> (unscaled by h^3) into part[2*(o*nb + b) + {0,1}].
+template <typename T>
+hipError_t launch_hamiltonian(const T *U, const T *veff, T *HU, double *part, int N,
+                              const StencilArgs &a, hipStream_t s);
+
+// rho[g] = sum_i occ_i u_i[g]^2 (FP64 accumulation)
+template <typename T>
+hipError_t launch_density(const T *U, const double *occ, double *rho, int N, i64 ng,
+                          hipStream_t s);
+
+// xc + effective potential + energy partials.  part[3*b + {0,1,2}] =
+// partial sums of (rho^(4/3), rho*vext, rho*vh).  veff32 nullable.
+hipError_t launch_xc_veff(const double *rho, const double *vh, const double *vext,
+                          double *veff, float *veff32, double *part, i64 ng,
+                          unsigned terms, int nblk, hipStream_t s);
+
+// out[k*nseg + seg] = scale * sum_j part[(seg*len + j)*K + k], j < len (deterministic)
+hipError_t launch_segment_sum(const double *part, double *out, int nseg, int len, int K,
+                              double scale, hipStream_t s);
+
+// ---- Poisson (conjugate gradients) on one FP64 field
+// q = -Lap p  and part[b] = partial of p.q
+hipError_t launch_neg_lap(const double *p, double *q, double *part, int n, double inv_h2,
+                          int nblk, hipStream_t s);
+// b = 4 pi (rho - mean), mean read from dmean[0]; r = b - q (q = A x);
+// part[2b] = r.r partial, part[2b+1] = b.b partial
+hipError_t launch_cg_rhs_residual(const double *rho, const double *dmean, const double *q,
+                                  double *r, double *part, i64 ng, int nblk, hipStream_t s);
+// scalar dot / norm partials of two fields
+hipError_t launch_dot2(const double *a, const double *b, double *part, i64 ng, int nblk,
+                       hipStream_t s);
+// p = z + beta p (beta = num[0]/den[0], or 0 when first != 0)
+hipError_t launch_cg_update_p(double *p, const double *z, const double *num, const double *den,
+                              int first, i64 ng, hipStream_t s);
+// x += alpha p; r -= alpha q; alpha = num[0]/den[0]; part = r.r partial
+hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *q,
+                               const double *num, const double *den, double *part, i64 ng,
+                               int nblk, hipStream_t s);
+// x *= a
+hipError_t launch_scale(double *x, double a, i64 ng, hipStream_t s);
+// dst = src - mean(src) with mean from dmean (used to fix the gauge)
+hipError_t launch_remove_mean(double *x, const double *dmean, i64 ng, hipStream_t s);
+// Spectral inverse of -Lap: out = (-Lap)^+ r (zero mean), via 3-D FFT.
+hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, double2 *w1,
+                                   const double *lam1, int n, hipStream_t s);
+
+// ---- block elementwise / reductions
+// Wt = (1 + tau sig_i) W - tau HW
+template <typename T>
+hipError_t launch_trial(const T *W, const T *HW, const double *sig, double tau, T *Wt,
+                        int N, i64 ng, hipStream_t s);
+// accept: U <- Wn; partials per (orbital, block) of
+//   s.s, s.y, y.y, zn.zn  with s = Wn - W, y = zn - z,
+//   z = HW - sig W, zn = HWn - sign Wn
+template <typename T>
+hipError_t launch_commit(T *U, const T *HW, const double *sig, const T *Wn, const T *HWn,
+                         const double *sign, double *part, int N, i64 ng, int nblk,
+                         hipStream_t s);
+// z.z partials for z = HW - sig W
+template <typename T>
+hipError_t launch_zz(const T *W, const T *HW, const double *sig, double *part, int N,
+                     i64 ng, int nblk, hipStream_t s);
+// dU = gE * 2 occ_i dv * HU
+template <typename T>
+hipError_t launch_backward_scale(const T *HU, const double *occ, double scale, T *dU,
+                                 int N, i64 ng, hipStream_t s);
+template <typename S, typename D>
+hipError_t launch_convert(const S *src, D *dst, i64 count, hipStream_t s);
+// non-finite check: flag[0] |= 1 if any element is NaN/Inf
+template <typename T>
+hipError_t launch_nonfinite(const T *x, i64 count, int *flag, hipStream_t s);
+
+// ---- ions
+hipError_t launch_ion_density(const double *atoms, int M, double *rho_ion, int n, double L,
+                              hipStream_t s);
+// part[((I*nblk)+b)*4 + {0..3}] partial sums for dE/dR_{x,y,z}, dE/dsigma
+hipError_t launch_ion_forces(const double *atoms, int M, const double *vh, double *part,
+                             int n, double L, int nblk, hipStream_t s);
+
+// ---- dense (dense_kernels.hip)
+// Partial Gram of A [N][ng]: see gram.  part holds nsplit * nblkpairs * 64*64 doubles.
+template <typename T>
+hipError_t launch_gram_partial(const T *A, int N, i64 ng, int nsplit, double *part,
+                               hipStream_t s);
+// Pass-1 BF16 Gram of FP32 data (products of BF16-rounded values, FP32 accumulation
+// flushed to FP64).
+hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, double *part,
+                                    hipStream_t s);
+// G = dv * sum of partials (full symmetric N x N)
+hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
+                              hipStream_t s);
+// Cholesky G = L L^T and Minv = L^-1 (lower).  info[0] = 1.0 if G is not
+// numerically SPD else 0.0; info[1] = max |G - I|.  Single workgroup.
+hipError_t launch_cholesky_inverse(double *G, double *Minv, int N, double *info,
+                                   hipStream_t s);
+// C = A * B for lower-triangular N x N matrices (FP64)
+hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int N,
+                               hipStream_t s);
+// out[j][g] = sum_i M[j][i] X[i][g], M lower triangular N x N FP64.  When rho
+// is non-null also rho[g] = sum_j occ_j out[j][g]^2.
+template <typename T>
+hipError_t launch_apply_lower(const double *M, const T *X, T *out, int N, i64 ng,
+                              const double *occ, double *rho, hipStream_t s);
+
+}  // namespace pou
