@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Orbital-update iterations per second on one MI355X.
+
+Workload (mixed96): periodic box of side 24 bohr on a 96^3 grid, 64 Gaussian
+ions with Z = 4 and width 0.5 bohr at seeded positions (minimum separation
+1.5 bohr), N = 128 doubly occupied orbitals from a seeded atom-centred start.
+One step is one call of pou_orbital_update_step: Algorithm M with n_org = 1
+(direction, Barzilai-Borwein step, backtracking with the trial energy,
+Cholesky-QR orthonormalisation).  The orbital block lives in HBM before the
+timed region starts.
+
+`value` is the mixed-precision rate; the FP64 rate, their ratio, the energy
+difference after FP64 refinement, the roofline of the dominant kernel (HIP
+events over the timed region) and the oracle timed on the host are reported
+in the same JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "orbital-update iters/sec at 96³ grid N=128, mixed vs FP64 at |ΔE|≤1e-6 Ha"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(group, N, ng, es):
+    """Bytes one launch of a kernel group must move at minimum (each operand once)."""
+    B = N * ng * es
+    return {
+        "hamiltonian": 2 * B + ng * es,     # read W, write H W, read V_eff once
+        "apply": 2 * B + ng * 8,            # read X, write L^-1 X, write rho (fused)
+        "gram": B,                          # read the block once
+        "trial": 3 * B,                     # read W, H W; write W - tau Z
+        "commit": 5 * B,                    # read W, H W, W_new, H W_new; write U
+        "density": B + ng * 8,
+    }.get(group)
+
+
+def cpu_baseline(cfg, budget_s=30.0):
+    """Time the oracle's Algorithm-M step on this workload (bounded sample)."""
+    import numpy as np
+    import synth
+    from oracle import ks, algm
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    R, Z, s = synth.atoms(cfg)
+    so = ks.System(cfg.n, cfg.L, R, Z, s, synth.occupations(cfg))
+    X = synth.orbitals(cfg)
+    A = algm.AlgorithmM(X, so, algm.Params())
+    t0 = time.perf_counter()
+    A.step()
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / t, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one oracle Algorithm-M step (trial orth + energy + H W) on the full "
+                      f"{cfg.n}^3 / N={cfg.norb} workload, {t:.1f} s; the oracle's initial "
+                      f"orthonormalisation and energy are not timed"}
+
+
+def run(args):
+    import numpy as np
+    import torch
+    import synth
+    import paper_1510_07230_amd as pk
+
+    cfg = synth.CONFIGS[args.workload]
+    R, Z, s = synth.atoms(cfg)
+    occ = synth.occupations(cfg)
+    X = synth.orbitals(cfg)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    g64 = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="fp64")
+    U64 = g64.new_block(X)
+    del X
+    err0 = g64.orthonormalize_(U64)
+    W0 = U64.clone()
+    progress(f"start orthonormalised (err {err0:.2e})")
+
+    def timed(g, U, steps, warmup, profile):
+        for _ in range(warmup):
+            g.step_(U)
+        torch.cuda.synchronize()
+        if profile:
+            g.profile(True)
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(g.step_(U))
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        prof = g.profile_read() if profile else None
+        if profile:
+            g.profile(False)
+        return t, infos, prof
+
+    t64, inf64, prof64 = timed(g64, U64, args.steps, args.warmup, True)
+    progress(f"fp64: {args.steps / t64:.1f} it/s, E={inf64[-1]['E']:.10f}")
+
+    g32 = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="mixed")
+    U32 = W0.to(torch.float32).contiguous()
+    g32.orthonormalize_(U32)
+    t32, inf32, prof32 = timed(g32, U32, args.steps, args.warmup, True)
+    progress(f"mixed: {args.steps / t32:.1f} it/s, E={inf32[-1]['E']:.10f}")
+
+    # roofline of the dominant kernel group of the mixed run
+    N, ng, es = cfg.norb, cfg.ng, 4
+    cand = {k: v for k, v in prof32.items() if algorithmic_bytes(k, N, ng, es) is not None and v[1] > 0}
+    dom = max(cand, key=lambda k: cand[k][0])
+    avg_ms = cand[dom][0] / cand[dom][1]
+    abytes = algorithmic_bytes(dom, N, ng, es)
+    achieved = abytes / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+                "algorithmic_bytes_per_launch": abytes,
+                "groups_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof32.items()},
+                "fp64_groups_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof64.items()}}
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / t32, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * t32 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mixed96: 96^3 periodic grid, L=24 bohr, 64 Gaussian ions Z=4 "
+                               "sigma=0.5, N=128 orbitals (f=2), atom-centred seeded start; "
+                               "mixed = FP32 orbitals/stencil, BF16-MFMA first Gram, FP32 second "
+                               "Gram and apply, FP64 Cholesky and reductions",
+                   "n": cfg.n, "L": cfg.L, "norb": N, "natoms": cfg.natoms},
+        "fp64": {"value": round(args.steps / t64, 3), "unit": "iters/s",
+                 "ms_per_step": round(1000.0 * t64 / args.steps, 4)},
+        "speedup_mixed_over_fp64": round(t64 / t32, 3),
+        "mean_trials_per_step": {"mixed": float(np.mean([i["s"] + 1 for i in inf32])),
+                                 "fp64": float(np.mean([i["s"] + 1 for i in inf64]))},
+        "roofline": roofline,
+    }
+
+    if not args.no_converge:
+        out["delta_E"] = converge(args, cfg, R, Z, s, occ, g64, U64, g32, U32, progress)
+    if not args.no_cpu_baseline:
+        progress("oracle CPU baseline")
+        del g64, g32, U64, U32, W0
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+def converge(args, cfg, R, Z, s, occ, g64, U64, g32, U32, progress):
+    """Untimed: converge FP64 and mixed (+ FP64 refinement) and compare energies."""
+    import numpy as np
+    import torch
+    import paper_1510_07230_amd as pk
+
+    def until(g, U, tol, cap_s, cap_steps):
+        df = []
+        t0 = time.perf_counter()
+        info = None
+        k = 0
+        while time.perf_counter() - t0 < cap_s and k < cap_steps:
+            info = g.step_(U)
+            df.append(info["df"])
+            k += 1
+            if len(df) >= 3 and np.mean(df[-3:]) < tol:
+                return info, k, True
+        return info, k, False
+
+    i64, k64, c64 = until(g64, U64, 1e-13, args.converge_seconds, 100000)
+    progress(f"fp64 converged={c64} after {k64} more steps, E={i64['E']:.12f}")
+    i32, k32, c32 = until(g32, U32, 1e-10, args.converge_seconds / 2, 100000)
+    progress(f"mixed phase: {k32} more steps, E={i32['E']:.12f}")
+    gr = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="fp64")
+    Ur = gr.new_block()
+    gr.convert(U32, Ur)
+    gr.orthonormalize_(Ur)
+    ir, kr, cr = until(gr, Ur, 1e-13, args.converge_seconds, 100000)
+    orth = gr.orthonormalize_(Ur.clone())
+    G = gr.gram(Ur)
+    orth_err = float(np.max(np.abs(G - np.eye(G.shape[0]))))
+    dE = abs(ir["E"] - i64["E"])
+    progress(f"refined: {kr} FP64 steps, E={ir['E']:.12f}, |dE|={dE:.2e}, orth={orth_err:.2e}")
+    return {"fp64_E": i64["E"], "fp64_converged": c64, "fp64_steps": k64 + args.steps + args.warmup,
+            "mixed_E_before_refine": i32["E"], "mixed_steps": k32 + args.steps + args.warmup,
+            "refined_E": ir["E"], "refine_steps": kr, "refine_converged": cr,
+            "abs_delta_E": dE, "orth_err_refined": orth_err,
+            "criterion": "3-step mean of df < 1e-13 (FP64 and refinement), < 1e-10 (mixed phase)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="mixed96")
+    ap.add_argument("--converge-seconds", type=float, default=40.0)
+    ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

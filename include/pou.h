@@ -179,6 +179,32 @@ pou_status pou_convert(pou_ctx *ctx, const void *src, int src_prec, void *dst,
 /* Reset the iteration state (l = 0, no BB history) without touching fields. */
 pou_status pou_reset_history(pou_ctx *ctx);
 
+/* ---- per-kernel timing with HIP events on the context's stream ---------- */
+
+/* Kernel groups timed when profiling is on. */
+enum {
+  POU_K_HAMILTONIAN = 0, /* H*U stencil sweep over all orbitals        */
+  POU_K_DENSITY = 1,     /* rho = sum f_i u_i^2 (when not fused)       */
+  POU_K_XC = 2,          /* exchange potential, V_eff, energy partials */
+  POU_K_POISSON = 3,     /* every kernel of the Hartree CG solve       */
+  POU_K_GRAM = 4,        /* Gram partial contraction (MFMA)            */
+  POU_K_CHOLESKY = 5,    /* Cholesky + triangular inverse, Gram reduce */
+  POU_K_APPLY = 6,       /* W <- L^-1 W (MFMA), fused density          */
+  POU_K_TRIAL = 7,       /* W - tau Z                                  */
+  POU_K_COMMIT = 8,      /* accept + Barzilai-Borwein dot products     */
+  POU_K_OTHER = 9,       /* reductions and the remaining small kernels */
+  POU_K_COUNT = 10
+};
+
+/* Turn event timing on (1) or off (0); turning it on clears the totals.
+   Each timed launch is bracketed by two hipEventRecord calls. */
+pou_status pou_profile_enable(pou_ctx *ctx, int enable);
+
+/* Total milliseconds and number of launches of kernel group `group` since
+   profiling was enabled (host outputs). */
+pou_status pou_profile_read(pou_ctx *ctx, int group, double *total_ms,
+                            long long *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,7 +76,12 @@ _SIGNATURES = {
     "pou_gram": (_i, [_vp, _vp, _dp]),
     "pou_convert": (_i, [_vp, _vp, _i, _vp, _i, ctypes.c_longlong]),
     "pou_reset_history": (_i, [_vp]),
+    "pou_profile_enable": (_i, [_vp, _i]),
+    "pou_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(ctypes.c_longlong)]),
 }
+
+KERNEL_GROUPS = ["hamiltonian", "density", "xc", "poisson", "gram", "cholesky", "apply",
+                 "trial", "commit", "other"]
 
 
 def header_symbols(path=HEADER):
@@ -252,6 +257,20 @@ class System:
 
     def reset_history(self):
         self._check(lib().pou_reset_history(self._h))
+
+    def profile(self, enable=True):
+        """Turn per-kernel-group HIP event timing on/off (on clears the totals)."""
+        self._check(lib().pou_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{group: (total_ms, launches)} since profiling was enabled."""
+        out = {}
+        for k, name in enumerate(KERNEL_GROUPS):
+            ms = ctypes.c_double(0.0)
+            n = ctypes.c_longlong(0)
+            self._check(lib().pou_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
 
 def _energy_fn():

@@ -5,6 +5,9 @@
 // apply W <- L^-1 W on MFMA.
 #include "pou_internal.h"
 
+#include <algorithm>
+#include <utility>
+
 namespace pou {
 
 namespace {
@@ -366,25 +369,534 @@ __global__ __launch_bounds__(kBlock) void k_apply_lower(const double *__restrict
   }
 }
 
+
+// ---------------------------------------------------------------- N <= 128
+
+// One elimination step k = K of the augmented sweep below (all indices into
+// the register array are compile-time).
+template <int K>
+__device__ __forceinline__ void chol_step(double (&a)[32], int c, int r0, int N, int ncol,
+                                          double *rowk, double *colk, const double *sdg,
+                                          int *sbad) {
+  if (K >= N) return;  // uniform over the workgroup
+  constexpr int MM = K >> 2, R0K = K & 3;
+  if (r0 == R0K && c < ncol) rowk[c] = a[MM];
+  if (c == K) {
+#pragma unroll
+    for (int mm = 0; mm < 32; ++mm) {
+      const int r = r0 + 4 * mm;
+      if (r < N) colk[r] = a[mm];
+    }
+  }
+  __syncthreads();
+  double p = rowk[K];
+  // a pivot at rounding level of the original diagonal means the columns
+  // are numerically dependent
+  if (!((p > 1e-13 * sdg[K]) && isfinite(p))) {
+    if (threadIdx.x == 0) *sbad = 1;
+    p = 1.0;
+  }
+  const double ip = 1.0 / p;
+  const double rc = (c < ncol) ? rowk[c] : 0.0;
+  const double rcp = rc * ip;
+  if (r0 == R0K) a[MM] = rc / sqrt(p);
+  else if (r0 > R0K && r0 + 4 * MM < N) a[MM] -= colk[r0 + 4 * MM] * rcp;
+#pragma unroll
+  for (int mm = MM + 1; mm < 32; ++mm) {
+    const int r = r0 + 4 * mm;
+    if (r < N) a[mm] -= colk[r] * rcp;
+  }
+  __syncthreads();
+}
+
+template <int... Ks>
+__device__ __forceinline__ void chol_sweep(std::integer_sequence<int, Ks...>, double (&a)[32],
+                                           int c, int r0, int N, int ncol, double *rowk,
+                                           double *colk, const double *sdg, int *sbad) {
+  (chol_step<Ks>(a, c, r0, N, ncol, rowk, colk, sdg, sbad), ...);
+}
+
+// Cholesky factor and inverse in one sweep: Gaussian elimination without
+// pivoting on the augmented matrix [G | I].  Step k divides row k by the square
+// root of its pivot and removes column k from the rows below; at the end the
+// left half holds L^T and the right half L^-1 (the row operations are L^-1
+// itself).  1024 threads: column c = t % 256 of [G | I], rows (t / 256) + 4m
+// held in registers.
+__global__ __launch_bounds__(1024) void k_chol_inv_small(const double *__restrict__ G,
+                                                         double *__restrict__ Minv,
+                                                         float *__restrict__ D32,
+                                                         double *__restrict__ D64, int N,
+                                                         double *__restrict__ info) {
+  __shared__ double rowk[256];
+  __shared__ double colk[128];
+  __shared__ double sdg[128];
+  __shared__ double sred[16];
+  __shared__ int sbad;
+  const int t = threadIdx.x;
+  const int c = t & 255, r0 = t >> 8;
+  const int ncol = 2 * N;
+  if (t < N) sdg[t] = G[(i64)t * N + t];
+  double a[32];
+  double m = 0.0;
+#pragma unroll
+  for (int mm = 0; mm < 32; ++mm) {
+    const int r = r0 + 4 * mm;
+    double v = 0.0;
+    if (r < N && c < ncol) {
+      if (c < N) {
+        v = G[(i64)r * N + c];
+        const double d = v - (r == c ? 1.0 : 0.0);
+        m = isfinite(d) ? fmax(m, fabs(d)) : INFINITY;
+      } else {
+        v = (c - N == r) ? 1.0 : 0.0;
+      }
+    }
+    a[mm] = v;
+  }
+  m = wave_max(m);
+  if ((t & 63) == 0) sred[t >> 6] = m;
+  if (t == 0) sbad = 0;
+  __syncthreads();
+  if (t == 0) {
+    double mx = 0.0;
+    for (int w = 0; w < 16; ++w) mx = fmax(mx, sred[w]);
+    info[1] = mx;
+  }
+  chol_sweep(std::make_integer_sequence<int, 128>{}, a, c, r0, N, ncol, rowk, colk, sdg, &sbad);
+  if (c >= N && c < ncol) {
+    const int j = c - N;
+#pragma unroll
+    for (int mm = 0; mm < 32; ++mm) {
+      const int r = r0 + 4 * mm;
+      if (r < N) {
+        const double v = a[mm];
+        Minv[(i64)r * N + j] = v;
+        const double d = v - (r == j ? 1.0 : 0.0);
+        D64[(i64)r * N + j] = d;
+        D32[(i64)r * N + j] = (float)d;
+      }
+    }
+  }
+  if (t == 0) info[0] = sbad ? 1.0 : 0.0;
+}
+
+// Tiles of the N <= 128 Gram owned by wave W: row tiles W and 7 - W with the
+// column tiles on or right of the diagonal (8 - W and W + 1 tiles, 9 in all).
+template <int W, int U>
+struct GramTile {
+  static constexpr int nfirst = 8 - W;
+  static constexpr int rt = U < nfirst ? W : 7 - W;
+  static constexpr int ct = U < nfirst ? W + U : (7 - W) + (U - nfirst);
+};
+
+// One staged chunk of KC points for wave W: 9 accumulating MFMA tiles.
+template <typename T, int NT, int W, int KC, int PITCH, typename Acc>
+__device__ inline void gram_chunk(const T (*s)[PITCH], Acc (&acc)[9], int r16, int q) {
+#pragma unroll
+  for (int ks = 0; ks < KC / 4; ++ks) {
+    T f[8];
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct)
+      f[ct] = (ct < NT && ct >= W) ? s[16 * ct + r16][4 * ks + q] : (T)0;
+#define POU_GT(U)                                                              \
+  if (GramTile<W, U>::rt < NT && GramTile<W, U>::ct < NT)                      \
+    acc[U] = mfma(f[GramTile<W, U>::rt], f[GramTile<W, U>::ct], acc[U]);
+    POU_GT(0) POU_GT(1) POU_GT(2) POU_GT(3) POU_GT(4) POU_GT(5) POU_GT(6) POU_GT(7) POU_GT(8)
+#undef POU_GT
+  }
+}
+
+template <int NT, int W, int KC, int PITCH>
+__device__ inline void gram_chunk_bf16(const float (*s)[PITCH], double (&accd)[9][4], int r16,
+                                       int q) {
+#pragma unroll
+  for (int kk = 0; kk < KC / 32; ++kk) {
+    bf8 f[8];
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        f[ct][e] = (ct < NT && ct >= W) ? (__bf16)s[16 * ct + r16][32 * kk + 8 * q + e]
+                                        : (__bf16)0.0f;
+    }
+#define POU_GTB(U)                                                                        \
+  if (GramTile<W, U>::rt < NT && GramTile<W, U>::ct < NT) {                               \
+    f4 c = f4{0, 0, 0, 0};                                                                \
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[GramTile<W, U>::rt], f[GramTile<W, U>::ct], \
+                                                c, 0, 0, 0);                              \
+    accd[U][0] += (double)c[0];                                                           \
+    accd[U][1] += (double)c[1];                                                           \
+    accd[U][2] += (double)c[2];                                                           \
+    accd[U][3] += (double)c[3];                                                           \
+  }
+    POU_GTB(0) POU_GTB(1) POU_GTB(2) POU_GTB(3) POU_GTB(4) POU_GTB(5) POU_GTB(6) POU_GTB(7)
+    POU_GTB(8)
+#undef POU_GTB
+  }
+}
+
+template <int W, int U>
+__device__ inline void gram_tile_rc(int &rt, int &ct) {
+  rt = GramTile<W, U>::rt;
+  ct = GramTile<W, U>::ct;
+}
+
+__device__ inline void gram_tile_runtime(int w, int u, int &rt, int &ct) {
+  const int nfirst = 8 - w;
+  rt = u < nfirst ? w : 7 - w;
+  ct = u < nfirst ? w + u : (7 - w) + (u - nfirst);
+}
+
+// Partial Gram over a range of grid points, whole N x N (N <= 128) upper
+// triangle per workgroup so every row is read once.  Chunks of KC points are
+// staged in LDS; the next chunk is loaded into registers while the current one
+// is multiplied.  The per-wave tile choice is resolved at compile time.
+template <typename T, int NT, int KC>
+__global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, int N, i64 ng,
+                                                       i64 kper, double *__restrict__ part) {
+  constexpr int ROWS = 16 * NT;
+  constexpr int PITCH = KC + 1;
+  constexpr int TPR = KC;                      // threads per staged row
+  constexpr int RSTEP = kBlock / TPR;          // rows per load round
+  constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
+  __shared__ T s[ROWS][PITCH];
+  typedef typename AccOf<T>::type Acc;
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const i64 k_beg = (i64)blockIdx.x * kper;
+  const i64 k_end = min(ng, k_beg + kper);
+  Acc acc[9];
+  double accd[9][4];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    acc[u] = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) accd[u][r] = 0.0;
+  }
+  const int col = t % TPR, row0 = t / TPR;
+  T nxt[PER];
+  auto load = [&](i64 k0) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      const i64 g = k0 + col;
+      nxt[e] = (row < N && g < k_end) ? A[(i64)row * ng + g] : (T)0;
+    }
+  };
+  if (k_beg < k_end) load(k_beg);
+  for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      if (row < ROWS) s[row][col] = nxt[e];
+    }
+    __syncthreads();
+    if (k0 + KC < k_end) load(k0 + KC);
+    switch (w) {
+      case 0: gram_chunk<T, NT, 0, KC, PITCH>(s, acc, r16, q); break;
+      case 1: gram_chunk<T, NT, 1, KC, PITCH>(s, acc, r16, q); break;
+      case 2: gram_chunk<T, NT, 2, KC, PITCH>(s, acc, r16, q); break;
+      default: gram_chunk<T, NT, 3, KC, PITCH>(s, acc, r16, q); break;
+    }
+    __syncthreads();
+    if (sizeof(T) == 4) {
+#pragma unroll
+      for (int u = 0; u < 9; ++u) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accd[u][r] += (double)acc[u][r];
+        acc[u] = Acc{0, 0, 0, 0};
+      }
+    }
+  }
+  double *outp = part + (i64)blockIdx.x * 128 * 128;
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    int rt, ct;
+    gram_tile_runtime(w, u, rt, ct);
+    if (rt < NT && ct < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rt + out_row<T>(q, r);
+        const int cl = 16 * ct + r16;
+        outp[row * 128 + cl] = (sizeof(T) == 4) ? accd[u][r] : (double)acc[u][r];
+      }
+    }
+  }
+}
+
+// The same contraction with the FP32 values rounded to BF16 (MFMA 16x16x32,
+// FP32 accumulation per 32 points, flushed into FP64).
+template <int NT, int KC>
+__global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restrict__ A, int N,
+                                                            i64 ng, i64 kper,
+                                                            double *__restrict__ part) {
+  constexpr int ROWS = 16 * NT;
+  constexpr int PITCH = KC + 4;
+  constexpr int TPR = KC;
+  constexpr int RSTEP = kBlock / TPR;
+  constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
+  __shared__ float s[ROWS][PITCH];
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const i64 k_beg = (i64)blockIdx.x * kper;
+  const i64 k_end = min(ng, k_beg + kper);
+  double accd[9][4];
+#pragma unroll
+  for (int u = 0; u < 9; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) accd[u][r] = 0.0;
+  const int col = t % TPR, row0 = t / TPR;
+  float nxt[PER];
+  auto load = [&](i64 k0) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      const i64 g = k0 + col;
+      nxt[e] = (row < N && g < k_end) ? A[(i64)row * ng + g] : 0.0f;
+    }
+  };
+  if (k_beg < k_end) load(k_beg);
+  for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      if (row < ROWS) s[row][col] = nxt[e];
+    }
+    __syncthreads();
+    if (k0 + KC < k_end) load(k0 + KC);
+    switch (w) {
+      case 0: gram_chunk_bf16<NT, 0, KC, PITCH>(s, accd, r16, q); break;
+      case 1: gram_chunk_bf16<NT, 1, KC, PITCH>(s, accd, r16, q); break;
+      case 2: gram_chunk_bf16<NT, 2, KC, PITCH>(s, accd, r16, q); break;
+      default: gram_chunk_bf16<NT, 3, KC, PITCH>(s, accd, r16, q); break;
+    }
+    __syncthreads();
+  }
+  double *outp = part + (i64)blockIdx.x * 128 * 128;
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    int rt, ct;
+    gram_tile_runtime(w, u, rt, ct);
+    if (rt < NT && ct < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        outp[(16 * rt + 4 * q + r) * 128 + 16 * ct + r16] = accd[u][r];
+    }
+  }
+}
+
+// Row tiles of the N <= 128 apply owned by wave W: W and 7 - W (balances the
+// triangle: 4(W+1) + 4(8-W) = 36 k-steps of 4 per wave).
+template <typename T, int NT, int W>
+__device__ inline void apply_load_a(const T *__restrict__ D, int N, T (&a0)[4 * NT],
+                                    T (&a1)[4 * NT], int r16, int q) {
+  constexpr int jt0 = W, jt1 = 7 - W;
+#pragma unroll
+  for (int ks = 0; ks < 4 * NT; ++ks) {
+    const int i = 4 * ks + q;
+    const int j0 = 16 * jt0 + r16, j1 = 16 * jt1 + r16;
+    a0[ks] = (jt0 < NT && ks < 4 * (jt0 + 1) && j0 < N && i < N) ? D[(i64)j0 * N + i] : (T)0;
+    a1[ks] = (jt1 < NT && ks < 4 * (jt1 + 1) && j1 < N && i < N) ? D[(i64)j1 * N + i] : (T)0;
+  }
+}
+
+template <typename T, int NT, int W, int GC, int PITCH, typename Acc>
+__device__ inline void apply_compute(const T (*xs)[PITCH], const T (&a0)[4 * NT],
+                                     const T (&a1)[4 * NT], Acc (&acc0)[GC / 16],
+                                     Acc (&acc1)[GC / 16], int r16, int q) {
+  constexpr int jt0 = W, jt1 = 7 - W;
+  constexpr int ke0 = jt0 < NT ? 4 * (jt0 + 1) : 0;
+  constexpr int ke1 = jt1 < NT ? 4 * (jt1 + 1) : 0;
+  constexpr int ke = ke0 > ke1 ? ke0 : ke1;
+#pragma unroll
+  for (int ks = 0; ks < ke; ++ks) {
+    T b[GC / 16];
+#pragma unroll
+    for (int cc = 0; cc < GC / 16; ++cc) b[cc] = xs[4 * ks + q][16 * cc + r16];
+    if (ks < ke0) {
+#pragma unroll
+      for (int cc = 0; cc < GC / 16; ++cc) acc0[cc] = mfma(a0[ks], b[cc], acc0[cc]);
+    }
+    if (ks < ke1) {
+#pragma unroll
+      for (int cc = 0; cc < GC / 16; ++cc) acc1[cc] = mfma(a1[ks], b[cc], acc1[cc]);
+    }
+  }
+}
+
+// out[j][g] = X[j][g] + sum_{i<=j} D[j][i] X[i][g] with D = L^-1 - I (lower
+// triangular, N <= 128).  The D fragments of a wave's two row tiles stay in
+// registers for the whole launch; the workgroup walks over blocks of GC grid
+// points, staging each X block in LDS while the next one is loaded into
+// registers.  Optional fused density rho[g] = sum_j occ_j out[j][g]^2.
+template <typename T, int NT, int GC>
+__global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
+                                                        const T *__restrict__ X,
+                                                        T *__restrict__ out, int N, i64 ng,
+                                                        const double *__restrict__ occ,
+                                                        double *__restrict__ rho) {
+  constexpr int ROWS = 16 * NT;
+  constexpr int PITCH = GC + 1;
+  constexpr int RSTEP = kBlock / GC;
+  constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
+  constexpr int NC = GC / 16;
+  __shared__ T xs[ROWS][PITCH];
+  __shared__ double srho[4][GC];
+  typedef typename AccOf<T>::type Acc;
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  T a0[4 * NT], a1[4 * NT];
+  switch (w) {
+    case 0: apply_load_a<T, NT, 0>(D, N, a0, a1, r16, q); break;
+    case 1: apply_load_a<T, NT, 1>(D, N, a0, a1, r16, q); break;
+    case 2: apply_load_a<T, NT, 2>(D, N, a0, a1, r16, q); break;
+    default: apply_load_a<T, NT, 3>(D, N, a0, a1, r16, q); break;
+  }
+  const int jt0 = w, jt1 = 7 - w;
+  const i64 nblk = (ng + GC - 1) / GC;
+  const int col = t % GC, row0 = t / GC;
+  T nxt[PER];
+  auto load = [&](i64 blk) {
+    const i64 g = blk * GC + col;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      nxt[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : (T)0;
+    }
+  };
+  i64 blk = blockIdx.x;
+  if (blk < nblk) load(blk);
+  for (; blk < nblk; blk += gridDim.x) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      if (row < ROWS) xs[row][col] = nxt[e];
+    }
+    __syncthreads();
+    if (blk + gridDim.x < nblk) load(blk + gridDim.x);
+    Acc acc0[NC], acc1[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      acc0[cc] = Acc{0, 0, 0, 0};
+      acc1[cc] = Acc{0, 0, 0, 0};
+    }
+    switch (w) {
+      case 0: apply_compute<T, NT, 0, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      case 1: apply_compute<T, NT, 1, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      case 2: apply_compute<T, NT, 2, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      default: apply_compute<T, NT, 3, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+    }
+    const i64 g0 = blk * GC;
+    double rp[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) rp[cc] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int jt = u == 0 ? jt0 : jt1;
+      if (jt >= NT) continue;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const i64 g = g0 + 16 * cc + r16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * jt + out_row<T>(q, r);
+          if (j < N && g < ng) {
+            const T v = xs[j][16 * cc + r16] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
+            out[(i64)j * ng + g] = v;
+            if (rho) rp[cc] += occ[j] * (double)v * (double)v;
+          }
+        }
+      }
+    }
+    if (rho != nullptr) {
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        double v = rp[cc];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (q == 0) srho[w][16 * cc + r16] = v;
+      }
+      __syncthreads();
+      if (t < GC) {
+        const i64 g = g0 + t;
+        if (g < ng) rho[g] = srho[0][t] + srho[1][t] + srho[2][t] + srho[3][t];
+      }
+    }
+  }
+}
+
+// G = dv * sum over splits of the 128 x 128 partial upper triangles; both halves.
+// Each 64-thread group sums one element over the splits, 4 splits per lane.
+__global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__restrict__ part,
+                                                              int N, int nsplit, double dv,
+                                                              double *__restrict__ G) {
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int e = blockIdx.x * 4 + (t >> 6);
+  if (e >= N * N) return;
+  const int i = e / N, j = e % N;
+  const int ri = min(i, j), cj = max(i, j);
+  double sacc = 0.0;
+  for (int sp = lane; sp < nsplit; sp += 64) sacc += part[(i64)sp * 128 * 128 + ri * 128 + cj];
+  sacc = wave_sum(sacc);
+  if (lane == 0) G[(i64)i * N + j] = sacc * dv;
+}
+
 }  // namespace
+
+#define POU_NT_SWITCH(NTV, MACRO) \
+  switch (NTV) {                  \
+    case 1: MACRO(1); break;      \
+    case 2: MACRO(2); break;      \
+    case 3: MACRO(3); break;      \
+    case 4: MACRO(4); break;      \
+    case 5: MACRO(5); break;      \
+    case 6: MACRO(6); break;      \
+    case 7: MACRO(7); break;      \
+    default: MACRO(8); break;     \
+  }
+
+size_t gram_partial_doubles(int N, int nsplit) {
+  if (N <= 128) return (size_t)nsplit * 128 * 128;
+  const int nb = (N + kGB - 1) / kGB;
+  return (size_t)nsplit * (nb * (nb + 1) / 2) * kGB * kGB;
+}
 
 template <typename T>
 hipError_t launch_gram_partial(const T *A, int N, i64 ng, int nsplit, double *part,
                                hipStream_t s) {
+  i64 kper = (ng + nsplit - 1) / nsplit;
+  kper = ((kper + 63) / 64) * 64;
+  if (N <= 128) {
+    const int NT = (N + 15) / 16;
+#define POU_GRAM_SMALL(K)                                                                  \
+  hipLaunchKernelGGL((k_gram_small<T, K, (sizeof(T) == 4 ? 64 : 32)>), dim3(nsplit), dim3(kBlock), \
+                     0, s, A, N, ng, kper, part)
+    POU_NT_SWITCH(NT, POU_GRAM_SMALL)
+#undef POU_GRAM_SMALL
+    return hipGetLastError();
+  }
   const int nb = (N + kGB - 1) / kGB;
   const int npairs = nb * (nb + 1) / 2;
-  i64 kper = (ng + nsplit - 1) / nsplit;
-  kper = ((kper + kKC - 1) / kKC) * kKC;
   hipLaunchKernelGGL(k_gram<T>, dim3(nsplit, npairs), dim3(kBlock), 0, s, A, N, ng, kper, part);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, double *part,
                                     hipStream_t s) {
+  i64 kper = (ng + nsplit - 1) / nsplit;
+  kper = ((kper + 63) / 64) * 64;
+  if (N <= 128) {
+    const int NT = (N + 15) / 16;
+#define POU_GRAM_SMALL_BF(K) \
+  hipLaunchKernelGGL((k_gram_small_bf16<K, 64>), dim3(nsplit), dim3(kBlock), 0, s, A, N, ng, kper, part)
+    POU_NT_SWITCH(NT, POU_GRAM_SMALL_BF)
+#undef POU_GRAM_SMALL_BF
+    return hipGetLastError();
+  }
   const int nb = (N + kGB - 1) / kGB;
   const int npairs = nb * (nb + 1) / 2;
-  i64 kper = (ng + nsplit - 1) / nsplit;
-  kper = ((kper + kKC - 1) / kKC) * kKC;
   hipLaunchKernelGGL(k_gram_bf16, dim3(nsplit, npairs), dim3(kBlock), 0, s, A, N, ng, kper,
                      part);
   return hipGetLastError();
@@ -392,6 +904,11 @@ hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, d
 
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s) {
+  if (N <= 128) {
+    hipLaunchKernelGGL(k_gram_reduce_small, dim3((N * N + 3) / 4), dim3(kBlock), 0, s, part, N,
+                       nsplit, dv, G);
+    return hipGetLastError();
+  }
   const int nb = (N + kGB - 1) / kGB;
   const int npairs = nb * (nb + 1) / 2;
   const i64 total = (i64)N * N;
@@ -402,8 +919,12 @@ hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, 
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky_inverse(double *G, double *Minv, int N, double *info,
-                                   hipStream_t s) {
+hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
+                                   double *info, hipStream_t s) {
+  if (N <= 128) {
+    hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(1024), 0, s, G, Minv, D32, D64, N, info);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, G, Minv, N, info);
   return hipGetLastError();
 }
@@ -417,8 +938,20 @@ hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int 
 }
 
 template <typename T>
-hipError_t launch_apply_lower(const double *M, const T *X, T *out, int N, i64 ng,
+hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, int N, i64 ng,
                               const double *occ, double *rho, hipStream_t s) {
+  if (N <= 128) {
+    const int NT = (N + 15) / 16;
+    constexpr int GC = sizeof(T) == 4 ? 64 : 32;
+    i64 nblk = (ng + GC - 1) / GC;
+    const int grid = (int)std::min<i64>(nblk, 1024);
+#define POU_APPLY_SMALL(K)                                                                  \
+  hipLaunchKernelGGL((k_apply_small<T, K, GC>), dim3(grid), dim3(kBlock), 0, s, D, X, out, N, \
+                     ng, occ, rho)
+    POU_NT_SWITCH(NT, POU_APPLY_SMALL)
+#undef POU_APPLY_SMALL
+    return hipGetLastError();
+  }
   const int NT = (N + 15) / 16;
   const int groups = (NT + 7) / 8;
   if (rho != nullptr && groups != 1) return hipErrorInvalidValue;
@@ -431,9 +964,11 @@ template hipError_t launch_gram_partial<double>(const double *, int, i64, int, d
                                                 hipStream_t);
 template hipError_t launch_gram_partial<float>(const float *, int, i64, int, double *,
                                                hipStream_t);
-template hipError_t launch_apply_lower<double>(const double *, const double *, double *, int,
-                                               i64, const double *, double *, hipStream_t);
-template hipError_t launch_apply_lower<float>(const double *, const float *, float *, int, i64,
-                                              const double *, double *, hipStream_t);
+template hipError_t launch_apply_lower<double>(const double *, const double *, const double *,
+                                               double *, int, i64, const double *, double *,
+                                               hipStream_t);
+template hipError_t launch_apply_lower<float>(const double *, const float *, const float *,
+                                              float *, int, i64, const double *, double *,
+                                              hipStream_t);
 
 }  // namespace pou

@@ -76,6 +76,8 @@ struct pou_ctx {
   size_t part_len = 0;
   double *d_gpart = nullptr;   // Gram partials
   double *d_G = nullptr, *d_Minv = nullptr, *d_Minv2 = nullptr, *d_Mcomb = nullptr;
+  double *d_D64 = nullptr;
+  float *d_D32 = nullptr;
   double *d_red = nullptr;     // small reduction outputs
   double *d_rep[2] = {nullptr, nullptr};  // evaluation reports (current, trial)
   void *d_HW = nullptr, *d_HWt = nullptr, *d_Wt = nullptr, *d_W1 = nullptr, *d_W2 = nullptr;
@@ -93,6 +95,16 @@ struct pou_ctx {
   void *eval_HU = nullptr;
   int last_cg_iters = 0;
   std::vector<double> rep_host;
+
+  // event timing
+  bool prof = false;
+  double prof_ms[POU_K_COUNT] = {};
+  long long prof_n[POU_K_COUNT] = {};
+  struct Pending { int tag; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int cur_tag = -1;
+  hipEvent_t cur_a = nullptr;
 };
 
 namespace {
@@ -108,6 +120,20 @@ pou_status fail(pou_ctx *c, pou_status s, const std::string &msg) {
     if (e_ != hipSuccess)                                                             \
       return fail(ctx, POU_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// launch with optional event timing of its kernel group
+#define KL(tag, expr)                                                                 \
+  do {                                                                                \
+    prof_begin(c, tag);                                                               \
+    hipError_t e_ = (expr);                                                           \
+    prof_end(c);                                                                      \
+    if (e_ != hipSuccess)                                                             \
+      return fail(c, POU_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void prof_begin(pou_ctx *c, int tag);
+void prof_end(pou_ctx *c);
+void prof_drain(pou_ctx *c);
 
 template <typename P>
 pou_status dalloc(pou_ctx *c, P **ptr, size_t bytes) {
@@ -132,6 +158,8 @@ void free_all(pou_ctx *c) {
   c->d_fft0 = c->d_fft1 = nullptr;
   c->d_sc = c->d_part = c->d_gpart = c->d_G = c->d_Minv = c->d_Minv2 = c->d_Mcomb = nullptr;
   c->d_red = nullptr;
+  c->d_D64 = nullptr;
+  c->d_D32 = nullptr;
   c->d_rep[0] = c->d_rep[1] = nullptr;
   c->d_HW = c->d_HWt = c->d_Wt = c->d_W1 = c->d_W2 = nullptr;
   c->have_system = false;
@@ -143,9 +171,61 @@ void free_all(pou_ctx *c) {
     if (s_ != POU_OK) return s_;        \
   } while (0)
 
+// ---- event timing: a (start, stop) event pair around each timed launch
+hipEvent_t pool_get(pou_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void prof_begin(pou_ctx *c, int tag) {
+  if (!c->prof) return;
+  c->cur_tag = tag;
+  c->cur_a = pool_get(c);
+  if (c->cur_a) (void)hipEventRecord(c->cur_a, c->stream);
+}
+
+void prof_end(pou_ctx *c) {
+  if (!c->prof || c->cur_tag < 0 || !c->cur_a) return;
+  hipEvent_t b = pool_get(c);
+  if (b) {
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({c->cur_tag, c->cur_a, b});
+  } else {
+    c->pool.push_back(c->cur_a);
+  }
+  c->cur_tag = -1;
+  c->cur_a = nullptr;
+}
+
+// after a stream synchronisation every recorded event has completed
+void prof_drain(pou_ctx *c) {
+  for (auto &p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_ms[p.tag] += ms;
+      c->prof_n[p.tag] += 1;
+    } else {
+      (void)hipGetLastError();
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
 pou_status sync_read(pou_ctx *c, void *host, const void *dev, size_t bytes) {
   HIPCHK(c, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_drain(c);
   return POU_OK;
 }
 
@@ -160,11 +240,11 @@ pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxi
   const int nb = c->nblk_field;
   const double ih2 = 1.0 / (c->h * c->h);
   double *sc = c->d_sc;  // [0] rz new, [1] rz old, [2] pq, [3] rr, [4] bb, [5] sum
-  HIPCHK(c, pou::launch_dot2(f, nullptr, c->d_part, ng, nb, s));
-  HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
-  HIPCHK(c, pou::launch_neg_lap(x, c->d_cg_q, nullptr, c->n, ih2, nb, s));
-  HIPCHK(c, pou::launch_cg_rhs_residual(f, sc + 5, c->d_cg_q, c->d_cg_r, c->d_part, ng, nb, s));
-  HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 2, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_dot2(f, nullptr, c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_neg_lap(x, c->d_cg_q, nullptr, c->n, ih2, nb, s));
+  KL(POU_K_POISSON, pou::launch_cg_rhs_residual(f, sc + 5, c->d_cg_q, c->d_cg_r, c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 2, 1.0, s));
   double rb[2];
   CHK(sync_read(c, rb, sc + 3, sizeof(rb)));
   const double bb = rb[1];
@@ -177,18 +257,18 @@ pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxi
   while (!conv && it < maxit) {
     const double *z = c->d_cg_r;
     if (precond) {
-      HIPCHK(c, pou::launch_spectral_inverse(c->d_cg_r, c->d_cg_z, c->d_fft0, c->d_fft1,
+      KL(POU_K_POISSON, pou::launch_spectral_inverse(c->d_cg_r, c->d_cg_z, c->d_fft0, c->d_fft1,
                                              c->d_lam1, c->n, s));
       z = c->d_cg_z;
     }
-    HIPCHK(c, pou::launch_dot2(c->d_cg_r, z, c->d_part, ng, nb, s));
-    HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 0, 1, nb, 1, 1.0, s));
-    HIPCHK(c, pou::launch_cg_update_p(c->d_cg_p, z, sc + 0, sc + 1, it == 0, ng, s));
-    HIPCHK(c, pou::launch_neg_lap(c->d_cg_p, c->d_cg_q, c->d_part, c->n, ih2, nb, s));
-    HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 2, 1, nb, 1, 1.0, s));
-    HIPCHK(c, pou::launch_cg_update_xr(x, c->d_cg_r, c->d_cg_p, c->d_cg_q, sc + 0, sc + 2,
+    KL(POU_K_POISSON, pou::launch_dot2(c->d_cg_r, z, c->d_part, ng, nb, s));
+    KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 0, 1, nb, 1, 1.0, s));
+    KL(POU_K_POISSON, pou::launch_cg_update_p(c->d_cg_p, z, sc + 0, sc + 1, it == 0, ng, s));
+    KL(POU_K_POISSON, pou::launch_neg_lap(c->d_cg_p, c->d_cg_q, c->d_part, c->n, ih2, nb, s));
+    KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 2, 1, nb, 1, 1.0, s));
+    KL(POU_K_POISSON, pou::launch_cg_update_xr(x, c->d_cg_r, c->d_cg_p, c->d_cg_q, sc + 0, sc + 2,
                                        c->d_part, ng, nb, s));
-    HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 1, 1.0, s));
+    KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 1, 1.0, s));
     HIPCHK(c, hipMemcpyAsync(sc + 1, sc + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
     ++it;
     if (it % check == 0 || it == maxit) {
@@ -198,9 +278,9 @@ pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxi
     }
   }
   // fix the gauge: zero mean
-  HIPCHK(c, pou::launch_dot2(x, nullptr, c->d_part, ng, nb, s));
-  HIPCHK(c, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
-  HIPCHK(c, pou::launch_remove_mean(x, sc + 5, ng, s));
+  KL(POU_K_POISSON, pou::launch_dot2(x, nullptr, c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_remove_mean(x, sc + 5, ng, s));
   if (iters) *iters = it;
   if (!conv)
     return fail(c, POU_ERR_CG_NO_CONV,
@@ -218,20 +298,20 @@ pou_status evaluate(pou_ctx *c, const T *W, T *HWout, double *rep, bool rho_read
                     int *cg_iters) {
   hipStream_t s = c->stream;
   const int N = c->N;
-  if (!rho_ready) HIPCHK(c, pou::launch_density<T>(W, c->d_occ, c->d_rho, N, c->ng, s));
+  if (!rho_ready) KL(POU_K_DENSITY, pou::launch_density<T>(W, c->d_occ, c->d_rho, N, c->ng, s));
   int it = 0;
   if (c->p.terms & POU_TERM_HARTREE) {
     CHK(poisson(c, c->d_rho, c->d_vh, c->p.cg_rtol, c->p.cg_maxit, c->p.cg_precond != 0, &it));
   }
   c->last_cg_iters = it;
   if (cg_iters) *cg_iters = it;
-  HIPCHK(c, pou::launch_xc_veff(c->d_rho, c->d_vh, c->d_vext, c->d_veff,
+  KL(POU_K_XC, pou::launch_xc_veff(c->d_rho, c->d_vh, c->d_vext, c->d_veff,
                                 sizeof(T) == 4 ? c->d_veff32 : nullptr, c->d_part, c->ng,
                                 c->p.terms, c->nblk_field, s));
-  HIPCHK(c, pou::launch_segment_sum(c->d_part, rep + 2 * N, 1, c->nblk_field, 3, c->dv, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep + 2 * N, 1, c->nblk_field, 3, c->dv, s));
   const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
-  HIPCHK(c, pou::launch_hamiltonian<T>(W, veff, HWout, c->d_part, N, c->st, s));
-  HIPCHK(c, pou::launch_segment_sum(c->d_part, rep, N, c->st.ntile * c->st.nzc, 2, c->dv, s));
+  KL(POU_K_HAMILTONIAN, pou::launch_hamiltonian<T>(W, veff, HWout, c->d_part, N, c->st, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep, N, c->st.ntile * c->st.nzc, 2, c->dv, s));
   return POU_OK;
 }
 
@@ -255,14 +335,19 @@ void terms_from_report(const pou_ctx *c, const double *rep, pou_energy_terms *t)
 // ------------------------------------------------------------------ orth
 
 template <typename T>
+const T *dmat(const pou_ctx *c) {
+  return sizeof(T) == 8 ? (const T *)c->d_D64 : (const T *)c->d_D32;
+}
+
+template <typename T>
 pou_status gram(pou_ctx *c, const T *X, bool bf16) {
   hipStream_t s = c->stream;
   if (bf16 && sizeof(T) == 4)
-    HIPCHK(c, pou::launch_gram_partial_bf16((const float *)X, c->N, c->ng, c->nsplit,
+    KL(POU_K_GRAM, pou::launch_gram_partial_bf16((const float *)X, c->N, c->ng, c->nsplit,
                                             c->d_gpart, s));
   else
-    HIPCHK(c, pou::launch_gram_partial<T>(X, c->N, c->ng, c->nsplit, c->d_gpart, s));
-  HIPCHK(c, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+    KL(POU_K_GRAM, pou::launch_gram_partial<T>(X, c->N, c->ng, c->nsplit, c->d_gpart, s));
+  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
   return POU_OK;
 }
 
@@ -279,12 +364,13 @@ pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info,
   *rho_done = false;
   for (int p = 0; p < passes; ++p) {
     CHK(gram<T>(c, cur, mixed && p == 0));
-    HIPCHK(c, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->N, info + 2 * p, s));
+    KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
+                                                       info + 2 * p, s));
     const bool last = (p == passes - 1);
     T *dst = last ? out : (T *)c->d_W1;
     if (cur == dst) return fail(c, POU_ERR_ARG, "internal: aliasing orth buffers");
     double *rho = (last && want_rho && fused_ok) ? c->d_rho : nullptr;
-    HIPCHK(c, pou::launch_apply_lower<T>(c->d_Minv, cur, dst, c->N, c->ng, c->d_occ, rho, s));
+    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), cur, dst, c->N, c->ng, c->d_occ, rho, s));
     if (rho) *rho_done = true;
     cur = dst;
   }
@@ -322,9 +408,9 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
   if (W != c->last_U || !c->cur_valid) CHK(restart<T>(c, W));
   double zz;
   if (!c->hist) {
-    HIPCHK(c, pou::launch_zz<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_part, N, c->ng,
+    KL(POU_K_OTHER, pou::launch_zz<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_part, N, c->ng,
                                 c->nblk_orb, s));
-    HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
+    KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
     std::vector<double> z(N);
     CHK(sync_read(c, z.data(), c->d_red, sizeof(double) * N));
     zz = 0.0;
@@ -352,7 +438,7 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
   for (int sidx = 0; sidx <= c->p.s_max; ++sidx) {
     tau = tau_bb * std::pow(c->p.delta, sidx);
     s_acc = sidx;
-    HIPCHK(c, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt, N,
+    KL(POU_K_TRIAL, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt, N,
                                    c->ng, s));
     bool rho_done = false;
     double *rep_t = c->d_rep[1];
@@ -376,10 +462,10 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
     }
   }
   // accept: U <- W2 and the dot products for the next BB step
-  HIPCHK(c, pou::launch_commit<T>(W, (const T *)c->d_HW, c->d_rep[0], (const T *)c->d_W2,
+  KL(POU_K_COMMIT, pou::launch_commit<T>(W, (const T *)c->d_HW, c->d_rep[0], (const T *)c->d_W2,
                                   (const T *)c->d_HWt, c->d_rep[1], c->d_part, N, c->ng,
                                   c->nblk_orb, s));
-  HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 4, c->dv, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 4, c->dv, s));
   std::vector<double> d(4 * N);
   CHK(sync_read(c, d.data(), c->d_red, sizeof(double) * 4 * N));
   double ss = 0, sy = 0, yy = 0, zn = 0;
@@ -433,8 +519,9 @@ pou_status orthonormalize_impl(pou_ctx *c, T *U, double *orth_err) {
   bool done = false;
   for (int p = 0; p < 3 && !done; ++p) {
     CHK(gram<T>(c, src, false));
-    HIPCHK(c, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->N, c->d_red, s));
-    HIPCHK(c, pou::launch_apply_lower<T>(c->d_Minv, src, dst, c->N, c->ng, nullptr, nullptr, s));
+    KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
+                                                       c->d_red, s));
+    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), src, dst, c->N, c->ng, nullptr, nullptr, s));
     CHK(sync_read(c, info, c->d_red, sizeof(info)));
     if (!std::isfinite(info[1])) return fail(c, POU_ERR_NONFINITE, "U is not finite");
     if (info[0] != 0.0)
@@ -455,6 +542,7 @@ pou_status orthonormalize_impl(pou_ctx *c, T *U, double *orth_err) {
     *orth_err = m;
   } else {
     HIPCHK(c, hipStreamSynchronize(s));
+    prof_drain(c);
   }
   if (c->last_U == U) c->cur_valid = false;
   if (c->eval_ptr == U) c->eval_ptr = nullptr;
@@ -486,12 +574,12 @@ pou_status backward_impl(pou_ctx *c, const T *U, double gE, T *dU, double *dR, d
   hipStream_t s = c->stream;
   if (c->eval_ptr != U) CHK(energy_impl<T>(c, U, nullptr));
   if (dU)
-    HIPCHK(c, pou::launch_backward_scale<T>((const T *)c->eval_HU, c->d_occ, gE * 2.0 * c->dv,
+    KL(POU_K_OTHER, pou::launch_backward_scale<T>((const T *)c->eval_HU, c->d_occ, gE * 2.0 * c->dv,
                                             dU, c->N, c->ng, s));
   if ((dR || dsig) && c->M > 0) {
     const int nb = std::min(256, c->nblk_field);
-    HIPCHK(c, pou::launch_ion_forces(c->d_atoms, c->M, c->d_vh, c->d_part, c->n, c->L, nb, s));
-    HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, c->M, nb, 4, -gE * c->dv, s));
+    KL(POU_K_OTHER, pou::launch_ion_forces(c->d_atoms, c->M, c->d_vh, c->d_part, c->n, c->L, nb, s));
+    KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, c->M, nb, 4, -gE * c->dv, s));
     std::vector<double> f(4 * c->M);
     CHK(sync_read(c, f.data(), c->d_red, sizeof(double) * f.size()));
     std::vector<double> R(3 * c->M), S(c->M);
@@ -505,6 +593,7 @@ pou_status backward_impl(pou_ctx *c, const T *U, double gE, T *dU, double *dR, d
                                        hipMemcpyHostToDevice, s));
   }
   HIPCHK(c, hipStreamSynchronize(s));
+  prof_drain(c);
   return POU_OK;
 }
 
@@ -512,11 +601,12 @@ template <typename T>
 pou_status hamiltonian_impl(pou_ctx *c, const T *U, T *HU, double *sigma) {
   hipStream_t s = c->stream;
   const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
-  HIPCHK(c, pou::launch_hamiltonian<T>(U, veff, HU, c->d_part, c->N, c->st, s));
-  HIPCHK(c, pou::launch_segment_sum(c->d_part, c->d_red, c->N, c->st.ntile * c->st.nzc, 2,
+  KL(POU_K_HAMILTONIAN, pou::launch_hamiltonian<T>(U, veff, HU, c->d_part, c->N, c->st, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, c->N, c->st.ntile * c->st.nzc, 2,
                                     c->dv, s));
   if (sigma) CHK(sync_read(c, sigma, c->d_red, sizeof(double) * c->N));
   else HIPCHK(c, hipStreamSynchronize(s));
+  prof_drain(c);
   return POU_OK;
 }
 
@@ -573,6 +663,8 @@ pou_status pou_destroy(pou_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   free_all(c);
+  prof_drain(c);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   delete c;
   return POU_OK;
 }
@@ -649,7 +741,8 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   c->nblk_orb = (int)std::max<i64>(1, std::min<i64>(64, ng / 16384));
   const int nb64 = (norb + 63) / 64;
   c->npairs = nb64 * (nb64 + 1) / 2;
-  c->nsplit = (int)std::max<i64>(1, std::min<i64>(std::max(1, 1024 / c->npairs), (ng + 31) / 32));
+  c->nsplit = (int)std::max<i64>(
+      1, std::min<i64>(norb <= 128 ? 512 : std::max(1, 1024 / c->npairs), (ng + 31) / 32));
 
   const size_t fbytes = sizeof(double) * (size_t)ng;
   const size_t bbytes = c->es * (size_t)ng * norb;
@@ -673,7 +766,9 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
                                   (size_t)3 * c->nblk_field, (size_t)4 * norb * c->nblk_orb,
                                   (size_t)4 * std::max(1, natoms) * 256, (size_t)16});
   CHK(dalloc(c, &c->d_part, sizeof(double) * c->part_len));
-  CHK(dalloc(c, &c->d_gpart, sizeof(double) * (size_t)c->nsplit * c->npairs * 64 * 64));
+  CHK(dalloc(c, &c->d_gpart, sizeof(double) * pou::gram_partial_doubles(norb, c->nsplit)));
+  CHK(dalloc(c, &c->d_D64, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_D32, sizeof(float) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_G, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Minv, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Minv2, sizeof(double) * (size_t)norb * norb));
@@ -702,13 +797,14 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   // V_ext = -P[rho_ion]: the periodic, background-neutralised potential of the
   // Gaussian ion charges
   if (natoms > 0 && (p.terms & POU_TERM_EXT)) {
-    HIPCHK(c, pou::launch_ion_density(c->d_atoms, natoms, c->d_rhoion, c->n, c->L, s));
+    KL(POU_K_OTHER, pou::launch_ion_density(c->d_atoms, natoms, c->d_rhoion, c->n, c->L, s));
     int it = 0;
     CHK(poisson(c, c->d_rhoion, c->d_vext, 1e-13, std::max(p.cg_maxit, 4000), p.cg_precond != 0,
                 &it));
-    HIPCHK(c, pou::launch_scale(c->d_vext, -1.0, ng, s));
+    KL(POU_K_POISSON, pou::launch_scale(c->d_vext, -1.0, ng, s));
   }
   HIPCHK(c, hipStreamSynchronize(s));
+  prof_drain(c);
   c->have_system = true;
   c->last_U = nullptr;
   c->cur_valid = false;
@@ -792,14 +888,39 @@ pou_status pou_convert(pou_ctx *c, const void *src, int src_prec, void *dst, int
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, POU_ERR_HIP, "hipSetDevice failed");
   hipStream_t s = c->stream;
   if (src_prec == POU_MIXED && dst_prec == POU_FP64)
-    HIPCHK(c, (pou::launch_convert<float, double>((const float *)src, (double *)dst, count, s)));
+    KL(POU_K_OTHER, (pou::launch_convert<float, double>((const float *)src, (double *)dst, count, s)));
   else if (src_prec == POU_FP64 && dst_prec == POU_MIXED)
-    HIPCHK(c, (pou::launch_convert<double, float>((const double *)src, (float *)dst, count, s)));
+    KL(POU_K_OTHER, (pou::launch_convert<double, float>((const double *)src, (float *)dst, count, s)));
   else if (src_prec == POU_FP64)
-    HIPCHK(c, (pou::launch_convert<double, double>((const double *)src, (double *)dst, count, s)));
+    KL(POU_K_OTHER, (pou::launch_convert<double, double>((const double *)src, (double *)dst, count, s)));
   else
-    HIPCHK(c, (pou::launch_convert<float, float>((const float *)src, (float *)dst, count, s)));
+    KL(POU_K_OTHER, (pou::launch_convert<float, float>((const float *)src, (float *)dst, count, s)));
   HIPCHK(c, hipStreamSynchronize(s));
+  prof_drain(c);
+  return POU_OK;
+}
+
+pou_status pou_profile_enable(pou_ctx *c, int enable) {
+  if (!c) return POU_ERR_ARG;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  prof_drain(c);
+  c->prof = enable != 0;
+  for (int k = 0; k < POU_K_COUNT; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  return POU_OK;
+}
+
+pou_status pou_profile_read(pou_ctx *c, int group, double *total_ms, long long *launches) {
+  if (!c) return POU_ERR_ARG;
+  if (group < 0 || group >= POU_K_COUNT) return fail(c, POU_ERR_ARG, "bad kernel group");
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  prof_drain(c);
+  if (total_ms) *total_ms = c->prof_ms[group];
+  if (launches) *launches = c->prof_n[group];
   return POU_OK;
 }
 

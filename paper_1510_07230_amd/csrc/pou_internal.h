@@ -174,17 +174,21 @@ hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, d
 // G = dv * sum of partials (full symmetric N x N)
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s);
-// Cholesky G = L L^T and Minv = L^-1 (lower).  info[0] = 1.0 if G is not
-// numerically SPD else 0.0; info[1] = max |G - I|.  Single workgroup.
-hipError_t launch_cholesky_inverse(double *G, double *Minv, int N, double *info,
-                                   hipStream_t s);
+// Cholesky G = L L^T and Minv = L^-1 (lower), plus D = Minv - I in FP64 and
+// FP32 (written for N <= 128).  info[0] = 1.0 if G is not numerically SPD
+// else 0.0; info[1] = max |G - I|.  Single workgroup.
+hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
+                                   double *info, hipStream_t s);
+// doubles needed by the Gram partial buffer
+size_t gram_partial_doubles(int N, int nsplit);
 // C = A * B for lower-triangular N x N matrices (FP64)
 hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int N,
                                hipStream_t s);
-// out[j][g] = sum_i M[j][i] X[i][g], M lower triangular N x N FP64.  When rho
+// out[j][g] = sum_i M[j][i] X[i][g], M lower triangular N x N FP64 (for
+// N <= 128 the kernel reads D = M - I in the element type instead).  When rho
 // is non-null also rho[g] = sum_j occ_j out[j][g]^2.
 template <typename T>
-hipError_t launch_apply_lower(const double *M, const T *X, T *out, int N, i64 ng,
+hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, int N, i64 ng,
                               const double *occ, double *rho, hipStream_t s);
 
 }  // namespace pou
