@@ -276,6 +276,25 @@ __global__ __launch_bounds__(1024) void k_cholesky_inverse(double *__restrict__ 
   if (t == 0) info[0] = sbad ? 1.0 : 0.0;
 }
 
+// M = A B for lower-triangular A, B, with D64 = M - I and D32 its FP32 copy
+// (the combined factor of two Cholesky-QR passes).
+__global__ __launch_bounds__(kBlock) void k_combine_factors(const double *__restrict__ A,
+                                                            const double *__restrict__ B,
+                                                            double *__restrict__ M,
+                                                            double *__restrict__ D64,
+                                                            float *__restrict__ D32, int N) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+    const int i = e / N, j = e % N;
+    double sacc = 0.0;
+    for (int k = j; k <= i; ++k) sacc += A[(i64)i * N + k] * B[(i64)k * N + j];
+    const double v = (j <= i) ? sacc : 0.0;
+    M[e] = v;
+    const double d = v - (i == j ? 1.0 : 0.0);
+    D64[e] = d;
+    D32[e] = (float)d;
+  }
+}
+
 // C = A B for lower-triangular A, B (upper parts zero).
 __global__ __launch_bounds__(kBlock) void k_lower_matmul(const double *__restrict__ A,
                                                          const double *__restrict__ B,
@@ -480,6 +499,175 @@ __global__ __launch_bounds__(1024) void k_chol_inv_small(const double *__restric
   if (t == 0) info[0] = sbad ? 1.0 : 0.0;
 }
 
+// ---------------------------------------------------------------- blocked Cholesky
+
+constexpr int kTP = 17;                 // padded pitch of a 16 x 16 FP64 tile in LDS
+constexpr int kTile = 16 * kTP;         // doubles per tile slot
+
+__device__ inline int tri_slot(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// D (+)= sign * X * Y^op for 16 x 16 FP64 tiles in LDS.  X is read as the
+// MFMA A operand (X[l%16][4s + q]); Y is read as Y[4s + q][l%16] (ytrans = 0)
+// or as Y^T, i.e. Y[l%16][4s + q] (ytrans = 1).  C is read from / written to
+// the accumulator layout (row q + 4r, column l%16) of dst; cin = 0 starts from 0.
+__device__ inline void tile_mma(const double *X, const double *Y, int ytrans, double sign,
+                                const double *C, double *dst, int l) {
+  const int r16 = l & 15, q = l >> 4;
+  d4 acc = d4{0, 0, 0, 0};
+  if (C) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = C[(q + 4 * r) * kTP + r16];
+  }
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const double a = sign * X[r16 * kTP + 4 * s4 + q];
+    const double b = ytrans ? Y[r16 * kTP + 4 * s4 + q] : Y[(4 * s4 + q) * kTP + r16];
+    acc = mfma(a, b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) dst[(q + 4 * r) * kTP + r16] = acc[r];
+}
+
+// Blocked Cholesky G = L L^T and L^-1 in one workgroup (N <= 128, 16-wide
+// panels, right-looking).  Panel p: one wave factors the 16 x 16 diagonal
+// block and inverts it (elimination on [A_pp | I]); the panel L_ip = A_ip
+// L_pp^-T and the block row B_pj <- L_pp^-1 B_pj of B = L^-1 follow on MFMA;
+// then the trailing update A_ij -= L_ip L_jp^T and the eliminations
+// B_ij -= L_ip B_pj.  A tile slot holds A_ij until its panel is processed and
+// B_ij afterwards.  Padding rows beyond N carry an identity diagonal.
+__global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restrict__ G, int N,
+                                                         double *__restrict__ Minv,
+                                                         float *__restrict__ D32,
+                                                         double *__restrict__ D64,
+                                                         double *__restrict__ info) {
+  __shared__ double slot[36 * kTile];
+  __shared__ double P[8 * kTile];
+  __shared__ double Li[kTile];
+  __shared__ double T[16 * 33];
+  __shared__ double sdg[128];
+  __shared__ double sred[4];
+  __shared__ int sbad;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int NT = (N + 15) / 16;
+  const int NP = 16 * NT;
+  double m = 0.0;
+  for (int e = t; e < NP * NP; e += kBlock) {
+    const int r = e / NP, c = e % NP;
+    if (c > r) continue;
+    double v;
+    if (r < N && c < N) {
+      v = G[(i64)r * N + c];
+      const double d = v - (r == c ? 1.0 : 0.0);
+      m = isfinite(d) ? fmax(m, fabs(d)) : INFINITY;
+    } else {
+      v = (r == c) ? 1.0 : 0.0;
+    }
+    slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] = v;
+  }
+  for (int r = t; r < NP; r += kBlock) sdg[r] = (r < N) ? G[(i64)r * N + r] : 1.0;
+  m = wave_max(m);
+  if (l == 0) sred[w] = m;
+  if (t == 0) sbad = 0;
+  __syncthreads();
+  if (t == 0) info[1] = fmax(fmax(sred[0], sred[1]), fmax(sred[2], sred[3]));
+  for (int p = 0; p < NT; ++p) {
+    // (a) one wave: [A_pp | I] -> [L_pp^T | L_pp^-1]
+    if (w == 0) {
+      const double *App = slot + tri_slot(p, p) * kTile;
+      for (int e = l; e < 512; e += 64) {
+        const int r = e >> 5, c = e & 31;
+        double v;
+        if (c < 16) v = (c <= r) ? App[r * kTP + c] : App[c * kTP + r];
+        else v = (c - 16 == r) ? 1.0 : 0.0;
+        T[r * 33 + c] = v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int k = 0; k < 16; ++k) {
+        double piv = T[k * 33 + k];
+        if (!((piv > 1e-13 * sdg[16 * p + k]) && isfinite(piv))) {
+          if (l == 0) sbad = 1;
+          piv = 1.0;
+        }
+        const double ip = 1.0 / piv, isp = 1.0 / sqrt(piv);
+        double nv[8];
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) {
+          const int e = l + 64 * mm;
+          const int r = e >> 5, c = e & 31;
+          const double v = T[r * 33 + c];
+          if (r == k) nv[mm] = v * isp;
+          else if (r > k) nv[mm] = v - T[r * 33 + k] * T[k * 33 + c] * ip;
+          else nv[mm] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) {
+          const int e = l + 64 * mm;
+          T[(e >> 5) * 33 + (e & 31)] = nv[mm];
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      for (int e = l; e < 256; e += 64) {
+        const int r = e >> 4, c = e & 15;
+        Li[r * kTP + c] = (c <= r) ? T[r * 33 + 16 + c] : 0.0;
+      }
+    }
+    __syncthreads();
+    // (b) panel L_ip = A_ip Li^T (i > p) into P[i]; (d) B_pj <- Li B_pj (j < p); B_pp = Li
+    {
+      const int nb = NT - 1 - p;  // panel tiles
+      const int nd = p;           // B row tiles
+      for (int task = w; task < nb + nd + 1; task += 4) {
+        if (task < nb) {
+          const int i = p + 1 + task;
+          tile_mma(slot + tri_slot(i, p) * kTile, Li, 1, 1.0, nullptr, P + i * kTile, l);
+        } else if (task < nb + nd) {
+          const int j = task - nb;
+          double *Bpj = slot + tri_slot(p, j) * kTile;
+          // in place: the MFMA chain reads the whole tile before the write
+          tile_mma(Li, Bpj, 0, 1.0, nullptr, Bpj, l);
+        } else {
+          double *Bpp = slot + tri_slot(p, p) * kTile;
+          for (int e = l; e < 256; e += 64) Bpp[(e >> 4) * kTP + (e & 15)] = Li[(e >> 4) * kTP + (e & 15)];
+        }
+      }
+    }
+    __syncthreads();
+    // (c) A_ij -= L_ip L_jp^T (p < j <= i); (e) B_ij -= L_ip B_pj (i > p, j <= p)
+    {
+      const int m1 = NT - 1 - p;
+      const int nc = m1 * (m1 + 1) / 2;
+      const int ne = m1 * (p + 1);
+      for (int task = w; task < nc + ne; task += 4) {
+        if (task < nc) {
+          // decode (i, j) with p < j <= i
+          int a = task, ii = 0;
+          while (a > ii) { a -= ii + 1; ++ii; }
+          const int i = p + 1 + ii, j = p + 1 + a;
+          double *Aij = slot + tri_slot(i, j) * kTile;
+          tile_mma(P + i * kTile, P + j * kTile, 1, -1.0, Aij, Aij, l);
+        } else {
+          const int a = task - nc;
+          const int i = p + 1 + a / (p + 1), j = a % (p + 1);
+          double *Bij = slot + tri_slot(i, j) * kTile;
+          tile_mma(P + i * kTile, slot + tri_slot(p, j) * kTile, 0, -1.0, j < p ? Bij : nullptr,
+                   Bij, l);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < N * N; e += kBlock) {
+    const int r = e / N, c = e % N;
+    const double v = (c <= r) ? slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] : 0.0;
+    Minv[e] = v;
+    const double d = v - (r == c ? 1.0 : 0.0);
+    D64[e] = d;
+    D32[e] = (float)d;
+  }
+  if (t == 0) info[0] = sbad ? 1.0 : 0.0;
+}
+
 // Tiles of the N <= 128 Gram owned by wave W: row tiles W and 7 - W with the
 // column tiles on or right of the diagonal (8 - W and W + 1 tiles, 9 in all).
 template <int W, int U>
@@ -551,9 +739,14 @@ __device__ inline void gram_tile_runtime(int w, int u, int &rt, int &ct) {
 // triangle per workgroup so every row is read once.  Chunks of KC points are
 // staged in LDS; the next chunk is loaded into registers while the current one
 // is multiplied.  The per-wave tile choice is resolved at compile time.
-template <typename T, int NT, int KC>
+// TRIAL: A is the trial point W - tau Z formed on the fly from W = A and
+// HW (z_i = H w_i - sigma_ii w_i, section 3.2) and written to Wt.
+template <typename T, int NT, int KC, bool TRIAL>
 __global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, int N, i64 ng,
-                                                       i64 kper, double *__restrict__ part) {
+                                                          i64 kper, double *__restrict__ part,
+                                                          const T *__restrict__ HW,
+                                                          const double *__restrict__ sig,
+                                                          double tau, T *__restrict__ Wt) {
   constexpr int ROWS = 16 * NT;
   constexpr int PITCH = KC + 1;
   constexpr int TPR = KC;                      // threads per staged row
@@ -575,20 +768,38 @@ __global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, 
   }
   const int col = t % TPR, row0 = t / TPR;
   T nxt[PER];
+  T nxh[TRIAL ? PER : 1];
+  T ca[TRIAL ? PER : 1];
+  if (TRIAL) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      ca[e] = (row < N) ? (T)(1.0 + tau * sig[row]) : (T)0;
+    }
+  }
   auto load = [&](i64 k0) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
       const i64 g = k0 + col;
-      nxt[e] = (row < N && g < k_end) ? A[(i64)row * ng + g] : (T)0;
+      const bool ok = row < N && g < k_end;
+      nxt[e] = ok ? A[(i64)row * ng + g] : (T)0;
+      if (TRIAL) nxh[e] = ok ? HW[(i64)row * ng + g] : (T)0;
     }
   };
   if (k_beg < k_end) load(k_beg);
+  const T tt = (T)tau;
   for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
-      if (row < ROWS) s[row][col] = nxt[e];
+      T v = nxt[e];
+      if (TRIAL) {
+        v = ca[e] * v - tt * nxh[e];
+        const i64 g = k0 + col;
+        if (row < N && g < k_end) Wt[(i64)row * ng + g] = v;
+      }
+      if (row < ROWS) s[row][col] = v;
     }
     __syncthreads();
     if (k0 + KC < k_end) load(k0 + KC);
@@ -626,10 +837,13 @@ __global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, 
 
 // The same contraction with the FP32 values rounded to BF16 (MFMA 16x16x32,
 // FP32 accumulation per 32 points, flushed into FP64).
-template <int NT, int KC>
+template <int NT, int KC, bool TRIAL>
 __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restrict__ A, int N,
-                                                            i64 ng, i64 kper,
-                                                            double *__restrict__ part) {
+                                                               i64 ng, i64 kper,
+                                                               double *__restrict__ part,
+                                                               const float *__restrict__ HW,
+                                                               const double *__restrict__ sig,
+                                                               double tau, float *__restrict__ Wt) {
   constexpr int ROWS = 16 * NT;
   constexpr int PITCH = KC + 4;
   constexpr int TPR = KC;
@@ -647,20 +861,38 @@ __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restr
     for (int r = 0; r < 4; ++r) accd[u][r] = 0.0;
   const int col = t % TPR, row0 = t / TPR;
   float nxt[PER];
+  float nxh[TRIAL ? PER : 1];
+  float ca[TRIAL ? PER : 1];
+  if (TRIAL) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      ca[e] = (row < N) ? (float)(1.0 + tau * sig[row]) : 0.0f;
+    }
+  }
   auto load = [&](i64 k0) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
       const i64 g = k0 + col;
-      nxt[e] = (row < N && g < k_end) ? A[(i64)row * ng + g] : 0.0f;
+      const bool ok = row < N && g < k_end;
+      nxt[e] = ok ? A[(i64)row * ng + g] : 0.0f;
+      if (TRIAL) nxh[e] = ok ? HW[(i64)row * ng + g] : 0.0f;
     }
   };
   if (k_beg < k_end) load(k_beg);
+  const float tt = (float)tau;
   for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
-      if (row < ROWS) s[row][col] = nxt[e];
+      float v = nxt[e];
+      if (TRIAL) {
+        v = ca[e] * v - tt * nxh[e];
+        const i64 g = k0 + col;
+        if (row < N && g < k_end) Wt[(i64)row * ng + g] = v;
+      }
+      if (row < ROWS) s[row][col] = v;
     }
     __syncthreads();
     if (k0 + KC < k_end) load(k0 + KC);
@@ -826,21 +1058,35 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
   }
 }
 
-// G = dv * sum over splits of the 128 x 128 partial upper triangles; both halves.
-// Each 64-thread group sums one element over the splits, 4 splits per lane.
+// G = dv * sum over splits of the 128 x 128 partial upper triangles; both
+// halves.  Lane = element (coalesced over the 128 x 128 partial), the four
+// waves of a workgroup take every fourth split and combine through LDS.
 __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__restrict__ part,
                                                               int N, int nsplit, double dv,
                                                               double *__restrict__ G) {
+  __shared__ double sacc[4][64];
   const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int e = blockIdx.x * 4 + (t >> 6);
-  if (e >= N * N) return;
-  const int i = e / N, j = e % N;
-  const int ri = min(i, j), cj = max(i, j);
-  double sacc = 0.0;
-  for (int sp = lane; sp < nsplit; sp += 64) sacc += part[(i64)sp * 128 * 128 + ri * 128 + cj];
-  sacc = wave_sum(sacc);
-  if (lane == 0) G[(i64)i * N + j] = sacc * dv;
+  const int lane = t & 63, w = t >> 6;
+  const int e = blockIdx.x * 64 + lane;  // element of the 128 x 128 partial
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int sp = w;
+  for (; sp + 12 < nsplit; sp += 16) {
+    acc0 += part[(i64)sp * 128 * 128 + e];
+    acc1 += part[(i64)(sp + 4) * 128 * 128 + e];
+    acc2 += part[(i64)(sp + 8) * 128 * 128 + e];
+    acc3 += part[(i64)(sp + 12) * 128 * 128 + e];
+  }
+  for (; sp < nsplit; sp += 4) acc0 += part[(i64)sp * 128 * 128 + e];
+  sacc[w][lane] = (acc0 + acc1) + (acc2 + acc3);
+  __syncthreads();
+  if (w == 0) {
+    const double v = (sacc[0][lane] + sacc[1][lane] + sacc[2][lane] + sacc[3][lane]) * dv;
+    const int r = e >> 7, c = e & 127;
+    if (r <= c && c < N) {
+      G[(i64)r * N + c] = v;
+      G[(i64)c * N + r] = v;
+    }
+  }
 }
 
 }  // namespace
@@ -866,46 +1112,64 @@ size_t gram_partial_doubles(int N, int nsplit) {
 template <typename T>
 hipError_t launch_gram_partial(const T *A, int N, i64 ng, int nsplit, double *part,
                                hipStream_t s) {
-  i64 kper = (ng + nsplit - 1) / nsplit;
-  kper = ((kper + 63) / 64) * 64;
-  if (N <= 128) {
-    const int NT = (N + 15) / 16;
-#define POU_GRAM_SMALL(K)                                                                  \
-  hipLaunchKernelGGL((k_gram_small<T, K, (sizeof(T) == 4 ? 64 : 32)>), dim3(nsplit), dim3(kBlock), \
-                     0, s, A, N, ng, kper, part)
-    POU_NT_SWITCH(NT, POU_GRAM_SMALL)
-#undef POU_GRAM_SMALL
-    return hipGetLastError();
-  }
-  const int nb = (N + kGB - 1) / kGB;
-  const int npairs = nb * (nb + 1) / 2;
-  hipLaunchKernelGGL(k_gram<T>, dim3(nsplit, npairs), dim3(kBlock), 0, s, A, N, ng, kper, part);
-  return hipGetLastError();
+  return launch_trial_gram<T>(A, nullptr, nullptr, 0.0, nullptr, N, ng, nsplit, false, part, s);
 }
 
 hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, double *part,
                                     hipStream_t s) {
+  return launch_trial_gram<float>(A, nullptr, nullptr, 0.0, nullptr, N, ng, nsplit, true, part, s);
+}
+
+template <typename T>
+hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, double tau, T *Wt,
+                             int N, i64 ng, int nsplit, bool bf16, double *part, hipStream_t s) {
   i64 kper = (ng + nsplit - 1) / nsplit;
   kper = ((kper + 63) / 64) * 64;
+  const bool trial = HW != nullptr;
   if (N <= 128) {
     const int NT = (N + 15) / 16;
-#define POU_GRAM_SMALL_BF(K) \
-  hipLaunchKernelGGL((k_gram_small_bf16<K, 64>), dim3(nsplit), dim3(kBlock), 0, s, A, N, ng, kper, part)
-    POU_NT_SWITCH(NT, POU_GRAM_SMALL_BF)
-#undef POU_GRAM_SMALL_BF
+    if (bf16 && sizeof(T) == 4) {
+      const float *Wf = (const float *)W;
+      const float *Hf = (const float *)HW;
+      float *Wtf = (float *)Wt;
+#define POU_GB(K)                                                                          \
+  if (trial)                                                                               \
+    hipLaunchKernelGGL((k_gram_small_bf16<K, 32, true>), dim3(nsplit), dim3(kBlock), 0, s, Wf, \
+                       N, ng, kper, part, Hf, sig, tau, Wtf);                             \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_gram_small_bf16<K, 64, false>), dim3(nsplit), dim3(kBlock), 0, s, Wf, \
+                       N, ng, kper, part, Hf, sig, tau, Wtf)
+      POU_NT_SWITCH(NT, POU_GB)
+#undef POU_GB
+      return hipGetLastError();
+    }
+#define POU_GS(K)                                                                             \
+  if (trial)                                                                                  \
+    hipLaunchKernelGGL((k_gram_small<T, K, 32, true>), dim3(nsplit), dim3(kBlock), 0, s, W, N, \
+                       ng, kper, part, HW, sig, tau, Wt);                                     \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_gram_small<T, K, (sizeof(T) == 4 ? 64 : 32), false>), dim3(nsplit),  \
+                       dim3(kBlock), 0, s, W, N, ng, kper, part, HW, sig, tau, Wt)
+    POU_NT_SWITCH(NT, POU_GS)
+#undef POU_GS
     return hipGetLastError();
   }
+  if (trial) return hipErrorInvalidValue;  // the engine forms the trial separately for N > 128
   const int nb = (N + kGB - 1) / kGB;
   const int npairs = nb * (nb + 1) / 2;
-  hipLaunchKernelGGL(k_gram_bf16, dim3(nsplit, npairs), dim3(kBlock), 0, s, A, N, ng, kper,
-                     part);
+  kper = ((kper + kKC - 1) / kKC) * kKC;
+  if (bf16 && sizeof(T) == 4)
+    hipLaunchKernelGGL(k_gram_bf16, dim3(nsplit, npairs), dim3(kBlock), 0, s, (const float *)W, N,
+                       ng, kper, part);
+  else
+    hipLaunchKernelGGL(k_gram<T>, dim3(nsplit, npairs), dim3(kBlock), 0, s, W, N, ng, kper, part);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s) {
   if (N <= 128) {
-    hipLaunchKernelGGL(k_gram_reduce_small, dim3((N * N + 3) / 4), dim3(kBlock), 0, s, part, N,
+    hipLaunchKernelGGL(k_gram_reduce_small, dim3(128 * 128 / 64), dim3(kBlock), 0, s, part, N,
                        nsplit, dv, G);
     return hipGetLastError();
   }
@@ -922,7 +1186,7 @@ hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, 
 hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
                                    double *info, hipStream_t s) {
   if (N <= 128) {
-    hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(1024), 0, s, G, Minv, D32, D64, N, info);
+    hipLaunchKernelGGL(k_chol_blocked, dim3(1), dim3(kBlock), 0, s, G, N, Minv, D32, D64, info);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, G, Minv, N, info);
@@ -937,14 +1201,22 @@ hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int 
   return hipGetLastError();
 }
 
+hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
+                                  float *D32, int N, hipStream_t s) {
+  int blocks = (N * N + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_combine_factors, dim3(blocks), dim3(kBlock), 0, s, A, B, M, D64, D32, N);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, int N, i64 ng,
                               const double *occ, double *rho, hipStream_t s) {
   if (N <= 128) {
     const int NT = (N + 15) / 16;
-    constexpr int GC = sizeof(T) == 4 ? 64 : 32;
+    constexpr int GC = sizeof(T) == 4 ? 32 : 16;
     i64 nblk = (ng + GC - 1) / GC;
-    const int grid = (int)std::min<i64>(nblk, 1024);
+    const int grid = (int)std::min<i64>(nblk, 512);
 #define POU_APPLY_SMALL(K)                                                                  \
   hipLaunchKernelGGL((k_apply_small<T, K, GC>), dim3(grid), dim3(kBlock), 0, s, D, X, out, N, \
                      ng, occ, rho)
@@ -960,6 +1232,12 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
   return hipGetLastError();
 }
 
+template hipError_t launch_trial_gram<double>(const double *, const double *, const double *,
+                                              double, double *, int, i64, int, bool, double *,
+                                              hipStream_t);
+template hipError_t launch_trial_gram<float>(const float *, const float *, const double *,
+                                             double, float *, int, i64, int, bool, double *,
+                                             hipStream_t);
 template hipError_t launch_gram_partial<double>(const double *, int, i64, int, double *,
                                                 hipStream_t);
 template hipError_t launch_gram_partial<float>(const float *, int, i64, int, double *,

@@ -377,8 +377,38 @@ pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info,
   return POU_OK;
 }
 
-// ------------------------------------------------------------------ step
+// Trial point and its orthonormalisation for N <= 128: one pass forms
+// Wt = W - tau Z and the first Gram; Cholesky; for two passes the first factor
+// is applied once to measure the second Gram, and the product of both factors
+// is applied to Wt in the final pass, which also forms rho.
+template <typename T>
+pou_status trial_orth_fused(pou_ctx *c, const T *W, double tau, double *info) {
+  hipStream_t s = c->stream;
+  const bool mixed = sizeof(T) == 4;
+  const int passes = c->p.orth_passes;
+  KL(POU_K_GRAM, pou::launch_trial_gram<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt,
+                                           c->N, c->ng, c->nsplit, mixed && passes == 2,
+                                           c->d_gpart, s));
+  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+  KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
+                                                  info, s));
+  if (passes == 2) {
+    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), (const T *)c->d_Wt,
+                                               (T *)c->d_W1, c->N, c->ng, nullptr, nullptr, s));
+    KL(POU_K_GRAM, pou::launch_trial_gram<T>((const T *)c->d_W1, nullptr, nullptr, 0.0, nullptr,
+                                             c->N, c->ng, c->nsplit, false, c->d_gpart, s));
+    KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+    KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv2, c->d_D32, c->d_D64, c->N,
+                                                    info + 2, s));
+    KL(POU_K_CHOLESKY, pou::launch_combine_factors(c->d_Minv2, c->d_Minv, c->d_Mcomb, c->d_D64,
+                                                   c->d_D32, c->N, s));
+  }
+  KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), (const T *)c->d_Wt,
+                                             (T *)c->d_W2, c->N, c->ng, c->d_occ, c->d_rho, s));
+  return POU_OK;
+}
 
+// ------------------------------------------------------------------ step
 template <typename T>
 pou_status restart(pou_ctx *c, const T *W) {
   int it = 0;
@@ -438,12 +468,17 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
   for (int sidx = 0; sidx <= c->p.s_max; ++sidx) {
     tau = tau_bb * std::pow(c->p.delta, sidx);
     s_acc = sidx;
-    KL(POU_K_TRIAL, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt, N,
-                                   c->ng, s));
     bool rho_done = false;
     double *rep_t = c->d_rep[1];
-    CHK(orth_passes<T>(c, (const T *)c->d_Wt, (T *)c->d_W2, passes, rep_t + 2 * N + 3, true,
-                       &rho_done));
+    if (N <= 128) {
+      CHK(trial_orth_fused<T>(c, W, tau, rep_t + 2 * N + 3));
+      rho_done = true;
+    } else {
+      KL(POU_K_TRIAL, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt,
+                                           N, c->ng, s));
+      CHK(orth_passes<T>(c, (const T *)c->d_Wt, (T *)c->d_W2, passes, rep_t + 2 * N + 3, true,
+                         &rho_done));
+    }
     int it = 0;
     CHK(evaluate<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, rho_done, &it));
     cg_total += it;

@@ -20,31 +20,41 @@ __host__ __device__ inline int wrap(int i, int n) {
 // ----------------------------------------------------------------- stencil
 
 // H u = -1/2 Lap_h u + V_eff u on the periodic grid (section 2.1 H(rho), with
-// the 8th-order finite-difference Laplacian), one orbital per blockIdx.z.
-// Each workgroup owns a 32x32 x-y tile and marches over a chunk of z planes;
-// the current plane with its radius-4 x/y halo is staged in LDS and the z
-// neighbours live in a per-thread register queue (2.5-D blocking).  The
+// the 8th-order finite-difference Laplacian).  Each workgroup owns a 32x32 x-y
+// tile of one orbital and marches over a chunk of z planes: the current plane
+// with its radius-4 x/y halo is staged in LDS and the z neighbours live in a
+// per-thread register queue (2.5-D blocking).  A thread computes 4 consecutive
+// y rows of one x column, so the y neighbours of its points overlap.  The
 // second differences are formed as sums of (u_{+m} - u_0) + (u_{-m} - u_0),
-// which is exact in real arithmetic because the weights sum to zero and
-// keeps FP32 cancellation small.
+// exact in real arithmetic because the weights sum to zero, which keeps FP32
+// cancellation small.
+//
+// Workgroup order: the 1-D grid is walked XCD by XCD (workgroup id mod 8
+// selects the XCD) so that all tiles of one (orbital, z chunk) run on the
+// same XCD one after another and their halos hit that XCD's L2.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
                                                         const T *__restrict__ veff,
                                                         T *__restrict__ HU,
                                                         double *__restrict__ part,
-                                                        StencilArgs a) {
+                                                        StencilArgs a, int N) {
   __shared__ T s[kTY + 2 * kRad][kTX + 2 * kRad + 1];
   __shared__ double red[4 * 2];
   const int n = a.n;
   const i64 ng = (i64)n * n * n;
   const int tiles_x = (n + kTX - 1) / kTX;
-  const int tile = blockIdx.x;
-  const int zc = blockIdx.y;
-  const int orb = blockIdx.z;
+  // XCD-aware decode: L = 8 j + x -> group g = x + 8 (j / ntile), tile = j % ntile
+  const int L = blockIdx.x;
+  const int xcd = L & 7, j = L >> 3;
+  const int grp = xcd + 8 * (j / a.ntile);
+  const int tile = j % a.ntile;
+  if (grp >= N * a.nzc) return;  // padding workgroups (before any barrier)
+  const int orb = grp / a.nzc;
+  const int zc = grp % a.nzc;
   const int x0 = (tile % tiles_x) * kTX;
   const int y0 = (tile / tiles_x) * kTY;
   const int tx = threadIdx.x & 31;
-  const int trow = threadIdx.x >> 5;  // 0..7
+  const int trow = threadIdx.x >> 5;  // 0..7, owns rows 4*trow .. 4*trow+3
   const T *u = U + (i64)orb * ng;
   T *hu = HU + (i64)orb * ng;
 
@@ -55,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   bool valid[kNB];
 #pragma unroll
   for (int r = 0; r < kNB; ++r) {
-    const int gy = y0 + trow + 8 * r;
+    const int gy = y0 + 4 * trow + r;
     gyw[r] = wrap(gy, n);
     valid[r] = vx && gy < n;
   }
@@ -81,48 +91,95 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
 #pragma unroll
     for (int r = 0; r < kNB; ++r) q[r][m] = u[((i64)zz * n + gyw[r]) * n + gxw];
   }
-  const double c[5] = {0.0, FD8::c1, FD8::c2, FD8::c3, FD8::c4};
-  const T ih2 = (T)a.inv_h2;
+  const T c1 = (T)FD8::c1, c2 = (T)FD8::c2, c3 = (T)FD8::c3, c4 = (T)FD8::c4;
+  const T cm[5] = {(T)0, c1, c2, c3, c4};
+  const T mh = (T)(-0.5 * a.inv_h2);
   double acc_sig = 0.0, acc_kin = 0.0;
 
-  for (int z = z0; z < z1; ++z) {
-    const int zn = wrap(z + kRad, n);
+  // Loads for plane zz are issued kPD planes ahead of their use into a ring
+  // of register sets (the halo of plane zz, the queue head zz + 4 and V_eff
+  // on plane zz), so kPD planes of loads are in flight per workgroup.  The
+  // z loop is unrolled by kPD so every ring index is a compile-time constant.
+  constexpr int kPD = 2;
+  T nhx[kPD], nhy[kPD], nq[kPD][kNB], nvf[kPD][kNB];
+  auto issue = [&](int slot, int zz) {
+    const i64 pl = (i64)zz * n;
+    const T hx = u[(pl + hx_gy) * n + hx_gx];
+    const T hy = u[(pl + hy_gy) * n + hy_gx];
+    const i64 pq = (i64)wrap(zz + kRad, n) * n;
+    T qq[kNB], vv[kNB];
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) q[r][2 * kRad] = u[((i64)zn * n + gyw[r]) * n + gxw];
-    const i64 plane = (i64)z * n;
-    // stage plane z
+    for (int r = 0; r < kNB; ++r) qq[r] = u[(pq + gyw[r]) * n + gxw];
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) s[trow + 8 * r + kRad][tx + kRad] = q[r][kRad];
-    s[hx_row + kRad][hx_lc + kRad] = u[(plane + hx_gy) * n + hx_gx];
-    s[hy_lr + kRad][hy_col + kRad] = u[(plane + hy_gy) * n + hy_gx];
-    __syncthreads();
+    for (int r = 0; r < kNB; ++r) vv[r] = veff[(pl + gyw[r]) * n + gxw];
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) {
-      const int ly = trow + 8 * r + kRad;
-      const int lx = tx + kRad;
-      const T c0 = q[r][kRad];
-      T lap = (T)0;
+    for (int k = 0; k < kPD; ++k) {
+      if (k == slot) {
+        nhx[k] = hx;
+        nhy[k] = hy;
 #pragma unroll
-      for (int m = 1; m <= kRad; ++m) {
-        const T dxm = (s[ly][lx + m] - c0) + (s[ly][lx - m] - c0);
-        const T dym = (s[ly + m][lx] - c0) + (s[ly - m][lx] - c0);
-        const T dzm = (q[r][kRad + m] - c0) + (q[r][kRad - m] - c0);
-        lap += (T)c[m] * ((dxm + dym) + dzm);
-      }
-      const T ku = (T)(-0.5) * lap * ih2;
-      if (valid[r]) {
-        const i64 g = (plane + gyw[r]) * n + gxw;
-        const T h = ku + veff[g] * c0;
-        hu[g] = h;
-        acc_sig += (double)c0 * (double)h;
-        acc_kin += (double)c0 * (double)ku;
+        for (int r = 0; r < kNB; ++r) {
+          nq[k][r] = qq[r];
+          nvf[k][r] = vv[r];
+        }
       }
     }
-    __syncthreads();
+  };
 #pragma unroll
-    for (int m = 0; m < 2 * kRad; ++m) {
+  for (int k = 0; k < kPD; ++k)
+    if (z0 + k < z1) issue(k, z0 + k);
+
+  for (int zb = z0; zb < z1; zb += kPD) {
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) q[r][m] = q[r][m + 1];
+    for (int k = 0; k < kPD; ++k) {
+      const int z = zb + k;
+      if (z < z1) {
+        const i64 plane = (i64)z * n;
+        T vf[kNB];
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) {
+          q[r][2 * kRad] = nq[k][r];
+          vf[r] = nvf[k][r];
+        }
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) s[4 * trow + r + kRad][tx + kRad] = q[r][kRad];
+        s[hx_row + kRad][hx_lc + kRad] = nhx[k];
+        s[hy_lr + kRad][hy_col + kRad] = nhy[k];
+        if (z + kPD < z1) issue(k, z + kPD);
+        __syncthreads();
+        // y column of this thread: rows 4 trow - 4 .. 4 trow + 7 (local + kRad offset)
+        T col[kNB + 2 * kRad];
+#pragma unroll
+        for (int kk = 0; kk < kNB + 2 * kRad; ++kk) col[kk] = s[4 * trow + kk][tx + kRad];
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) {
+          const int ly = 4 * trow + r + kRad;
+          const int lx = tx + kRad;
+          const T c0 = col[r + kRad];
+          T lap = (T)0;
+#pragma unroll
+          for (int m = 1; m <= kRad; ++m) {
+            const T dxm = (s[ly][lx + m] - c0) + (s[ly][lx - m] - c0);
+            const T dym = (col[r + kRad + m] - c0) + (col[r + kRad - m] - c0);
+            const T dzm = (q[r][kRad + m] - c0) + (q[r][kRad - m] - c0);
+            lap += cm[m] * ((dxm + dym) + dzm);
+          }
+          const T ku = mh * lap;
+          if (valid[r]) {
+            const i64 g = (plane + gyw[r]) * n + gxw;
+            const T h = ku + vf[r] * c0;
+            hu[g] = h;
+            acc_sig += (double)c0 * (double)h;
+            acc_kin += (double)c0 * (double)ku;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 2 * kRad; ++m) {
+#pragma unroll
+          for (int r = 0; r < kNB; ++r) q[r][m] = q[r][m + 1];
+        }
+      }
     }
   }
   double v[2] = {acc_sig, acc_kin};
@@ -732,8 +789,10 @@ inline int grid_for(i64 work, int cap = 4096) {
 template <typename T>
 hipError_t launch_hamiltonian(const T *U, const T *veff, T *HU, double *part, int N,
                               const StencilArgs &a, hipStream_t s) {
-  dim3 grid(a.ntile, a.nzc, N);
-  hipLaunchKernelGGL(k_hamiltonian<T>, grid, dim3(kBlock), 0, s, U, veff, HU, part, a);
+  const int groups = N * a.nzc;
+  const int per_xcd = (groups + 7) / 8;
+  dim3 grid(8 * per_xcd * a.ntile);
+  hipLaunchKernelGGL(k_hamiltonian<T>, grid, dim3(kBlock), 0, s, U, veff, HU, part, a, N);
   return hipGetLastError();
 }
 

@@ -171,6 +171,15 @@ hipError_t launch_gram_partial(const T *A, int N, i64 ng, int nsplit, double *pa
 // flushed to FP64).
 hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, double *part,
                                     hipStream_t s);
+// Trial point and Gram in one pass: Wt = (1 + tau sig_i) W - tau HW is written
+// and its partial Gram accumulated (N <= 128; HW == nullptr: plain Gram of W).
+// bf16: products of BF16-rounded FP32 values (first Cholesky-QR pass).
+template <typename T>
+hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, double tau, T *Wt,
+                             int N, i64 ng, int nsplit, bool bf16, double *part, hipStream_t s);
+// M = A B (lower-triangular), D64 = M - I, D32 = (float) D64
+hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
+                                  float *D32, int N, hipStream_t s);
 // G = dv * sum of partials (full symmetric N x N)
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s);
