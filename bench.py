@@ -26,6 +26,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "orbital-update iters/sec at 96³ grid N=128, mixed vs FP64 at |ΔE|≤1e-6 Ha"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mixed96.json")
+KERNEL_SOURCES = {"apply": "dense_kernels.hip", "gram": "dense_kernels.hip",
+                  "hamiltonian": "grid_kernels.hip", "trial": "grid_kernels.hip",
+                  "commit": "grid_kernels.hip", "density": "grid_kernels.hip"}
+
+
+def source_sha(name):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1510_07230_amd", "csrc", name)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(group):
+    """HBM bytes per launch of the group's kernel from the committed rocprofv3
+    counter runs, or None if absent or the kernel source changed since."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))["groups"][group]
+    except Exception:
+        return None
+    if rec.get("source_sha") != source_sha(KERNEL_SOURCES[group]):
+        return None
+    return rec["bytes_per_launch"]
 
 
 def algorithmic_bytes(group, N, ng, es):
@@ -122,7 +144,7 @@ def run(args):
     achieved = abytes / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+                "traffic": measured_traffic(dom), "avg_launch_ms": round(avg_ms, 5),
                 "algorithmic_bytes_per_launch": abytes,
                 "groups_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof32.items()},
                 "fp64_groups_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof64.items()}}
@@ -153,6 +175,15 @@ def run(args):
         "roofline": roofline,
     }
 
+    if args.calibrate_copy:
+        # a plain copy kernel of known size (one FP32 block, read once and
+        # written once) for scaling the FETCH_SIZE / WRITE_SIZE counters
+        tmp = torch.empty_like(U32)
+        for _ in range(3):
+            g32.convert(U32, tmp)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": U32.numel() * 4, "write": U32.numel() * 4}
+        del tmp
     if not args.no_converge:
         out["delta_E"] = converge(args, cfg, R, Z, s, occ, g64, U64, g32, U32, progress)
     if not args.no_cpu_baseline:
@@ -212,6 +243,7 @@ def main():
     ap.add_argument("--converge-seconds", type=float, default=40.0)
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

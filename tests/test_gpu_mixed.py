@@ -1,0 +1,92 @@
+"""Mixed precision (FP32 orbitals and stencil, BF16 first Gram, FP32 second
+Gram and apply, FP64 Cholesky and reductions) against FP64 and the oracle.
+
+Targets stated for the method: energies within 1e-6 Ha of the FP64 result
+after FP64 refinement, orthonormality error <= 1e-10 after refinement.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ks, orth as oorth, algm
+from _common import oracle_system, gpu_system, to_np, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(g, U, tol, max_steps):
+    df = []
+    info = None
+    for k in range(max_steps):
+        info = g.step_(U)
+        df.append(info["df"])
+        if len(df) >= 3 and np.mean(df[-3:]) < tol:
+            return info, k + 1, True
+    return info, max_steps, False
+
+
+def test_mixed_energy_and_orth_match_fp64():
+    cfg = synth.CONFIGS["fp64_48"]
+    so = oracle_system(cfg)
+    W = oorth.orth(synth.orbitals(cfg), so.h)[0]
+    e_o = ks.energy(W, so).E
+    g32 = gpu_system(cfg, "mixed")
+    U32 = g32.new_block(W)
+    e32 = g32.energy(U32)["E"]
+    print(f"[mixed] E oracle {e_o:.12f} mixed {e32:.12f} rel {abs(e32 - e_o) / abs(e_o):.2e}")
+    assert abs(e32 - e_o) < 2e-6 * abs(e_o)
+    X = synth.orbitals(cfg)
+    Ux = g32.new_block(X)
+    err = g32.orthonormalize_(Ux)
+    assert err < 1e-6
+    assert rel(to_np(Ux), oorth.orth(X, so.h)[0]) < 1e-4
+
+
+def test_mixed_then_refined_reaches_fp64_minimum():
+    """fp64_48: mixed steps, FP64 refinement; |E - E_fp64| <= 1e-6 Ha."""
+    import paper_1510_07230_amd as pk
+    cfg = synth.CONFIGS["fp64_48"]
+    so = oracle_system(cfg)
+    W = oorth.orth(synth.orbitals(cfg), so.h)[0]
+    g64 = gpu_system(cfg, "fp64")
+    U64 = g64.new_block(W)
+    i64, k64, c64 = _run(g64, U64, 1e-13, 6000)
+    g32 = gpu_system(cfg, "mixed")
+    U32 = g32.new_block(W)
+    i32, k32, _ = _run(g32, U32, 1e-9, 3000)
+    gr = gpu_system(cfg, "fp64")
+    Ur = gr.new_block()
+    gr.convert(U32, Ur)
+    gr.orthonormalize_(Ur)
+    ir, kr, cr = _run(gr, Ur, 1e-13, 6000)
+    G = gr.gram(Ur)
+    orth_err = float(np.max(np.abs(G - np.eye(cfg.norb))))
+    print(f"[mixed] fp64 {i64['E']:.12f} ({k64} steps, conv {c64}); mixed {i32['E']:.12f} "
+          f"({k32}); refined {ir['E']:.12f} ({kr}, conv {cr}); orth {orth_err:.2e}")
+    assert c64 and cr
+    assert abs(ir["E"] - i64["E"]) <= 1e-6
+    assert orth_err <= 1e-10
+
+
+def test_converged_energy_matches_oracle_small16():
+    cfg = synth.CONFIGS["small16"]
+    so = oracle_system(cfg)
+    A = algm.AlgorithmM(synth.orbitals(cfg), so)
+    A.run(3000, tol=1e-13)
+    g = gpu_system(cfg, "fp64")
+    U = g.new_block(synth.orbitals(cfg))
+    g.orthonormalize_(U)
+    info, k, conv = _run(g, U, 1e-13, 3000)
+    g32 = gpu_system(cfg, "mixed")
+    U32 = g32.new_block(synth.orbitals(cfg))
+    g32.orthonormalize_(U32)
+    i32, _, _ = _run(g32, U32, 1e-9, 3000)
+    gr = gpu_system(cfg, "fp64")
+    Ur = gr.new_block()
+    gr.convert(U32, Ur)
+    gr.orthonormalize_(Ur)
+    ir, _, cr = _run(gr, Ur, 1e-13, 3000)
+    print(f"[conv] oracle {A.E:.12f} gpu {info['E']:.12f} refined {ir['E']:.12f}")
+    assert conv and cr
+    assert abs(info["E"] - A.E) <= 1e-6
+    assert abs(ir["E"] - A.E) <= 1e-6
