@@ -543,7 +543,6 @@ __global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restric
   __shared__ double slot[36 * kTile];
   __shared__ double P[8 * kTile];
   __shared__ double Li[kTile];
-  __shared__ double T[16 * 33];
   __shared__ double sdg[128];
   __shared__ double sred[4];
   __shared__ int sbad;
@@ -571,45 +570,45 @@ __global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restric
   __syncthreads();
   if (t == 0) info[1] = fmax(fmax(sred[0], sred[1]), fmax(sred[2], sred[3]));
   for (int p = 0; p < NT; ++p) {
-    // (a) one wave: [A_pp | I] -> [L_pp^T | L_pp^-1]
+    // (a) one wave: [A_pp | I] -> [L_pp^T | L_pp^-1].  Lane l holds column
+    // c = l % 32 of the 16 x 32 augmented block, rows 2m + l / 32 (m < 8);
+    // pivot, row k and column k travel by cross-lane shuffles.
     if (w == 0) {
       const double *App = slot + tri_slot(p, p) * kTile;
-      for (int e = l; e < 512; e += 64) {
-        const int r = e >> 5, c = e & 31;
-        double v;
-        if (c < 16) v = (c <= r) ? App[r * kTP + c] : App[c * kTP + r];
-        else v = (c - 16 == r) ? 1.0 : 0.0;
-        T[r * 33 + c] = v;
+      const int c = l & 31, hi = l >> 5;
+      double v[8];
+#pragma unroll
+      for (int mm = 0; mm < 8; ++mm) {
+        const int r = 2 * mm + hi;
+        if (c < 16) v[mm] = (c <= r) ? App[r * kTP + c] : App[c * kTP + r];
+        else v[mm] = (c - 16 == r) ? 1.0 : 0.0;
       }
-      __builtin_amdgcn_wave_barrier();
+#pragma unroll
       for (int k = 0; k < 16; ++k) {
-        double piv = T[k * 33 + k];
+        double piv = __shfl(v[k >> 1], 32 * (k & 1) + k, 64);
+        const double rk = __shfl(v[k >> 1], 32 * (k & 1) + c, 64);
+        double ck[8];
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) ck[mm] = __shfl(v[mm], 32 * hi + k, 64);
         if (!((piv > 1e-13 * sdg[16 * p + k]) && isfinite(piv))) {
           if (l == 0) sbad = 1;
           piv = 1.0;
         }
         const double ip = 1.0 / piv, isp = 1.0 / sqrt(piv);
-        double nv[8];
+        const double rki = rk * ip;
 #pragma unroll
         for (int mm = 0; mm < 8; ++mm) {
-          const int e = l + 64 * mm;
-          const int r = e >> 5, c = e & 31;
-          const double v = T[r * 33 + c];
-          if (r == k) nv[mm] = v * isp;
-          else if (r > k) nv[mm] = v - T[r * 33 + k] * T[k * 33 + c] * ip;
-          else nv[mm] = v;
+          const int r = 2 * mm + hi;
+          if (r == k) v[mm] = rk * isp;
+          else if (r > k) v[mm] -= ck[mm] * rki;
         }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int mm = 0; mm < 8; ++mm) {
-          const int e = l + 64 * mm;
-          T[(e >> 5) * 33 + (e & 31)] = nv[mm];
-        }
-        __builtin_amdgcn_wave_barrier();
       }
-      for (int e = l; e < 256; e += 64) {
-        const int r = e >> 4, c = e & 15;
-        Li[r * kTP + c] = (c <= r) ? T[r * 33 + 16 + c] : 0.0;
+      if (c >= 16) {
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) {
+          const int r = 2 * mm + hi;
+          Li[r * kTP + (c - 16)] = (c - 16 <= r) ? v[mm] : 0.0;
+        }
       }
     }
     __syncthreads();
@@ -746,7 +745,8 @@ __global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, 
                                                           i64 kper, double *__restrict__ part,
                                                           const T *__restrict__ HW,
                                                           const double *__restrict__ sig,
-                                                          double tau, T *__restrict__ Wt) {
+                                                          const double *__restrict__ dtau,
+                                                          double tscale, T *__restrict__ Wt) {
   constexpr int ROWS = 16 * NT;
   constexpr int PITCH = KC + 1;
   constexpr int TPR = KC;                      // threads per staged row
@@ -770,6 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, 
   T nxt[PER];
   T nxh[TRIAL ? PER : 1];
   T ca[TRIAL ? PER : 1];
+  const double tau = TRIAL ? dtau[0] * tscale : 0.0;
   if (TRIAL) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
@@ -843,7 +844,9 @@ __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restr
                                                                double *__restrict__ part,
                                                                const float *__restrict__ HW,
                                                                const double *__restrict__ sig,
-                                                               double tau, float *__restrict__ Wt) {
+                                                               const double *__restrict__ dtau,
+                                                               double tscale,
+                                                               float *__restrict__ Wt) {
   constexpr int ROWS = 16 * NT;
   constexpr int PITCH = KC + 4;
   constexpr int TPR = KC;
@@ -863,6 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restr
   float nxt[PER];
   float nxh[TRIAL ? PER : 1];
   float ca[TRIAL ? PER : 1];
+  const double tau = TRIAL ? dtau[0] * tscale : 0.0;
   if (TRIAL) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
@@ -1058,6 +1062,117 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
   }
 }
 
+// First Cholesky-QR pass fused with the second Gram (FP32 orbitals, N <= 128):
+// W1 = X + (L1^-1 - I) X is formed block by block exactly as k_apply_small
+// does, kept in LDS instead of being written out, and its partial Gram
+// <W1^T W1> over the workgroup's blocks is accumulated with FP32 MFMA and
+// flushed into FP64 after every block.  part[blockIdx.x] holds the partial.
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_apply_gram(const float *__restrict__ D,
+                                                       const float *__restrict__ X, int N,
+                                                       i64 ng, double *__restrict__ part) {
+  constexpr int GC = 32;
+  constexpr int ROWS = 16 * NT;
+  constexpr int PITCH = GC + 1;
+  constexpr int RSTEP = kBlock / GC;
+  constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
+  constexpr int NC = GC / 16;
+  __shared__ float xs[ROWS][PITCH];
+  __shared__ float w1s[ROWS][PITCH];
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  float a0[4 * NT], a1[4 * NT];
+  switch (w) {
+    case 0: apply_load_a<float, NT, 0>(D, N, a0, a1, r16, q); break;
+    case 1: apply_load_a<float, NT, 1>(D, N, a0, a1, r16, q); break;
+    case 2: apply_load_a<float, NT, 2>(D, N, a0, a1, r16, q); break;
+    default: apply_load_a<float, NT, 3>(D, N, a0, a1, r16, q); break;
+  }
+  const int jt0 = w, jt1 = 7 - w;
+  f4 gacc[9];
+  double gd[9][4];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    gacc[u] = f4{0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gd[u][r] = 0.0;
+  }
+  const i64 nblk = (ng + GC - 1) / GC;
+  const int col = t % GC, row0 = t / GC;
+  float nxt[PER];
+  auto load = [&](i64 blk) {
+    const i64 g = blk * GC + col;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      nxt[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : 0.0f;
+    }
+  };
+  i64 blk = blockIdx.x;
+  if (blk < nblk) load(blk);
+  for (; blk < nblk; blk += gridDim.x) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      if (row < ROWS) xs[row][col] = nxt[e];
+    }
+    __syncthreads();
+    if (blk + gridDim.x < nblk) load(blk + gridDim.x);
+    f4 acc0[NC], acc1[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      acc0[cc] = f4{0, 0, 0, 0};
+      acc1[cc] = f4{0, 0, 0, 0};
+    }
+    switch (w) {
+      case 0: apply_compute<float, NT, 0, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      case 1: apply_compute<float, NT, 1, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      case 2: apply_compute<float, NT, 2, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      default: apply_compute<float, NT, 3, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+    }
+    // W1 block into LDS (rows beyond N stay zero so they add nothing to the Gram)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int jt = u == 0 ? jt0 : jt1;
+      if (jt >= NT) continue;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * jt + 4 * q + r;
+          const float v = xs[j][16 * cc + r16] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
+          w1s[j][16 * cc + r16] = v;
+        }
+      }
+    }
+    __syncthreads();
+    switch (w) {
+      case 0: gram_chunk<float, NT, 0, GC, PITCH>(w1s, gacc, r16, q); break;
+      case 1: gram_chunk<float, NT, 1, GC, PITCH>(w1s, gacc, r16, q); break;
+      case 2: gram_chunk<float, NT, 2, GC, PITCH>(w1s, gacc, r16, q); break;
+      default: gram_chunk<float, NT, 3, GC, PITCH>(w1s, gacc, r16, q); break;
+    }
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gd[u][r] += (double)gacc[u][r];
+      gacc[u] = f4{0, 0, 0, 0};
+    }
+  }
+  double *outp = part + (i64)blockIdx.x * 128 * 128;
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    int rt, ct;
+    gram_tile_runtime(w, u, rt, ct);
+    if (rt < NT && ct < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        outp[(16 * rt + 4 * q + r) * 128 + 16 * ct + r16] = gd[u][r];
+    }
+  }
+}
+
 // G = dv * sum over splits of the 128 x 128 partial upper triangles; both
 // halves.  Lane = element (coalesced over the 128 x 128 partial), the four
 // waves of a workgroup take every fourth split and combine through LDS.
@@ -1112,17 +1227,20 @@ size_t gram_partial_doubles(int N, int nsplit) {
 template <typename T>
 hipError_t launch_gram_partial(const T *A, int N, i64 ng, int nsplit, double *part,
                                hipStream_t s) {
-  return launch_trial_gram<T>(A, nullptr, nullptr, 0.0, nullptr, N, ng, nsplit, false, part, s);
+  return launch_trial_gram<T>(A, nullptr, nullptr, nullptr, 0.0, nullptr, N, ng, nsplit, false,
+                              part, s);
 }
 
 hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, double *part,
                                     hipStream_t s) {
-  return launch_trial_gram<float>(A, nullptr, nullptr, 0.0, nullptr, N, ng, nsplit, true, part, s);
+  return launch_trial_gram<float>(A, nullptr, nullptr, nullptr, 0.0, nullptr, N, ng, nsplit, true,
+                                  part, s);
 }
 
 template <typename T>
-hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, double tau, T *Wt,
-                             int N, i64 ng, int nsplit, bool bf16, double *part, hipStream_t s) {
+hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const double *dtau,
+                             double tscale, T *Wt, int N, i64 ng, int nsplit, bool bf16,
+                             double *part, hipStream_t s) {
   i64 kper = (ng + nsplit - 1) / nsplit;
   kper = ((kper + 63) / 64) * 64;
   const bool trial = HW != nullptr;
@@ -1135,10 +1253,10 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, double 
 #define POU_GB(K)                                                                          \
   if (trial)                                                                               \
     hipLaunchKernelGGL((k_gram_small_bf16<K, 32, true>), dim3(nsplit), dim3(kBlock), 0, s, Wf, \
-                       N, ng, kper, part, Hf, sig, tau, Wtf);                             \
+                       N, ng, kper, part, Hf, sig, dtau, tscale, Wtf);                             \
   else                                                                                     \
     hipLaunchKernelGGL((k_gram_small_bf16<K, 64, false>), dim3(nsplit), dim3(kBlock), 0, s, Wf, \
-                       N, ng, kper, part, Hf, sig, tau, Wtf)
+                       N, ng, kper, part, Hf, sig, dtau, tscale, Wtf)
       POU_NT_SWITCH(NT, POU_GB)
 #undef POU_GB
       return hipGetLastError();
@@ -1146,10 +1264,10 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, double 
 #define POU_GS(K)                                                                             \
   if (trial)                                                                                  \
     hipLaunchKernelGGL((k_gram_small<T, K, 32, true>), dim3(nsplit), dim3(kBlock), 0, s, W, N, \
-                       ng, kper, part, HW, sig, tau, Wt);                                     \
+                       ng, kper, part, HW, sig, dtau, tscale, Wt);                                     \
   else                                                                                        \
     hipLaunchKernelGGL((k_gram_small<T, K, (sizeof(T) == 4 ? 64 : 32), false>), dim3(nsplit),  \
-                       dim3(kBlock), 0, s, W, N, ng, kper, part, HW, sig, tau, Wt)
+                       dim3(kBlock), 0, s, W, N, ng, kper, part, HW, sig, dtau, tscale, Wt)
     POU_NT_SWITCH(NT, POU_GS)
 #undef POU_GS
     return hipGetLastError();
@@ -1201,6 +1319,18 @@ hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int 
   return hipGetLastError();
 }
 
+hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, int nsplit,
+                             double *part, hipStream_t s) {
+  if (N > 128) return hipErrorInvalidValue;
+  const int NT = (N + 15) / 16;
+#define POU_AG(K)                                                                        \
+  hipLaunchKernelGGL((k_apply_gram<K>), dim3(nsplit), dim3(kBlock), 0, s, D32, X, N, ng, \
+                     part)
+  POU_NT_SWITCH(NT, POU_AG)
+#undef POU_AG
+  return hipGetLastError();
+}
+
 hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
                                   float *D32, int N, hipStream_t s) {
   int blocks = (N * N + kBlock - 1) / kBlock;
@@ -1233,11 +1363,11 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
 }
 
 template hipError_t launch_trial_gram<double>(const double *, const double *, const double *,
-                                              double, double *, int, i64, int, bool, double *,
-                                              hipStream_t);
+                                              const double *, double, double *, int, i64, int,
+                                              bool, double *, hipStream_t);
 template hipError_t launch_trial_gram<float>(const float *, const float *, const double *,
-                                             double, float *, int, i64, int, bool, double *,
-                                             hipStream_t);
+                                             const double *, double, float *, int, i64, int, bool,
+                                             double *, hipStream_t);
 template hipError_t launch_gram_partial<double>(const double *, int, i64, int, double *,
                                                 hipStream_t);
 template hipError_t launch_gram_partial<float>(const float *, int, i64, int, double *,

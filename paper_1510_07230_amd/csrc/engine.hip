@@ -24,9 +24,11 @@ using pou::i64;
 namespace {
 
 struct Report {
-  // device layout of one evaluation report: [sigma N | kin N | e3 | info 2*kMaxPass]
+  // device layout of one evaluation report:
+  // [sigma N | kin N | e3 | orth info 2*kMaxPass | Poisson rr, bb]
   static constexpr int kMaxPass = 4;
-  static int size(int N) { return 2 * N + 3 + 2 * kMaxPass; }
+  static int size(int N) { return 2 * N + 3 + 2 * kMaxPass + 2; }
+  static int rr(int N) { return 2 * N + 3 + 2 * kMaxPass; }
 };
 
 double lambda1(int n, double h, int k) {
@@ -79,6 +81,7 @@ struct pou_ctx {
   double *d_D64 = nullptr;
   float *d_D32 = nullptr;
   double *d_red = nullptr;     // small reduction outputs
+  double *d_scal = nullptr;    // (tau_BB, zz, ss, sy, yy) of the current step
   double *d_rep[2] = {nullptr, nullptr};  // evaluation reports (current, trial)
   void *d_HW = nullptr, *d_HWt = nullptr, *d_Wt = nullptr, *d_W1 = nullptr, *d_W2 = nullptr;
   std::vector<void *> allocs;
@@ -158,6 +161,7 @@ void free_all(pou_ctx *c) {
   c->d_fft0 = c->d_fft1 = nullptr;
   c->d_sc = c->d_part = c->d_gpart = c->d_G = c->d_Minv = c->d_Minv2 = c->d_Mcomb = nullptr;
   c->d_red = nullptr;
+  c->d_scal = nullptr;
   c->d_D64 = nullptr;
   c->d_D32 = nullptr;
   c->d_rep[0] = c->d_rep[1] = nullptr;
@@ -289,10 +293,58 @@ pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxi
   return POU_OK;
 }
 
+// One iteration of conjugate gradients preconditioned by the exact spectral
+// inverse, warm-started from x, without host synchronisation; the final
+// residual and right-hand side norms land in rrbb[0..1] for the caller's check.
+pou_status poisson_async(pou_ctx *c, const double *f, double *x, double *rrbb) {
+  hipStream_t s = c->stream;
+  const i64 ng = c->ng;
+  const int nb = c->nblk_field;
+  const double ih2 = 1.0 / (c->h * c->h);
+  double *sc = c->d_sc;  // [0] rz, [1] -, [2] pq, [3] rr, [4] bb, [5] sum f, [6] sum x
+  KL(POU_K_POISSON, pou::launch_dot2(f, nullptr, c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_neg_lap(x, c->d_cg_q, nullptr, c->n, ih2, nb, s));
+  KL(POU_K_POISSON, pou::launch_cg_rhs_residual(f, sc + 5, c->d_cg_q, c->d_cg_r, c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 2, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_spectral_inverse(c->d_cg_r, c->d_cg_z, c->d_fft0, c->d_fft1,
+                                                 c->d_lam1, c->n, s));
+  KL(POU_K_POISSON, pou::launch_dot2(c->d_cg_r, c->d_cg_z, c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 0, 1, nb, 1, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_cg_update_p(c->d_cg_p, c->d_cg_z, sc + 0, sc + 1, 1, ng, s));
+  KL(POU_K_POISSON, pou::launch_neg_lap(c->d_cg_p, c->d_cg_q, c->d_part, c->n, ih2, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 2, 1, nb, 1, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_cg_update_xr(x, c->d_cg_r, c->d_cg_p, c->d_cg_q, sc + 0, sc + 2,
+                                             c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 1, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_dot2(x, nullptr, c->d_part, ng, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 6, 1, nb, 1, 1.0, s));
+  KL(POU_K_POISSON, pou::launch_remove_mean(x, sc + 6, ng, s));
+  HIPCHK(c, hipMemcpyAsync(rrbb, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return POU_OK;
+}
+
 // ------------------------------------------------------------------ energy
 
+// V_eff, H W and the energy partials of W for the current rho and V_H; the
+// report (sigma, kin, energy sums) lands in rep on the device.
+template <typename T>
+pou_status potentials_and_h(pou_ctx *c, const T *W, T *HWout, double *rep) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  KL(POU_K_XC, pou::launch_xc_veff(c->d_rho, c->d_vh, c->d_vext, c->d_veff,
+                                   sizeof(T) == 4 ? c->d_veff32 : nullptr, c->d_part, c->ng,
+                                   c->p.terms, c->nblk_field, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep + 2 * N, 1, c->nblk_field, 3, c->dv, s));
+  const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
+  KL(POU_K_HAMILTONIAN, pou::launch_hamiltonian<T>(W, veff, HWout, c->d_part, N, c->st, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep, N, c->st.ntile * c->st.nzc, 2, c->dv, s));
+  return POU_OK;
+}
+
 // Evaluate rho (unless already formed), V_H, V_eff, H W and the energy terms
-// of W; report (sigma, kin, energy sums) lands in rep on the device.
+// of W.  With the spectral preconditioner the Hartree solve runs without host
+// synchronisation and its residual is checked when the report is read.
 template <typename T>
 pou_status evaluate(pou_ctx *c, const T *W, T *HWout, double *rep, bool rho_ready,
                     int *cg_iters) {
@@ -300,18 +352,49 @@ pou_status evaluate(pou_ctx *c, const T *W, T *HWout, double *rep, bool rho_read
   const int N = c->N;
   if (!rho_ready) KL(POU_K_DENSITY, pou::launch_density<T>(W, c->d_occ, c->d_rho, N, c->ng, s));
   int it = 0;
-  if (c->p.terms & POU_TERM_HARTREE) {
-    CHK(poisson(c, c->d_rho, c->d_vh, c->p.cg_rtol, c->p.cg_maxit, c->p.cg_precond != 0, &it));
+  double *rrbb = rep + Report::rr(N);
+  if ((c->p.terms & POU_TERM_HARTREE) && c->p.cg_precond != 0) {
+    CHK(poisson_async(c, c->d_rho, c->d_vh, rrbb));
+    it = 1;
+  } else {
+    if (c->p.terms & POU_TERM_HARTREE)
+      CHK(poisson(c, c->d_rho, c->d_vh, c->p.cg_rtol, c->p.cg_maxit, c->p.cg_precond != 0, &it));
+    HIPCHK(c, hipMemsetAsync(rrbb, 0, 2 * sizeof(double), s));
   }
   c->last_cg_iters = it;
   if (cg_iters) *cg_iters = it;
-  KL(POU_K_XC, pou::launch_xc_veff(c->d_rho, c->d_vh, c->d_vext, c->d_veff,
-                                sizeof(T) == 4 ? c->d_veff32 : nullptr, c->d_part, c->ng,
-                                c->p.terms, c->nblk_field, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep + 2 * N, 1, c->nblk_field, 3, c->dv, s));
-  const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
-  KL(POU_K_HAMILTONIAN, pou::launch_hamiltonian<T>(W, veff, HWout, c->d_part, N, c->st, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep, N, c->st.ntile * c->st.nzc, 2, c->dv, s));
+  return potentials_and_h<T>(c, W, HWout, rep);
+}
+
+// evaluate(), then read the report (and the step scalars) to the host; if the
+// one-iteration Hartree solve missed its tolerance, finish it with the checked
+// solver and redo the potentials.
+template <typename T>
+pou_status eval_report(pou_ctx *c, const T *W, T *HWout, double *rep, bool rho_ready,
+                       std::vector<double> &host, double *scal_host, int *cg_iters) {
+  const int N = c->N;
+  int it = 0;
+  CHK(evaluate<T>(c, W, HWout, rep, rho_ready, &it));
+  host.resize(Report::size(N));
+  HIPCHK(c, hipMemcpyAsync(host.data(), rep, sizeof(double) * Report::size(N),
+                           hipMemcpyDeviceToHost, c->stream));
+  if (scal_host)
+    HIPCHK(c, hipMemcpyAsync(scal_host, c->d_scal, 5 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_drain(c);
+  const double rr = host[Report::rr(N)], bb = host[Report::rr(N) + 1];
+  if (!std::isfinite(rr) || !std::isfinite(bb))
+    return fail(c, POU_ERR_NONFINITE, "Poisson right-hand side or residual is not finite");
+  if (rr > c->p.cg_rtol * c->p.cg_rtol * bb) {
+    int more = 0;
+    CHK(poisson(c, c->d_rho, c->d_vh, c->p.cg_rtol, c->p.cg_maxit, true, &more));
+    it += more;
+    c->last_cg_iters = it;
+    CHK(potentials_and_h<T>(c, W, HWout, rep));
+    CHK(sync_read(c, host.data(), rep, sizeof(double) * Report::size(N)));
+  }
+  if (cg_iters) *cg_iters = it;
   return POU_OK;
 }
 
@@ -382,21 +465,28 @@ pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info,
 // is applied once to measure the second Gram, and the product of both factors
 // is applied to Wt in the final pass, which also forms rho.
 template <typename T>
-pou_status trial_orth_fused(pou_ctx *c, const T *W, double tau, double *info) {
+pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info) {
   hipStream_t s = c->stream;
   const bool mixed = sizeof(T) == 4;
   const int passes = c->p.orth_passes;
-  KL(POU_K_GRAM, pou::launch_trial_gram<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt,
-                                           c->N, c->ng, c->nsplit, mixed && passes == 2,
-                                           c->d_gpart, s));
+  KL(POU_K_GRAM, pou::launch_trial_gram<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, tscale,
+                                           (T *)c->d_Wt, c->N, c->ng, c->nsplit,
+                                           mixed && passes == 2, c->d_gpart, s));
   KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
   KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
                                                   info, s));
   if (passes == 2) {
-    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), (const T *)c->d_Wt,
-                                               (T *)c->d_W1, c->N, c->ng, nullptr, nullptr, s));
-    KL(POU_K_GRAM, pou::launch_trial_gram<T>((const T *)c->d_W1, nullptr, nullptr, 0.0, nullptr,
-                                             c->N, c->ng, c->nsplit, false, c->d_gpart, s));
+    if (mixed) {
+      // W1 = Wt L1^-T stays on chip: only its Gram leaves the kernel
+      KL(POU_K_APPLY, pou::launch_apply_gram(c->d_D32, (const float *)c->d_Wt, c->N, c->ng,
+                                             c->nsplit, c->d_gpart, s));
+    } else {
+      KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), (const T *)c->d_Wt,
+                                                 (T *)c->d_W1, c->N, c->ng, nullptr, nullptr, s));
+      KL(POU_K_GRAM, pou::launch_trial_gram<T>((const T *)c->d_W1, nullptr, nullptr, nullptr,
+                                               0.0, nullptr, c->N, c->ng, c->nsplit, false,
+                                               c->d_gpart, s));
+    }
     KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv2, c->d_D32, c->d_D64, c->N,
                                                     info + 2, s));
@@ -411,11 +501,11 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tau, double *info) {
 // ------------------------------------------------------------------ step
 template <typename T>
 pou_status restart(pou_ctx *c, const T *W) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
   int it = 0;
-  CHK(evaluate<T>(c, W, (T *)c->d_HW, c->d_rep[0], false, &it));
   std::vector<double> &r = c->rep_host;
-  r.resize(Report::size(c->N));
-  CHK(sync_read(c, r.data(), c->d_rep[0], sizeof(double) * Report::size(c->N)));
+  CHK(eval_report<T>(c, W, (T *)c->d_HW, c->d_rep[0], false, r, nullptr, &it));
   pou_energy_terms t;
   terms_from_report(c, r.data(), &t);
   if (!std::isfinite(t.E)) return fail(c, POU_ERR_NONFINITE, "energy of U is not finite");
@@ -428,61 +518,51 @@ pou_status restart(pou_ctx *c, const T *W) {
   c->cur_valid = true;
   c->eval_ptr = W;
   c->eval_HU = c->d_HW;
+  // ||Z||^2 of the start and tau_init on the device (no history yet)
+  KL(POU_K_OTHER, pou::launch_zz<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_part, N, c->ng,
+                                    c->nblk_orb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
+  KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, 0, c->p.tau_init, c->d_scal, s));
   return POU_OK;
 }
 
+// One iteration of Algorithm M.  tau_BB and ||Z||^2 of the current iterate
+// live on the device (d_scal); the trial kernels read tau = tau_BB * delta^s
+// from there, and the only host synchronisation per trial is the energy
+// report, which also returns tau_BB and ||Z||^2 for the test of eq. "ene-de".
 template <typename T>
 pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
   hipStream_t s = c->stream;
   const int N = c->N;
   if (W != c->last_U || !c->cur_valid) CHK(restart<T>(c, W));
-  double zz;
-  if (!c->hist) {
-    KL(POU_K_OTHER, pou::launch_zz<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_part, N, c->ng,
-                                c->nblk_orb, s));
-    KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
-    std::vector<double> z(N);
-    CHK(sync_read(c, z.data(), c->d_red, sizeof(double) * N));
-    zz = 0.0;
-    for (double v : z) zz += v;
-  } else {
-    zz = c->zz_next;
-  }
-  // Barzilai-Borwein step (section 3.2): tau1 = ss/|sy|, tau2 = |sy|/yy
-  double tau_bb = c->p.tau_init;
-  if (c->hist) {
-    const double asy = std::fabs(c->sy);
-    const int mode = (c->p.bb_mode == 1 || c->p.bb_mode == 2) ? c->p.bb_mode
-                                                               : ((c->l % 2 == 1) ? 1 : 2);
-    const double t = (mode == 1) ? c->ss / asy : asy / c->yy;
-    if (std::isfinite(t) && t > 0.0) tau_bb = t;
-  }
   const int passes = c->p.orth_passes;
   pou_energy_terms et{};
-  double tau = tau_bb;
+  double tau = 0.0, tau_bb = 0.0, zz = 0.0;
   int s_acc = 0, cg_total = 0;
   bool accepted = false;
   double gram_dev = 0.0;
   std::vector<double> &r = c->rep_host;
-  r.resize(Report::size(N));
+  double scal[5];
   for (int sidx = 0; sidx <= c->p.s_max; ++sidx) {
-    tau = tau_bb * std::pow(c->p.delta, sidx);
+    const double tscale = std::pow(c->p.delta, sidx);
     s_acc = sidx;
     bool rho_done = false;
     double *rep_t = c->d_rep[1];
     if (N <= 128) {
-      CHK(trial_orth_fused<T>(c, W, tau, rep_t + 2 * N + 3));
+      CHK(trial_orth_fused<T>(c, W, tscale, rep_t + 2 * N + 3));
       rho_done = true;
     } else {
-      KL(POU_K_TRIAL, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], tau, (T *)c->d_Wt,
-                                           N, c->ng, s));
+      KL(POU_K_TRIAL, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, tscale,
+                                           (T *)c->d_Wt, N, c->ng, s));
       CHK(orth_passes<T>(c, (const T *)c->d_Wt, (T *)c->d_W2, passes, rep_t + 2 * N + 3, true,
                          &rho_done));
     }
     int it = 0;
-    CHK(evaluate<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, rho_done, &it));
+    CHK(eval_report<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, rho_done, r, scal, &it));
     cg_total += it;
-    CHK(sync_read(c, r.data(), rep_t, sizeof(double) * Report::size(N)));
+    tau_bb = scal[0];
+    zz = scal[1];
+    tau = tau_bb * tscale;
     for (int p = 0; p < passes; ++p)
       if (r[2 * N + 3 + 2 * p] != 0.0)
         return fail(c, POU_ERR_NOT_SPD, "trial Gram matrix is not positive definite (pass " +
@@ -496,24 +576,15 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
       break;
     }
   }
-  // accept: U <- W2 and the dot products for the next BB step
+  // accept: U <- W2, and the dot products and step of the next iteration
   KL(POU_K_COMMIT, pou::launch_commit<T>(W, (const T *)c->d_HW, c->d_rep[0], (const T *)c->d_W2,
-                                  (const T *)c->d_HWt, c->d_rep[1], c->d_part, N, c->ng,
-                                  c->nblk_orb, s));
+                                         (const T *)c->d_HWt, c->d_rep[1], c->d_part, N, c->ng,
+                                         c->nblk_orb, s));
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 4, c->dv, s));
-  std::vector<double> d(4 * N);
-  CHK(sync_read(c, d.data(), c->d_red, sizeof(double) * 4 * N));
-  double ss = 0, sy = 0, yy = 0, zn = 0;
-  for (int i = 0; i < N; ++i) {
-    ss += d[0 * N + i];
-    sy += d[1 * N + i];
-    yy += d[2 * N + i];
-    zn += d[3 * N + i];
-  }
-  c->ss = ss;
-  c->sy = sy;
-  c->yy = yy;
-  c->zz_next = zn;
+  const int lnext = c->l + 1;
+  const int mode = (c->p.bb_mode == 1 || c->p.bb_mode == 2) ? c->p.bb_mode
+                                                             : ((lnext % 2 == 1) ? 1 : 2);
+  KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, mode, c->p.tau_init, c->d_scal, s));
   std::swap(c->d_HW, c->d_HWt);
   std::swap(c->d_rep[0], c->d_rep[1]);
   const double E_old = c->E;
@@ -538,7 +609,7 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
     info->Q = c->Q;
     info->gram_dev = gram_dev;
   }
-  c->l += 1;
+  c->l = lnext;
   return POU_OK;
 }
 
@@ -590,10 +661,8 @@ pou_status energy_impl(pou_ctx *c, const T *U, pou_energy_terms *out) {
   T *hu = (T *)((c->last_U == U && c->cur_valid) ? c->d_HW : c->d_HWt);
   double *rep = (hu == (T *)c->d_HW) ? c->d_rep[0] : c->d_rep[1];
   int it = 0;
-  CHK(evaluate<T>(c, U, hu, rep, false, &it));
   std::vector<double> &r = c->rep_host;
-  r.resize(Report::size(c->N));
-  CHK(sync_read(c, r.data(), rep, sizeof(double) * Report::size(c->N)));
+  CHK(eval_report<T>(c, U, hu, rep, false, r, nullptr, &it));
   pou_energy_terms t;
   terms_from_report(c, r.data(), &t);
   t.cg_iters = it;
@@ -809,6 +878,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_Minv2, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Mcomb, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_red, sizeof(double) * (size_t)std::max(4 * norb, 4 * std::max(1, natoms)) + 64));
+  CHK(dalloc(c, &c->d_scal, sizeof(double) * 8));
   CHK(dalloc(c, &c->d_rep[0], sizeof(double) * Report::size(norb)));
   CHK(dalloc(c, &c->d_rep[1], sizeof(double) * Report::size(norb)));
   CHK(dalloc(c, &c->d_HW, bbytes));

@@ -358,7 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_p(double *__restrict__ p,
                                                         const double *__restrict__ num,
                                                         const double *__restrict__ den,
                                                         int first, i64 ng) {
-  const double beta = first ? 0.0 : num[0] / den[0];
+  double beta = first ? 0.0 : num[0] / den[0];
+  if (!isfinite(beta)) beta = 0.0;  // exact zero residual
   for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
        g += (i64)gridDim.x * blockDim.x)
     p[g] = z[g] + beta * (first ? 0.0 : p[g]);
@@ -372,7 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_xr(double *__restrict__ x,
                                                          const double *__restrict__ den,
                                                          double *__restrict__ part, i64 ng) {
   __shared__ double red[4];
-  const double alpha = num[0] / den[0];
+  double alpha = num[0] / den[0];
+  if (!isfinite(alpha)) alpha = 0.0;  // exact zero residual
   double acc = 0.0;
   for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
        g += (i64)gridDim.x * blockDim.x) {
@@ -676,9 +678,11 @@ __global__ __launch_bounds__(kBlock) void k_ion_forces(const double *__restrict_
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_trial(const T *__restrict__ W,
                                                   const T *__restrict__ HW,
-                                                  const double *__restrict__ sig, double tau,
+                                                  const double *__restrict__ sig,
+                                                  const double *__restrict__ dtau, double tscale,
                                                   T *__restrict__ Wt, i64 ng) {
   const int orb = blockIdx.y;
+  const double tau = dtau[0] * tscale;
   const double a = 1.0 + tau * sig[orb];
   const T ta = (T)a, tt = (T)tau;
   const i64 off = (i64)orb * ng;
@@ -773,6 +777,38 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const T *__restrict__ x, i
        g += (i64)gridDim.x * blockDim.x)
     bad |= !isfinite((double)x[g]);
   if (bad) flag[0] = 1;
+}
+
+// Barzilai-Borwein step from the per-orbital dot products (section 3.2):
+// tau1 = tr<S^T S> / |tr<S^T Y>|, tau2 = |tr<S^T Y>| / tr<Y^T Y>; mode 0 means
+// no history (tau_init).  red holds [k * N + i] per-orbital sums (k = 0 ss,
+// 1 sy, 2 yy, 3 zz) or, in mode 0, zz per orbital in [i].  Summed in orbital
+// order by one thread.  out = (tau_BB, zz, ss, sy, yy).
+__global__ void k_bb_tau(const double *__restrict__ red, int N, int mode, double tau_init,
+                         double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double ss = 0.0, sy = 0.0, yy = 0.0, zz = 0.0;
+  if (mode == 0) {
+    for (int i = 0; i < N; ++i) zz += red[i];
+  } else {
+    for (int i = 0; i < N; ++i) {
+      ss += red[i];
+      sy += red[N + i];
+      yy += red[2 * N + i];
+      zz += red[3 * N + i];
+    }
+  }
+  double tau = tau_init;
+  if (mode != 0) {
+    const double asy = fabs(sy);
+    const double t = (mode == 1) ? ss / asy : asy / yy;
+    if (isfinite(t) && t > 0.0) tau = t;
+  }
+  out[0] = tau;
+  out[1] = zz;
+  out[2] = ss;
+  out[3] = sy;
+  out[4] = yy;
 }
 
 inline int grid_for(i64 work, int cap = 4096) {
@@ -888,10 +924,10 @@ hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, do
 }
 
 template <typename T>
-hipError_t launch_trial(const T *W, const T *HW, const double *sig, double tau, T *Wt, int N,
-                        i64 ng, hipStream_t s) {
+hipError_t launch_trial(const T *W, const T *HW, const double *sig, const double *dtau,
+                        double tscale, T *Wt, int N, i64 ng, hipStream_t s) {
   dim3 grid(grid_for(ng, 1024), N);
-  hipLaunchKernelGGL(k_trial<T>, grid, dim3(kBlock), 0, s, W, HW, sig, tau, Wt, ng);
+  hipLaunchKernelGGL(k_trial<T>, grid, dim3(kBlock), 0, s, W, HW, sig, dtau, tscale, Wt, ng);
   return hipGetLastError();
 }
 
@@ -935,6 +971,12 @@ hipError_t launch_nonfinite(const T *x, i64 count, int *flag, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_bb_tau(const double *red, int N, int mode, double tau_init, double *out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_bb_tau, dim3(1), dim3(64), 0, s, red, N, mode, tau_init, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ion_density(const double *atoms, int M, double *rho_ion, int n, double L,
                               hipStream_t s) {
   const i64 ng = (i64)n * n * n;
@@ -955,8 +997,8 @@ hipError_t launch_ion_forces(const double *atoms, int M, const double *vh, doubl
                                             const StencilArgs &, hipStream_t);              \
   template hipError_t launch_density<T>(const T *, const double *, double *, int, i64,      \
                                         hipStream_t);                                       \
-  template hipError_t launch_trial<T>(const T *, const T *, const double *, double, T *,    \
-                                      int, i64, hipStream_t);                               \
+  template hipError_t launch_trial<T>(const T *, const T *, const double *, const double *, \
+                                      double, T *, int, i64, hipStream_t);                  \
   template hipError_t launch_commit<T>(T *, const T *, const double *, const T *, const T *, \
                                        const double *, double *, int, i64, int,             \
                                        hipStream_t);                                        \

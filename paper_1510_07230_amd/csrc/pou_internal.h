@@ -130,10 +130,13 @@ hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, do
                                    const double *lam1, int n, hipStream_t s);
 
 // ---- block elementwise / reductions
-// Wt = (1 + tau sig_i) W - tau HW
+// Wt = (1 + tau sig_i) W - tau HW with tau = dtau[0] * tscale
 template <typename T>
-hipError_t launch_trial(const T *W, const T *HW, const double *sig, double tau, T *Wt,
-                        int N, i64 ng, hipStream_t s);
+hipError_t launch_trial(const T *W, const T *HW, const double *sig, const double *dtau,
+                        double tscale, T *Wt, int N, i64 ng, hipStream_t s);
+// Barzilai-Borwein step on the device: out = (tau_BB, zz, ss, sy, yy)
+hipError_t launch_bb_tau(const double *red, int N, int mode, double tau_init, double *out,
+                         hipStream_t s);
 // accept: U <- Wn; partials per (orbital, block) of
 //   s.s, s.y, y.y, zn.zn  with s = Wn - W, y = zn - z,
 //   z = HW - sig W, zn = HWn - sign Wn
@@ -175,8 +178,13 @@ hipError_t launch_gram_partial_bf16(const float *A, int N, i64 ng, int nsplit, d
 // and its partial Gram accumulated (N <= 128; HW == nullptr: plain Gram of W).
 // bf16: products of BF16-rounded FP32 values (first Cholesky-QR pass).
 template <typename T>
-hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, double tau, T *Wt,
-                             int N, i64 ng, int nsplit, bool bf16, double *part, hipStream_t s);
+hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const double *dtau,
+                             double tscale, T *Wt, int N, i64 ng, int nsplit, bool bf16,
+                             double *part, hipStream_t s);
+// First Cholesky-QR pass fused with the second Gram (FP32, N <= 128): the
+// partial Gram of X + D32 X over nsplit workgroups into part (nothing else written)
+hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, int nsplit,
+                             double *part, hipStream_t s);
 // M = A B (lower-triangular), D64 = M - I, D32 = (float) D64
 hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
                                   float *D32, int N, hipStream_t s);
