@@ -535,22 +535,30 @@ __device__ inline void tile_mma(const double *X, const double *Y, int ytrans, do
 // then the trailing update A_ij -= L_ip L_jp^T and the eliminations
 // B_ij -= L_ip B_pj.  A tile slot holds A_ij until its panel is processed and
 // B_ij afterwards.  Padding rows beyond N carry an identity diagonal.
-__global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restrict__ G, int N,
-                                                         double *__restrict__ Minv,
-                                                         float *__restrict__ D32,
-                                                         double *__restrict__ D64,
-                                                         double *__restrict__ info) {
-  __shared__ double slot[36 * kTile];
-  __shared__ double P[8 * kTile];
+//
+// LDS_TILES: tiles live in LDS (N <= 128, ~100 KB); otherwise in the global
+// workspace ws (L2-resident; N <= 512: 528 tile slots plus 32 panel tiles).
+template <bool LDS_TILES, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict__ G, int N,
+                                                       double *__restrict__ Minv,
+                                                       float *__restrict__ D32,
+                                                       double *__restrict__ D64,
+                                                       double *__restrict__ info,
+                                                       double *__restrict__ ws) {
+  __shared__ double slot_s[LDS_TILES ? 36 * kTile : 1];
+  __shared__ double P_s[LDS_TILES ? 8 * kTile : 1];
   __shared__ double Li[kTile];
-  __shared__ double sdg[128];
-  __shared__ double sred[4];
+  __shared__ double sdg[512];
+  __shared__ double sred[NTHR / 64];
   __shared__ int sbad;
+  double *slot = LDS_TILES ? slot_s : ws;
+  double *P = LDS_TILES ? P_s : ws + 528 * kTile;
+  constexpr int NW = NTHR / 64;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int NT = (N + 15) / 16;
   const int NP = 16 * NT;
   double m = 0.0;
-  for (int e = t; e < NP * NP; e += kBlock) {
+  for (int e = t; e < NP * NP; e += NTHR) {
     const int r = e / NP, c = e % NP;
     if (c > r) continue;
     double v;
@@ -563,12 +571,16 @@ __global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restric
     }
     slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] = v;
   }
-  for (int r = t; r < NP; r += kBlock) sdg[r] = (r < N) ? G[(i64)r * N + r] : 1.0;
+  for (int r = t; r < NP; r += NTHR) sdg[r] = (r < N) ? G[(i64)r * N + r] : 1.0;
   m = wave_max(m);
   if (l == 0) sred[w] = m;
   if (t == 0) sbad = 0;
   __syncthreads();
-  if (t == 0) info[1] = fmax(fmax(sred[0], sred[1]), fmax(sred[2], sred[3]));
+  if (t == 0) {
+    double mx = 0.0;
+    for (int k = 0; k < NW; ++k) mx = fmax(mx, sred[k]);
+    info[1] = mx;
+  }
   for (int p = 0; p < NT; ++p) {
     // (a) one wave: [A_pp | I] -> [L_pp^T | L_pp^-1].  Lane l holds column
     // c = l % 32 of the 16 x 32 augmented block, rows 2m + l / 32 (m < 8);
@@ -616,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restric
     {
       const int nb = NT - 1 - p;  // panel tiles
       const int nd = p;           // B row tiles
-      for (int task = w; task < nb + nd + 1; task += 4) {
+      for (int task = w; task < nb + nd + 1; task += NW) {
         if (task < nb) {
           const int i = p + 1 + task;
           tile_mma(slot + tri_slot(i, p) * kTile, Li, 1, 1.0, nullptr, P + i * kTile, l);
@@ -637,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restric
       const int m1 = NT - 1 - p;
       const int nc = m1 * (m1 + 1) / 2;
       const int ne = m1 * (p + 1);
-      for (int task = w; task < nc + ne; task += 4) {
+      for (int task = w; task < nc + ne; task += NW) {
         if (task < nc) {
           // decode (i, j) with p < j <= i
           int a = task, ii = 0;
@@ -656,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_chol_blocked(const double *__restric
     }
     __syncthreads();
   }
-  for (int e = t; e < N * N; e += kBlock) {
+  for (int e = t; e < N * N; e += NTHR) {
     const int r = e / N, c = e % N;
     const double v = (c <= r) ? slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] : 0.0;
     Minv[e] = v;
@@ -1218,6 +1230,8 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
     default: MACRO(8); break;     \
   }
 
+size_t chol_workspace_doubles(int N) { return N <= 128 ? 0 : (size_t)(528 + 32) * kTile; }
+
 size_t gram_partial_doubles(int N, int nsplit) {
   if (N <= 128) return (size_t)nsplit * 128 * 128;
   const int nb = (N + kGB - 1) / kGB;
@@ -1302,9 +1316,15 @@ hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, 
 }
 
 hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
-                                   double *info, hipStream_t s) {
+                                   double *info, double *ws, hipStream_t s) {
   if (N <= 128) {
-    hipLaunchKernelGGL(k_chol_blocked, dim3(1), dim3(kBlock), 0, s, G, N, Minv, D32, D64, info);
+    hipLaunchKernelGGL((k_chol_blocked<true, kBlock>), dim3(1), dim3(kBlock), 0, s, G, N, Minv, D32,
+                       D64, info, ws);
+    return hipGetLastError();
+  }
+  if (N <= 512 && ws != nullptr) {
+    hipLaunchKernelGGL((k_chol_blocked<false, 1024>), dim3(1), dim3(1024), 0, s, G, N, Minv, D32,
+                       D64, info, ws);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, G, Minv, N, info);

@@ -80,6 +80,7 @@ struct pou_ctx {
   double *d_G = nullptr, *d_Minv = nullptr, *d_Minv2 = nullptr, *d_Mcomb = nullptr;
   double *d_D64 = nullptr;
   float *d_D32 = nullptr;
+  double *d_cholws = nullptr;  // blocked Cholesky tiles when N > 128
   double *d_red = nullptr;     // small reduction outputs
   double *d_scal = nullptr;    // (tau_BB, zz, ss, sy, yy) of the current step
   double *d_rep[2] = {nullptr, nullptr};  // evaluation reports (current, trial)
@@ -164,6 +165,7 @@ void free_all(pou_ctx *c) {
   c->d_scal = nullptr;
   c->d_D64 = nullptr;
   c->d_D32 = nullptr;
+  c->d_cholws = nullptr;
   c->d_rep[0] = c->d_rep[1] = nullptr;
   c->d_HW = c->d_HWt = c->d_Wt = c->d_W1 = c->d_W2 = nullptr;
   c->have_system = false;
@@ -448,7 +450,7 @@ pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info,
   for (int p = 0; p < passes; ++p) {
     CHK(gram<T>(c, cur, mixed && p == 0));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
-                                                       info + 2 * p, s));
+                                                       info + 2 * p, c->d_cholws, s));
     const bool last = (p == passes - 1);
     T *dst = last ? out : (T *)c->d_W1;
     if (cur == dst) return fail(c, POU_ERR_ARG, "internal: aliasing orth buffers");
@@ -474,7 +476,7 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
                                            mixed && passes == 2, c->d_gpart, s));
   KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
   KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
-                                                  info, s));
+                                                  info, c->d_cholws, s));
   if (passes == 2) {
     if (mixed) {
       // W1 = Wt L1^-T stays on chip: only its Gram leaves the kernel
@@ -489,7 +491,7 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
     }
     KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv2, c->d_D32, c->d_D64, c->N,
-                                                    info + 2, s));
+                                                    info + 2, c->d_cholws, s));
     KL(POU_K_CHOLESKY, pou::launch_combine_factors(c->d_Minv2, c->d_Minv, c->d_Mcomb, c->d_D64,
                                                    c->d_D32, c->N, s));
   }
@@ -626,7 +628,7 @@ pou_status orthonormalize_impl(pou_ctx *c, T *U, double *orth_err) {
   for (int p = 0; p < 3 && !done; ++p) {
     CHK(gram<T>(c, src, false));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
-                                                       c->d_red, s));
+                                                       c->d_red, c->d_cholws, s));
     KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), src, dst, c->N, c->ng, nullptr, nullptr, s));
     CHK(sync_read(c, info, c->d_red, sizeof(info)));
     if (!std::isfinite(info[1])) return fail(c, POU_ERR_NONFINITE, "U is not finite");
@@ -873,6 +875,8 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_gpart, sizeof(double) * pou::gram_partial_doubles(norb, c->nsplit)));
   CHK(dalloc(c, &c->d_D64, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_D32, sizeof(float) * (size_t)norb * norb));
+  if (pou::chol_workspace_doubles(norb) > 0)
+    CHK(dalloc(c, &c->d_cholws, sizeof(double) * pou::chol_workspace_doubles(norb)));
   CHK(dalloc(c, &c->d_G, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Minv, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Minv2, sizeof(double) * (size_t)norb * norb));

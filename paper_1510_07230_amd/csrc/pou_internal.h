@@ -195,7 +195,9 @@ hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, 
 // FP32 (written for N <= 128).  info[0] = 1.0 if G is not numerically SPD
 // else 0.0; info[1] = max |G - I|.  Single workgroup.
 hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
-                                   double *info, hipStream_t s);
+                                   double *info, double *ws, hipStream_t s);
+// doubles of global workspace the blocked Cholesky needs for N > 128
+size_t chol_workspace_doubles(int N);
 // doubles needed by the Gram partial buffer
 size_t gram_partial_doubles(int N, int nsplit);
 // C = A * B for lower-triangular N x N matrices (FP64)

@@ -231,3 +231,39 @@ def test_state_error_before_set_system():
     t = pk.EnergyTerms()
     assert L.pou_energy(h, ctypes.c_void_p(1), ctypes.byref(t)) == -2
     assert L.pou_destroy(h) == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_more_than_128_orbitals(prec):
+    """N = 144 (> 128): generic Gram/apply path and the workspace Cholesky."""
+    cfg = synth.custom("n144", 20, 9.0, 6, 2.0, 0.5, 144, min_sep=1.5, seed_id=80)
+    print(f"[n144] {prec}", flush=True)
+    so = oracle_system(cfg)
+    X = synth.orbitals(cfg)
+    W_o, _ = oorth.orth(X, so.h)
+    p = algm.Params()
+    p.tau_init = 1.0 / algm.lambda_max_kinetic(so.h)
+    g = gpu_system(cfg, prec, tau_init=p.tau_init)
+    U = g.new_block(X)
+    err = g.orthonormalize_(U)
+    if prec == "fp64":
+        assert err < 1e-12
+        assert rel(to_np(U), W_o) < 1e-9
+        A = algm.AlgorithmM(W_o, so, p, orthonormalize_start=False)
+        U = g.new_block(W_o)
+        for k in range(3):
+            r = A.step()
+            info = g.step_(U)
+            assert info["s"] == r.s
+            assert abs(info["E"] - r.E) < 1e-9 * max(1, abs(r.E)), (k, info["E"], r.E)
+    else:
+        assert err < 1e-5
+        e0 = ks.energy(W_o, so).E
+        U = g.new_block(W_o)
+        assert abs(g.energy(U)["E"] - e0) < 2e-6 * abs(e0)
+        E_prev = None
+        for k in range(5):
+            info = g.step_(U)
+            assert np.isfinite(info["E"])
+        G = g.gram(U)
+        assert np.max(np.abs(G - np.eye(cfg.norb))) < 1e-5
