@@ -86,8 +86,10 @@ typedef struct {
   int orth_passes;  /* Cholesky-QR passes per trial (1 or 2); 0 -> 1 for FP64, 2 for MIXED */
   double cg_rtol;   /* Poisson CG relative residual target; <= 0 -> 1e-12 (FP64) */
   int cg_maxit;     /* Poisson CG iteration cap; <= 0 -> 2000                    */
-  int cg_precond;   /* 0: plain CG; 1: CG preconditioned by the exact spectral
-                       inverse of -Lap (FFT), which converges in 1-2 iterations */
+  int cg_precond;   /* 0: plain CG; 1: solve with the exact spectral inverse of
+                       -Lap (FFT), check the residual against cg_rtol and, only
+                       if it is missed, finish with CG preconditioned by that
+                       inverse */
   unsigned terms;   /* energy-term mask, POU_TERM_*                              */
 } pou_params;
 
@@ -190,15 +192,22 @@ enum {
   POU_K_GRAM = 4,        /* Gram partial contraction (MFMA)            */
   POU_K_CHOLESKY = 5,    /* Cholesky + triangular inverse, Gram reduce */
   POU_K_APPLY = 6,       /* W <- L^-1 W (MFMA), fused density          */
-  POU_K_TRIAL = 7,       /* W - tau Z                                  */
+  POU_K_TRIAL = 7,       /* W - tau Z, fused with its first Gram        */
   POU_K_COMMIT = 8,      /* accept + Barzilai-Borwein dot products     */
   POU_K_OTHER = 9,       /* reductions and the remaining small kernels */
-  POU_K_COUNT = 10
+  POU_K_APPLY_GRAM = 10, /* first Cholesky-QR apply fused with the
+                            second Gram (mixed precision, two passes)   */
+  POU_K_COUNT = 11
 };
 
-/* Turn event timing on (1) or off (0); turning it on clears the totals.
-   Each timed launch is bracketed by two hipEventRecord calls. */
-pou_status pou_profile_enable(pou_ctx *ctx, int enable);
+#define POU_PROFILE_ALL ((1u << POU_K_COUNT) - 1u)
+
+/* Time the kernel groups whose bit (1u << POU_K_*) is set in group_mask;
+   0 turns timing off, POU_PROFILE_ALL times every group.  Synchronises the
+   stream and clears the totals.  Each timed launch is bracketed by two
+   hipEventRecord calls, which add a few microseconds of idle time between
+   launches: leave groups that are not being measured untimed. */
+pou_status pou_profile_enable(pou_ctx *ctx, unsigned group_mask);
 
 /* Total milliseconds and number of launches of kernel group `group` since
    profiling was enabled (host outputs). */

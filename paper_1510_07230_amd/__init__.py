@@ -76,12 +76,12 @@ _SIGNATURES = {
     "pou_gram": (_i, [_vp, _vp, _dp]),
     "pou_convert": (_i, [_vp, _vp, _i, _vp, _i, ctypes.c_longlong]),
     "pou_reset_history": (_i, [_vp]),
-    "pou_profile_enable": (_i, [_vp, _i]),
+    "pou_profile_enable": (_i, [_vp, ctypes.c_uint]),
     "pou_profile_read": (_i, [_vp, _i, _dp, ctypes.POINTER(ctypes.c_longlong)]),
 }
 
 KERNEL_GROUPS = ["hamiltonian", "density", "xc", "poisson", "gram", "cholesky", "apply",
-                 "trial", "commit", "other"]
+                 "trial", "commit", "other", "apply_gram"]
 
 
 def header_symbols(path=HEADER):
@@ -258,9 +258,18 @@ class System:
     def reset_history(self):
         self._check(lib().pou_reset_history(self._h))
 
-    def profile(self, enable=True):
-        """Turn per-kernel-group HIP event timing on/off (on clears the totals)."""
-        self._check(lib().pou_profile_enable(self._h, 1 if enable else 0))
+    def profile(self, enable=True, groups=None):
+        """Turn per-kernel-group HIP event timing on/off (on clears the totals).
+
+        groups: names from KERNEL_GROUPS to time (default: all of them).  Each
+        timed launch adds event records to the stream, so time only the groups
+        being measured when the step time matters."""
+        mask = 0
+        if enable:
+            names = KERNEL_GROUPS if groups is None else groups
+            for name in names:
+                mask |= 1 << KERNEL_GROUPS.index(name)
+        self._check(lib().pou_profile_enable(self._h, mask))
 
     def profile_read(self):
         """{group: (total_ms, launches)} since profiling was enabled."""

@@ -6,6 +6,8 @@
 #include "pou_internal.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <utility>
 
 namespace pou {
@@ -276,22 +278,44 @@ __global__ __launch_bounds__(1024) void k_cholesky_inverse(double *__restrict__ 
   if (t == 0) info[0] = sbad ? 1.0 : 0.0;
 }
 
-// M = A B for lower-triangular A, B, with D64 = M - I and D32 its FP32 copy
-// (the combined factor of two Cholesky-QR passes).
-__global__ __launch_bounds__(kBlock) void k_combine_factors(const double *__restrict__ A,
-                                                            const double *__restrict__ B,
-                                                            double *__restrict__ M,
-                                                            double *__restrict__ D64,
-                                                            float *__restrict__ D32, int N) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
-    const int i = e / N, j = e % N;
-    double sacc = 0.0;
-    for (int k = j; k <= i; ++k) sacc += A[(i64)i * N + k] * B[(i64)k * N + j];
-    const double v = (j <= i) ? sacc : 0.0;
-    M[e] = v;
-    const double d = v - (i == j ? 1.0 : 0.0);
-    D64[e] = d;
-    D32[e] = (float)d;
+// M = A B for lower-triangular A, B (N x N, zeros above the diagonal), with
+// D64 = M - I and D32 its FP32 copy: the combined factor of two Cholesky-QR
+// passes.  One wave per 16 x 16 output tile (I, J) on FP64 MFMA, summing the
+// tile products A_IK B_KJ for J <= K <= I; tiles above the diagonal are zero.
+__global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict__ A,
+                                                        const double *__restrict__ B,
+                                                        double *__restrict__ M,
+                                                        double *__restrict__ D64,
+                                                        float *__restrict__ D32, int N) {
+  const int NT = (N + 15) / 16;
+  const int I = blockIdx.x / NT, J = blockIdx.x % NT;
+  const int l = threadIdx.x, r16 = l & 15, q = l >> 4;
+  d4 acc = d4{0, 0, 0, 0};
+  if (J <= I) {
+    const int ia = 16 * I + r16, jb = 16 * J + r16;
+    for (int K = J; K <= I; ++K) {
+      double a[4], b[4];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 16 * K + 4 * s4 + q;
+        a[s4] = (ia < N && k < N) ? A[(i64)ia * N + k] : 0.0;
+        b[s4] = (jb < N && k < N) ? B[(i64)k * N + jb] : 0.0;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) acc = mfma(a[s4], b[s4], acc);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * I + out_row<double>(q, r), j = 16 * J + r16;
+    if (i < N && j < N) {
+      const double v = (j <= i) ? acc[r] : 0.0;
+      const i64 e = (i64)i * N + j;
+      M[e] = v;
+      const double d = v - (i == j ? 1.0 : 0.0);
+      D64[e] = d;
+      D32[e] = (float)d;
+    }
   }
 }
 
@@ -558,18 +582,32 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
   const int NT = (N + 15) / 16;
   const int NP = 16 * NT;
   double m = 0.0;
-  for (int e = t; e < NP * NP; e += NTHR) {
-    const int r = e / NP, c = e % NP;
-    if (c > r) continue;
-    double v;
-    if (r < N && c < N) {
-      v = G[(i64)r * N + c];
-      const double d = v - (r == c ? 1.0 : 0.0);
-      m = isfinite(d) ? fmax(m, fabs(d)) : INFINITY;
-    } else {
-      v = (r == c) ? 1.0 : 0.0;
+  // the lower triangle of G into the tile slots, 16 independent loads per
+  // thread in flight at a time
+  constexpr int kLB = 16;
+  for (int e0 = t; e0 < NP * NP; e0 += NTHR * kLB) {
+    double v[kLB];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * NTHR;
+      const int r = e / NP, c = e - (e / NP) * NP;
+      v[u] = (e < NP * NP && c <= r && r < N) ? G[(i64)r * N + c] : 0.0;
     }
-    slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] = v;
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * NTHR;
+      const int r = e / NP, c = e - (e / NP) * NP;
+      if (e < NP * NP && c <= r) {
+        double x = v[u];
+        if (r < N) {
+          const double d = x - (r == c ? 1.0 : 0.0);
+          m = isfinite(d) ? fmax(m, fabs(d)) : INFINITY;
+        } else {
+          x = (r == c) ? 1.0 : 0.0;
+        }
+        slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] = x;
+      }
+    }
   }
   for (int r = t; r < NP; r += NTHR) sdg[r] = (r < N) ? G[(i64)r * N + r] : 1.0;
   m = wave_max(m);
@@ -976,7 +1014,10 @@ __device__ inline void apply_compute(const T (*xs)[PITCH], const T (&a0)[4 * NT]
 // triangular, N <= 128).  The D fragments of a wave's two row tiles stay in
 // registers for the whole launch; the workgroup walks over blocks of GC grid
 // points, staging each X block in LDS while the next one is loaded into
-// registers.  Optional fused density rho[g] = sum_j occ_j out[j][g]^2.
+// registers.  Optional fused density rho[g] = sum_j occ_j out[j][g]^2 (FP64
+// accumulation): each wave leaves its partial of a block in LDS and the
+// partials are summed after the next block's first barrier, so the density
+// adds no barrier of its own.
 template <typename T, int NT, int GC>
 __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
                                                         const T *__restrict__ X,
@@ -989,7 +1030,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
   constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
   constexpr int NC = GC / 16;
   __shared__ T xs[ROWS][PITCH];
-  __shared__ double srho[4][GC];
+  __shared__ double srho[2][4][GC];
   typedef typename AccOf<T>::type Acc;
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
@@ -1001,6 +1042,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
     default: apply_load_a<T, NT, 3>(D, N, a0, a1, r16, q); break;
   }
   const int jt0 = w, jt1 = 7 - w;
+  // occupations of the rows this lane writes
+  double occv[2][4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int jt = u == 0 ? jt0 : jt1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * jt + out_row<T>(q, r);
+      occv[u][r] = (rho != nullptr && jt < NT && j < N) ? occ[j] : 0.0;
+    }
+  }
   const i64 nblk = (ng + GC - 1) / GC;
   const int col = t % GC, row0 = t / GC;
   T nxt[PER];
@@ -1012,10 +1064,21 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
       nxt[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : (T)0;
     }
   };
+  // density of the previous block still to be summed from srho[buf ^ 1]
+  auto flush_rho = [&](i64 pblk, int pbuf) {
+    if (t < GC) {
+      const i64 g = pblk * GC + t;
+      if (g < ng)
+        rho[g] = srho[pbuf][0][t] + srho[pbuf][1][t] + srho[pbuf][2][t] + srho[pbuf][3][t];
+    }
+  };
+  i64 pending = -1;
+  int buf = 0;
   i64 blk = blockIdx.x;
   if (blk < nblk) load(blk);
   for (; blk < nblk; blk += gridDim.x) {
     __syncthreads();
+    if (rho != nullptr && pending >= 0) flush_rho(pending, buf ^ 1);
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
@@ -1052,7 +1115,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
           if (j < N && g < ng) {
             const T v = xs[j][16 * cc + r16] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
             out[(i64)j * ng + g] = v;
-            if (rho) rp[cc] += occ[j] * (double)v * (double)v;
+            rp[cc] += occv[u][r] * ((double)v * (double)v);
           }
         }
       }
@@ -1063,14 +1126,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
         double v = rp[cc];
         v += __shfl_xor(v, 16, 64);
         v += __shfl_xor(v, 32, 64);
-        if (q == 0) srho[w][16 * cc + r16] = v;
+        if (q == 0) srho[buf][w][16 * cc + r16] = v;
       }
-      __syncthreads();
-      if (t < GC) {
-        const i64 g = g0 + t;
-        if (g < ng) rho[g] = srho[0][t] + srho[1][t] + srho[2][t] + srho[3][t];
-      }
+      pending = blk;
+      buf ^= 1;
     }
+  }
+  if (rho != nullptr && pending >= 0) {
+    __syncthreads();
+    flush_rho(pending, buf ^ 1);
   }
 }
 
@@ -1195,6 +1259,8 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int e = blockIdx.x * 64 + lane;  // element of the 128 x 128 partial
+  // the partials hold the upper triangle only: skip ranges entirely below it
+  if (((blockIdx.x * 64) & 127) + 63 < (int)((blockIdx.x * 64) >> 7)) return;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   int sp = w;
   for (; sp + 12 < nsplit; sp += 16) {
@@ -1216,6 +1282,31 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
   }
 }
 
+// Workgroups of `kernel` (kBlock threads, static LDS only) that are resident
+// on the current device at once: the grid of a kernel that walks its work in
+// a grid-stride loop.  Cached per kernel and device.
+int resident_workgroups(const void *kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 512;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kernel, dev});
+  if (it != cache.end()) return it->second;
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 512;
+  }
+  const int g = std::max(1, per) * std::max(1, cus);
+  cache[{kernel, dev}] = g;
+  return g;
+}
+
 }  // namespace
 
 #define POU_NT_SWITCH(NTV, MACRO) \
@@ -1229,6 +1320,27 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
     case 7: MACRO(7); break;      \
     default: MACRO(8); break;     \
   }
+
+int gram_split(int N, bool fp32) {
+  if (N > 128) return 0;
+  const int NT = (N + 15) / 16;
+  int g = 1 << 30;
+  auto take = [&](const void *k) { g = std::min(g, resident_workgroups(k)); };
+#define POU_GSPLIT(K)                                                         \
+  if (fp32) {                                                                 \
+    take((const void *)k_gram_small_bf16<K, 32, true>);                       \
+    take((const void *)k_gram_small_bf16<K, 64, false>);                      \
+    take((const void *)k_gram_small<float, K, 32, true>);                     \
+    take((const void *)k_gram_small<float, K, 64, false>);                    \
+    take((const void *)k_apply_gram<K>);                                      \
+  } else {                                                                    \
+    take((const void *)k_gram_small<double, K, 32, true>);                    \
+    take((const void *)k_gram_small<double, K, 32, false>);                   \
+  }
+  POU_NT_SWITCH(NT, POU_GSPLIT)
+#undef POU_GSPLIT
+  return std::max(256, std::min(g, 1024));
+}
 
 size_t chol_workspace_doubles(int N) { return N <= 128 ? 0 : (size_t)(528 + 32) * kTile; }
 
@@ -1353,9 +1465,9 @@ hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, in
 
 hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
                                   float *D32, int N, hipStream_t s) {
-  int blocks = (N * N + kBlock - 1) / kBlock;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_combine_factors, dim3(blocks), dim3(kBlock), 0, s, A, B, M, D64, D32, N);
+  if (N > 512) return hipErrorInvalidValue;
+  const int NT = (N + 15) / 16;
+  hipLaunchKernelGGL(k_combine_factors, dim3(NT * NT), dim3(64), 0, s, A, B, M, D64, D32, N);
   return hipGetLastError();
 }
 
@@ -1366,10 +1478,13 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
     const int NT = (N + 15) / 16;
     constexpr int GC = sizeof(T) == 4 ? 32 : 16;
     i64 nblk = (ng + GC - 1) / GC;
-    const int grid = (int)std::min<i64>(nblk, 512);
 #define POU_APPLY_SMALL(K)                                                                  \
-  hipLaunchKernelGGL((k_apply_small<T, K, GC>), dim3(grid), dim3(kBlock), 0, s, D, X, out, N, \
-                     ng, occ, rho)
+  {                                                                                         \
+    const int grid = (int)std::min<i64>(                                                    \
+        nblk, resident_workgroups((const void *)k_apply_small<T, K, GC>));                  \
+    hipLaunchKernelGGL((k_apply_small<T, K, GC>), dim3(grid), dim3(kBlock), 0, s, D, X, out, \
+                       N, ng, occ, rho);                                                    \
+  }
     POU_NT_SWITCH(NT, POU_APPLY_SMALL)
 #undef POU_APPLY_SMALL
     return hipGetLastError();

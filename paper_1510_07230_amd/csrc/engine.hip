@@ -101,7 +101,7 @@ struct pou_ctx {
   std::vector<double> rep_host;
 
   // event timing
-  bool prof = false;
+  unsigned prof_mask = 0;  // kernel groups timed (bit k for group k)
   double prof_ms[POU_K_COUNT] = {};
   long long prof_n[POU_K_COUNT] = {};
   struct Pending { int tag; hipEvent_t a, b; };
@@ -193,14 +193,14 @@ hipEvent_t pool_get(pou_ctx *c) {
 }
 
 void prof_begin(pou_ctx *c, int tag) {
-  if (!c->prof) return;
+  if (!((c->prof_mask >> tag) & 1u)) return;
   c->cur_tag = tag;
   c->cur_a = pool_get(c);
   if (c->cur_a) (void)hipEventRecord(c->cur_a, c->stream);
 }
 
 void prof_end(pou_ctx *c) {
-  if (!c->prof || c->cur_tag < 0 || !c->cur_a) return;
+  if (c->cur_tag < 0 || !c->cur_a) return;
   hipEvent_t b = pool_get(c);
   if (b) {
     (void)hipEventRecord(b, c->stream);
@@ -264,7 +264,7 @@ pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxi
     const double *z = c->d_cg_r;
     if (precond) {
       KL(POU_K_POISSON, pou::launch_spectral_inverse(c->d_cg_r, c->d_cg_z, c->d_fft0, c->d_fft1,
-                                             c->d_lam1, c->n, s));
+                                             c->d_lam1, c->n, 1.0, s));
       z = c->d_cg_z;
     }
     KL(POU_K_POISSON, pou::launch_dot2(c->d_cg_r, z, c->d_part, ng, nb, s));
@@ -295,34 +295,23 @@ pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxi
   return POU_OK;
 }
 
-// One iteration of conjugate gradients preconditioned by the exact spectral
-// inverse, warm-started from x, without host synchronisation; the final
-// residual and right-hand side norms land in rrbb[0..1] for the caller's check.
+// Hartree solve without host synchronisation: x = 4 pi (-Lap)^+ (f - mean f)
+// through the spectral inverse of the FD8 operator (the FFT zeroes the mean
+// mode), then the residual of -Lap x = 4 pi (f - mean f) is measured; its
+// r.r and b.b land in rrbb[0..1] for the caller's check.
 pou_status poisson_async(pou_ctx *c, const double *f, double *x, double *rrbb) {
   hipStream_t s = c->stream;
   const i64 ng = c->ng;
   const int nb = c->nblk_field;
   const double ih2 = 1.0 / (c->h * c->h);
-  double *sc = c->d_sc;  // [0] rz, [1] -, [2] pq, [3] rr, [4] bb, [5] sum f, [6] sum x
+  double *sc = c->d_sc;  // [5] sum f
+  const double fourpi = 12.566370614359172954;
+  KL(POU_K_POISSON, pou::launch_spectral_inverse(f, x, c->d_fft0, c->d_fft1, c->d_lam1, c->n,
+                                                 fourpi, s));
   KL(POU_K_POISSON, pou::launch_dot2(f, nullptr, c->d_part, ng, nb, s));
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
-  KL(POU_K_POISSON, pou::launch_neg_lap(x, c->d_cg_q, nullptr, c->n, ih2, nb, s));
-  KL(POU_K_POISSON, pou::launch_cg_rhs_residual(f, sc + 5, c->d_cg_q, c->d_cg_r, c->d_part, ng, nb, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 2, 1.0, s));
-  KL(POU_K_POISSON, pou::launch_spectral_inverse(c->d_cg_r, c->d_cg_z, c->d_fft0, c->d_fft1,
-                                                 c->d_lam1, c->n, s));
-  KL(POU_K_POISSON, pou::launch_dot2(c->d_cg_r, c->d_cg_z, c->d_part, ng, nb, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 0, 1, nb, 1, 1.0, s));
-  KL(POU_K_POISSON, pou::launch_cg_update_p(c->d_cg_p, c->d_cg_z, sc + 0, sc + 1, 1, ng, s));
-  KL(POU_K_POISSON, pou::launch_neg_lap(c->d_cg_p, c->d_cg_q, c->d_part, c->n, ih2, nb, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 2, 1, nb, 1, 1.0, s));
-  KL(POU_K_POISSON, pou::launch_cg_update_xr(x, c->d_cg_r, c->d_cg_p, c->d_cg_q, sc + 0, sc + 2,
-                                             c->d_part, ng, nb, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 3, 1, nb, 1, 1.0, s));
-  KL(POU_K_POISSON, pou::launch_dot2(x, nullptr, c->d_part, ng, nb, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 6, 1, nb, 1, 1.0, s));
-  KL(POU_K_POISSON, pou::launch_remove_mean(x, sc + 6, ng, s));
-  HIPCHK(c, hipMemcpyAsync(rrbb, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  KL(POU_K_POISSON, pou::launch_poisson_residual(x, f, sc + 5, c->d_part, c->n, ih2, nb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rrbb, 1, nb, 2, 1.0, s));
   return POU_OK;
 }
 
@@ -471,7 +460,7 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
   hipStream_t s = c->stream;
   const bool mixed = sizeof(T) == 4;
   const int passes = c->p.orth_passes;
-  KL(POU_K_GRAM, pou::launch_trial_gram<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, tscale,
+  KL(POU_K_TRIAL, pou::launch_trial_gram<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, tscale,
                                            (T *)c->d_Wt, c->N, c->ng, c->nsplit,
                                            mixed && passes == 2, c->d_gpart, s));
   KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
@@ -480,7 +469,7 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
   if (passes == 2) {
     if (mixed) {
       // W1 = Wt L1^-T stays on chip: only its Gram leaves the kernel
-      KL(POU_K_APPLY, pou::launch_apply_gram(c->d_D32, (const float *)c->d_Wt, c->N, c->ng,
+      KL(POU_K_APPLY_GRAM, pou::launch_apply_gram(c->d_D32, (const float *)c->d_Wt, c->N, c->ng,
                                              c->nsplit, c->d_gpart, s));
     } else {
       KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), (const T *)c->d_Wt,
@@ -848,7 +837,9 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   const int nb64 = (norb + 63) / 64;
   c->npairs = nb64 * (nb64 + 1) / 2;
   c->nsplit = (int)std::max<i64>(
-      1, std::min<i64>(norb <= 128 ? 512 : std::max(1, 1024 / c->npairs), (ng + 31) / 32));
+      1, std::min<i64>(norb <= 128 ? pou::gram_split(norb, c->es == 4)
+                                   : std::max(1, 1024 / c->npairs),
+                       (ng + 31) / 32));
 
   const size_t fbytes = sizeof(double) * (size_t)ng;
   const size_t bbytes = c->es * (size_t)ng * norb;
@@ -1009,12 +1000,12 @@ pou_status pou_convert(pou_ctx *c, const void *src, int src_prec, void *dst, int
   return POU_OK;
 }
 
-pou_status pou_profile_enable(pou_ctx *c, int enable) {
+pou_status pou_profile_enable(pou_ctx *c, unsigned group_mask) {
   if (!c) return POU_ERR_ARG;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   prof_drain(c);
-  c->prof = enable != 0;
+  c->prof_mask = group_mask & POU_PROFILE_ALL;
   for (int k = 0; k < POU_K_COUNT; ++k) {
     c->prof_ms[k] = 0.0;
     c->prof_n[k] = 0;

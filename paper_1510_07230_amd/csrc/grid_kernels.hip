@@ -279,32 +279,43 @@ __global__ __launch_bounds__(kBlock) void k_segment_sum(const double *__restrict
 
 // ----------------------------------------------------------------- Poisson
 
+// -Lap p at point g = (z*n + y)*n + x of a periodic FP64 field; c0 = p[g].
+// Indices are 32-bit (n <= 1024 keeps n^3 below 2^31).
+__device__ inline double neg_lap_at(const double *__restrict__ p, unsigned g, int n,
+                                    double inv_h2, double &c0) {
+  const unsigned un = (unsigned)n;
+  const unsigned yz = g / un;
+  const int x = (int)(g - yz * un);
+  const int z = (int)(yz / un);
+  const int y = (int)(yz - (unsigned)z * un);
+  const unsigned row = g - (unsigned)x;            // (z*n + y)*n
+  const unsigned plane = (unsigned)z * un * un;    // z*n*n
+  const unsigned nn = un * un;
+  const double c[5] = {0.0, FD8::c1, FD8::c2, FD8::c3, FD8::c4};
+  c0 = p[g];
+  double lap = 0.0;
+#pragma unroll
+  for (int m = 1; m <= kRad; ++m) {
+    const double dx = (p[row + wrap(x + m, n)] - c0) + (p[row + wrap(x - m, n)] - c0);
+    const double dy = (p[plane + (unsigned)wrap(y + m, n) * un + x] - c0) +
+                      (p[plane + (unsigned)wrap(y - m, n) * un + x] - c0);
+    const double dz = (p[(unsigned)wrap(z + m, n) * nn + (g - plane)] - c0) +
+                      (p[(unsigned)wrap(z - m, n) * nn + (g - plane)] - c0);
+    lap += c[m] * ((dx + dy) + dz);
+  }
+  return -lap * inv_h2;
+}
+
 __global__ __launch_bounds__(kBlock) void k_neg_lap(const double *__restrict__ p,
                                                     double *__restrict__ q,
                                                     double *__restrict__ part, int n,
                                                     double inv_h2) {
   __shared__ double red[4];
-  const i64 ng = (i64)n * n * n;
-  const double c[5] = {0.0, FD8::c1, FD8::c2, FD8::c3, FD8::c4};
+  const unsigned ng = (unsigned)n * n * n;
   double acc = 0.0;
-  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
-       g += (i64)gridDim.x * blockDim.x) {
-    const int x = (int)(g % n);
-    const int y = (int)((g / n) % n);
-    const int z = (int)(g / ((i64)n * n));
-    const double c0 = p[g];
-    double lap = 0.0;
-#pragma unroll
-    for (int m = 1; m <= kRad; ++m) {
-      const double dx = (p[((i64)z * n + y) * n + wrap(x + m, n)] - c0) +
-                        (p[((i64)z * n + y) * n + wrap(x - m, n)] - c0);
-      const double dy = (p[((i64)z * n + wrap(y + m, n)) * n + x] - c0) +
-                        (p[((i64)z * n + wrap(y - m, n)) * n + x] - c0);
-      const double dz = (p[((i64)wrap(z + m, n) * n + y) * n + x] - c0) +
-                        (p[((i64)wrap(z - m, n) * n + y) * n + x] - c0);
-      lap += c[m] * ((dx + dy) + dz);
-    }
-    const double v = -lap * inv_h2;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
+    double c0;
+    const double v = neg_lap_at(p, g, n, inv_h2, c0);
     q[g] = v;
     acc += c0 * v;
   }
@@ -312,6 +323,33 @@ __global__ __launch_bounds__(kBlock) void k_neg_lap(const double *__restrict__ p
     double v[1] = {acc};
     block_sum<1>(v, red);
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+  }
+}
+
+// Residual of the Hartree equation -Lap x = 4 pi (rho - mean rho) without
+// storing it: partials of (r.r, b.b) per block into part[2*block + k].
+__global__ __launch_bounds__(kBlock) void k_poisson_residual(const double *__restrict__ x,
+                                                             const double *__restrict__ rho,
+                                                             const double *__restrict__ dsum,
+                                                             double *__restrict__ part, int n,
+                                                             double inv_h2) {
+  __shared__ double red[4 * 2];
+  const unsigned ng = (unsigned)n * n * n;
+  const double mean = dsum[0] / (double)ng;
+  const double fourpi = 12.566370614359172954;
+  double a0 = 0.0, a1 = 0.0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
+    double c0;
+    const double b = fourpi * (rho[g] - mean);
+    const double rr = b - neg_lap_at(x, g, n, inv_h2, c0);
+    a0 += rr * rr;
+    a1 += b * b;
+  }
+  double v[2] = {a0, a1};
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = v[1];
   }
 }
 
@@ -782,22 +820,28 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const T *__restrict__ x, i
 // Barzilai-Borwein step from the per-orbital dot products (section 3.2):
 // tau1 = tr<S^T S> / |tr<S^T Y>|, tau2 = |tr<S^T Y>| / tr<Y^T Y>; mode 0 means
 // no history (tau_init).  red holds [k * N + i] per-orbital sums (k = 0 ss,
-// 1 sy, 2 yy, 3 zz) or, in mode 0, zz per orbital in [i].  Summed in orbital
-// order by one thread.  out = (tau_BB, zz, ss, sy, yy).
-__global__ void k_bb_tau(const double *__restrict__ red, int N, int mode, double tau_init,
-                         double *__restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// 1 sy, 2 yy, 3 zz) or, in mode 0, zz per orbital in [i].  One wave, fixed
+// summation order.  out = (tau_BB, zz, ss, sy, yy).
+__global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, int N, int mode,
+                                                double tau_init, double *__restrict__ out) {
+  const int l = threadIdx.x;
   double ss = 0.0, sy = 0.0, yy = 0.0, zz = 0.0;
-  if (mode == 0) {
-    for (int i = 0; i < N; ++i) zz += red[i];
-  } else {
-    for (int i = 0; i < N; ++i) {
+  // lane l sums orbitals l, l + 64, ...; the wave then combines in a fixed order
+  for (int i = l; i < N; i += 64) {
+    if (mode == 0) {
+      zz += red[i];
+    } else {
       ss += red[i];
       sy += red[N + i];
       yy += red[2 * N + i];
       zz += red[3 * N + i];
     }
   }
+  ss = wave_sum(ss);
+  sy = wave_sum(sy);
+  yy = wave_sum(yy);
+  zz = wave_sum(zz);
+  if (l != 0) return;
   double tau = tau_init;
   if (mode != 0) {
     const double asy = fabs(sy);
@@ -861,6 +905,13 @@ hipError_t launch_neg_lap(const double *p, double *q, double *part, int n, doubl
   return hipGetLastError();
 }
 
+hipError_t launch_poisson_residual(const double *x, const double *rho, const double *dsum,
+                                  double *part, int n, double inv_h2, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_poisson_residual, dim3(nblk), dim3(kBlock), 0, s, x, rho, dsum, part, n,
+                     inv_h2);
+  return hipGetLastError();
+}
+
 hipError_t launch_cg_rhs_residual(const double *rho, const double *dsum, const double *q,
                                   double *r, double *part, i64 ng, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_rhs_residual, dim3(nblk), dim3(kBlock), 0, s, rho, dsum, q, r, part,
@@ -900,7 +951,7 @@ hipError_t launch_remove_mean(double *x, const double *dsum, i64 ng, hipStream_t
 }
 
 hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, double2 *w1,
-                                   const double *lam1, int n, hipStream_t s) {
+                                   const double *lam1, int n, double scale, hipStream_t s) {
   const Radices f = factorize(n);
   int lb = 1024 / n;  // two LDS buffers of lb*n complex doubles: at most 32 KiB
   if (lb < 1) lb = 1;
@@ -908,7 +959,7 @@ hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, do
   const size_t lds = (size_t)2 * lb * n * sizeof(double2);
   const int groups = (n + lb - 1) / lb;
   const dim3 grid(groups * n), block(kBlock);
-  const double invn3 = 1.0 / ((double)n * n * n);
+  const double invn3 = scale / ((double)n * n * n);
   // x forward (real in) -> y forward -> z forward, divide, z inverse -> y inverse -> x inverse
   hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)r, (void *)w0, n, 0, lb, 1, f,
                      lam1, 1.0);

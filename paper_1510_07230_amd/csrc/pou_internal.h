@@ -126,8 +126,11 @@ hipError_t launch_scale(double *x, double a, i64 ng, hipStream_t s);
 // dst = src - mean(src) with mean from dmean (used to fix the gauge)
 hipError_t launch_remove_mean(double *x, const double *dmean, i64 ng, hipStream_t s);
 // Spectral inverse of -Lap: out = (-Lap)^+ r (zero mean), via 3-D FFT.
+// out = scale * (-Lap)^+ r by FFT (zero mean), exact for the FD8 operator.
 hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, double2 *w1,
-                                   const double *lam1, int n, hipStream_t s);
+                                   const double *lam1, int n, double scale, hipStream_t s);
+hipError_t launch_poisson_residual(const double *x, const double *rho, const double *dsum,
+                                   double *part, int n, double inv_h2, int nblk, hipStream_t s);
 
 // ---- block elementwise / reductions
 // Wt = (1 + tau sig_i) W - tau HW with tau = dtau[0] * tscale
@@ -200,6 +203,9 @@ hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *
 size_t chol_workspace_doubles(int N);
 // doubles needed by the Gram partial buffer
 size_t gram_partial_doubles(int N, int nsplit);
+// Number of K splits (workgroups) of the N <= 128 Gram kernels: as many as are
+// resident on the device at once, clamped to [256, 1024]; 0 for N > 128.
+int gram_split(int N, bool fp32);
 // C = A * B for lower-triangular N x N matrices (FP64)
 hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int N,
                                hipStream_t s);
