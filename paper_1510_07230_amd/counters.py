@@ -1,15 +1,45 @@
 """Summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of bench.py.
 
-Usage: python -m paper_1510_07230_amd.counters FETCH_CSV WRITE_CSV BLOCK_BYTES
+Usage:
+  python -m paper_1510_07230_amd.counters FETCH_CSV WRITE_CSV BLOCK_BYTES \\
+      [--json OUT.json] [--md OUT.md] [--norb N --n n]
+
 BLOCK_BYTES is the size of the plain copy (k_convert<float,float>) that the
---calibrate-copy run performs: it reads and writes BLOCK_BYTES once, which
-scales the counters to bytes.  Prints per-kernel KiB per dispatch, the scale
-factors and the scaled HBM bytes per launch.
+--calibrate-copy run of bench.py performs: it reads and writes BLOCK_BYTES
+once, which scales the counters (KiB per dispatch) to bytes.  The JSON holds,
+per kernel group of the mixed-precision step, the scaled HBM bytes of one
+launch, the algorithmic bytes and a hash of the kernel's source file, so a
+reader can tell whether the figures still describe the current kernel.
 """
+import argparse
 import csv
+import hashlib
 import json
+import os
 import sys
 from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# kernel group -> (kernel-name fragment of the mixed step, source file)
+GROUP_KERNELS = {
+    "trial": ("k_gram_small_bf16<8, 32, true>", "dense_kernels.hip"),
+    "apply_gram": ("k_apply_gram<8>", "dense_kernels.hip"),
+    "apply": ("k_apply_small<float, 8, 32>", "dense_kernels.hip"),
+    "hamiltonian": ("k_hamiltonian<float>", "grid_kernels.hip"),
+    "commit": ("k_commit<float>", "grid_kernels.hip"),
+}
+
+
+def algorithmic_bytes(group, N, ng, es=4):
+    B = N * ng * es
+    return {"trial": 3 * B, "apply_gram": B, "apply": 2 * B + 8 * ng,
+            "hamiltonian": 2 * B + es * ng, "commit": 5 * B}[group]
+
+
+def source_sha(name):
+    path = os.path.join(HERE, "csrc", name)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
 def per_kernel(path):
@@ -19,21 +49,90 @@ def per_kernel(path):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
-def main():
-    fetch = per_kernel(sys.argv[1])
-    write = per_kernel(sys.argv[2])
-    block = float(sys.argv[3])
+def short(name):
+    for pre in ("void pou::(anonymous namespace)::", "pou::(anonymous namespace)::"):
+        if name.startswith(pre):
+            name = ("void " if pre.startswith("void") else "") + name[len(pre):]
+    return name[:80] + ("..." if len(name) > 80 else "")
+
+
+def summarise(fetch_csv, write_csv, block, N, n):
+    fetch = per_kernel(fetch_csv)
+    write = per_kernel(write_csv)
     copy = [k for k in fetch if "k_convert<float, float>" in k][0]
     sf = block / (fetch[copy][0] * 1024.0)
     sw = block / (write[copy][0] * 1024.0)
-    out = {"copy_kernel": copy, "copy_fetch_kib": fetch[copy][0], "copy_write_kib": write[copy][0],
-           "scale_fetch": sf, "scale_write": sw, "kernels": {}}
-    for k in sorted(fetch, key=lambda k: -fetch[k][0]):
+    kernels = {}
+    for k in fetch:
         f = fetch[k][0]
         w = write.get(k, (0.0, 0))[0]
-        out["kernels"][k] = {"fetch_kib": f, "write_kib": w, "dispatches": fetch[k][1],
-                             "hbm_bytes": f * 1024 * sf + w * 1024 * sw}
-    json.dump(out, sys.stdout, indent=1)
+        kernels[k] = {"fetch_kib": f, "write_kib": w, "dispatches": fetch[k][1],
+                      "hbm_bytes": f * 1024 * sf + w * 1024 * sw}
+    ng = n ** 3
+    groups = {}
+    for g, (frag, src) in GROUP_KERNELS.items():
+        hits = [k for k in kernels if frag in k]
+        if not hits:
+            continue
+        rec = kernels[hits[0]]
+        alg = algorithmic_bytes(g, N, ng)
+        groups[g] = {"kernel": frag, "fetch_kib_per_dispatch": round(rec["fetch_kib"], 1),
+                     "write_kib_per_dispatch": round(rec["write_kib"], 1),
+                     "bytes_per_launch": int(round(rec["hbm_bytes"])),
+                     "algorithmic_bytes": alg,
+                     "ratio_to_algorithmic": round(rec["hbm_bytes"] / alg, 3),
+                     "source_file": src, "source_sha": source_sha(src)}
+    calib = {"copy_kernel": short(copy), "block_bytes": block,
+             "copy_fetch_kib": fetch[copy][0], "copy_write_kib": write[copy][0],
+             "scale_fetch": sf, "scale_write": sw}
+    return {"calibration": calib, "groups": groups, "kernels": kernels}
+
+
+def markdown(res, cmds):
+    c = res["calibration"]
+    out = ["# HBM traffic per launch from FETCH_SIZE / WRITE_SIZE (mixed96, mixed precision)", "",
+           "Two counter runs, one counter each, then scaled by the counts of a plain copy "
+           "kernel of known size:", ""]
+    out += ["    " + x for x in cmds]
+    out += ["", f"Copy calibration (k_convert<float,float>, {c['block_bytes']:,} bytes read and "
+                f"written): FETCH_SIZE {c['copy_fetch_kib']:.0f} KiB -> scale {c['scale_fetch']:.4f}; "
+                f"WRITE_SIZE {c['copy_write_kib']:.0f} KiB -> scale {c['scale_write']:.4f}.", "",
+            "| group | kernel | FETCH KiB | WRITE KiB | HBM bytes/launch | algorithmic | ratio |",
+            "|---|---|---:|---:|---:|---:|---:|"]
+    for g, r in res["groups"].items():
+        out.append(f"| {g} | `{r['kernel']}` | {r['fetch_kib_per_dispatch']:.0f} | "
+                   f"{r['write_kib_per_dispatch']:.0f} | {r['bytes_per_launch']:,} | "
+                   f"{r['algorithmic_bytes']:,} | {r['ratio_to_algorithmic']} |")
+    out += ["", "All kernels (scaled HBM MB per dispatch):", "", "| kernel | dispatches | MB |",
+            "|---|---:|---:|"]
+    for k, r in sorted(res["kernels"].items(), key=lambda kv: -kv[1]["hbm_bytes"]):
+        out.append(f"| `{short(k)}` | {r['dispatches']} | {r['hbm_bytes'] / 1e6:.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("fetch")
+    ap.add_argument("write")
+    ap.add_argument("block", type=float)
+    ap.add_argument("--json")
+    ap.add_argument("--md")
+    ap.add_argument("--norb", type=int, default=128)
+    ap.add_argument("--n", type=int, default=96)
+    a = ap.parse_args()
+    res = summarise(a.fetch, a.write, a.block, a.norb, a.n)
+    cmds = [
+        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/full/fetch -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
+        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/full/write -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
+        f"python -m paper_1510_07230_amd.counters fetch/run_counter_collection.csv write/run_counter_collection.csv {int(a.block)} --json profiles/traffic_mixed96.json --md profiles/traffic_mixed96.md",
+    ]
+    if a.json:
+        rec = {"_commands": cmds, "calibration": res["calibration"], "groups": res["groups"]}
+        json.dump(rec, open(a.json, "w"), indent=1)
+    if a.md:
+        open(a.md, "w").write(markdown(res, cmds))
+    if not a.json and not a.md:
+        json.dump(res, sys.stdout, indent=1)
 
 
 if __name__ == "__main__":

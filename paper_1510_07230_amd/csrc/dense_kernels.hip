@@ -1138,11 +1138,88 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
   }
 }
 
+// Transposed form of apply_compute: the MFMA operands are swapped, so that
+// acc[cc][r] holds (D X)^T, i.e. orbital 16*jt + lane%16 at grid point
+// 16*cc + 4*(lane/16) + r: four consecutive points of one orbital per lane.
+template <int NT, int W, int GC, int PITCH>
+__device__ inline void apply_compute_t(const float (*xs)[PITCH], const float (&a0)[4 * NT],
+                                       const float (&a1)[4 * NT], f4 (&acc0)[GC / 16],
+                                       f4 (&acc1)[GC / 16], int r16, int q) {
+  constexpr int jt0 = W, jt1 = 7 - W;
+  constexpr int ke0 = jt0 < NT ? 4 * (jt0 + 1) : 0;
+  constexpr int ke1 = jt1 < NT ? 4 * (jt1 + 1) : 0;
+  constexpr int ke = ke0 > ke1 ? ke0 : ke1;
+#pragma unroll
+  for (int ks = 0; ks < ke; ++ks) {
+    float b[GC / 16];
+#pragma unroll
+    for (int cc = 0; cc < GC / 16; ++cc) b[cc] = xs[4 * ks + q][16 * cc + r16];
+    if (ks < ke0) {
+#pragma unroll
+      for (int cc = 0; cc < GC / 16; ++cc) acc0[cc] = mfma(b[cc], a0[ks], acc0[cc]);
+    }
+    if (ks < ke1) {
+#pragma unroll
+      for (int cc = 0; cc < GC / 16; ++cc) acc1[cc] = mfma(b[cc], a1[ks], acc1[cc]);
+    }
+  }
+}
+
+// Gram tiles of wave W over one 32-point chunk of W1 held in LDS as two BF16
+// pieces, W1 = hi + lo (hi = bf16(W1), lo = bf16(W1 - hi)).  Each tile sums
+// the four products lo lo^T, hi lo^T, lo hi^T, hi hi^T in FP32 on BF16 MFMA
+// (exact products, FP32 accumulation), which leaves only the rounding of lo
+// (2^-18 relative) and the FP32 sums; it is flushed into FP64 per chunk.
+// Tiles are visited column tile by column tile (ct = W .. 7), each with row
+// tiles W and, once ct >= 7 - W, 7 - W (the GramTile ownership).
+template <int NT, int W, int PB>
+__device__ inline void gram_chunk_split(const __bf16 (*hs)[PB], const __bf16 (*ls)[PB],
+                                        double (&gd)[9][4], int r16, int q) {
+  constexpr int nfirst = 8 - W;
+  bf8 rh0 = bf8{}, rl0 = bf8{}, rh1 = bf8{}, rl1 = bf8{};
+  if (W < NT) {
+    rh0 = *(const bf8 *)&hs[16 * W + r16][8 * q];
+    rl0 = *(const bf8 *)&ls[16 * W + r16][8 * q];
+  }
+  if (7 - W < NT) {
+    rh1 = *(const bf8 *)&hs[16 * (7 - W) + r16][8 * q];
+    rl1 = *(const bf8 *)&ls[16 * (7 - W) + r16][8 * q];
+  }
+#pragma unroll
+  for (int ct = W; ct < 8; ++ct) {
+    if (ct >= NT) continue;
+    const bf8 ch = *(const bf8 *)&hs[16 * ct + r16][8 * q];
+    const bf8 cl = *(const bf8 *)&ls[16 * ct + r16][8 * q];
+    {
+      f4 c = f4{0, 0, 0, 0};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl0, cl, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh0, cl, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl0, ch, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh0, ch, c, 0, 0, 0);
+      const int u = ct - W;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gd[u][r] += (double)c[r];
+    }
+    if (ct >= 7 - W && 7 - W < NT) {
+      f4 c = f4{0, 0, 0, 0};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl1, cl, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh1, cl, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl1, ch, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh1, ch, c, 0, 0, 0);
+      const int u = nfirst + (ct - (7 - W));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gd[u][r] += (double)c[r];
+    }
+  }
+}
+
 // First Cholesky-QR pass fused with the second Gram (FP32 orbitals, N <= 128):
-// W1 = X + (L1^-1 - I) X is formed block by block exactly as k_apply_small
-// does, kept in LDS instead of being written out, and its partial Gram
-// <W1^T W1> over the workgroup's blocks is accumulated with FP32 MFMA and
-// flushed into FP64 after every block.  part[blockIdx.x] holds the partial.
+// W1 = X + (L1^-1 - I) X is formed block by block on FP32 MFMA as in
+// k_apply_small (with the operands swapped, so each lane ends up with four
+// consecutive grid points of one orbital), kept on chip as its BF16 hi/lo
+// pieces, and its partial Gram <W1^T W1> over the workgroup's blocks is
+// accumulated by gram_chunk_split (FP32-accurate) and flushed into FP64 after
+// every block.  part[blockIdx.x] holds the partial.
 template <int NT>
 __global__ __launch_bounds__(kBlock) void k_apply_gram(const float *__restrict__ D,
                                                        const float *__restrict__ X, int N,
@@ -1150,11 +1227,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_gram(const float *__restrict__
   constexpr int GC = 32;
   constexpr int ROWS = 16 * NT;
   constexpr int PITCH = GC + 1;
+  constexpr int PB = GC + 8;  // BF16 row pitch: 80 bytes keeps 16-byte fragment reads aligned
   constexpr int RSTEP = kBlock / GC;
   constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
   constexpr int NC = GC / 16;
   __shared__ float xs[ROWS][PITCH];
-  __shared__ float w1s[ROWS][PITCH];
+  __shared__ __attribute__((aligned(16))) __bf16 hs[ROWS][PB];
+  __shared__ __attribute__((aligned(16))) __bf16 ls[ROWS][PB];
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
   float a0[4 * NT], a1[4 * NT];
@@ -1165,14 +1244,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_gram(const float *__restrict__
     default: apply_load_a<float, NT, 3>(D, N, a0, a1, r16, q); break;
   }
   const int jt0 = w, jt1 = 7 - w;
-  f4 gacc[9];
   double gd[9][4];
 #pragma unroll
-  for (int u = 0; u < 9; ++u) {
-    gacc[u] = f4{0, 0, 0, 0};
+  for (int u = 0; u < 9; ++u)
 #pragma unroll
     for (int r = 0; r < 4; ++r) gd[u][r] = 0.0;
-  }
   const i64 nblk = (ng + GC - 1) / GC;
   const int col = t % GC, row0 = t / GC;
   float nxt[PER];
@@ -1202,38 +1278,39 @@ __global__ __launch_bounds__(kBlock) void k_apply_gram(const float *__restrict__
       acc1[cc] = f4{0, 0, 0, 0};
     }
     switch (w) {
-      case 0: apply_compute<float, NT, 0, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      case 1: apply_compute<float, NT, 1, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      case 2: apply_compute<float, NT, 2, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      default: apply_compute<float, NT, 3, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      case 0: apply_compute_t<NT, 0, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      case 1: apply_compute_t<NT, 1, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      case 2: apply_compute_t<NT, 2, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+      default: apply_compute_t<NT, 3, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
     }
-    // W1 block into LDS (rows beyond N stay zero so they add nothing to the Gram)
+    // W1 = X + D X as BF16 hi/lo pieces (rows beyond N are zero: X and D are)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int jt = u == 0 ? jt0 : jt1;
       if (jt >= NT) continue;
+      const int j = 16 * jt + r16;
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
+        const int p0 = 16 * cc + 4 * q;
+        __bf16 h4[4], l4[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int j = 16 * jt + 4 * q + r;
-          const float v = xs[j][16 * cc + r16] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
-          w1s[j][16 * cc + r16] = v;
+          const float v = xs[j][p0 + r] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
+          const __bf16 hv = (__bf16)v;
+          h4[r] = hv;
+          l4[r] = (__bf16)(v - (float)hv);
         }
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+        *(bf4 *)&hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
+        *(bf4 *)&ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
       }
     }
     __syncthreads();
     switch (w) {
-      case 0: gram_chunk<float, NT, 0, GC, PITCH>(w1s, gacc, r16, q); break;
-      case 1: gram_chunk<float, NT, 1, GC, PITCH>(w1s, gacc, r16, q); break;
-      case 2: gram_chunk<float, NT, 2, GC, PITCH>(w1s, gacc, r16, q); break;
-      default: gram_chunk<float, NT, 3, GC, PITCH>(w1s, gacc, r16, q); break;
-    }
-#pragma unroll
-    for (int u = 0; u < 9; ++u) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gd[u][r] += (double)gacc[u][r];
-      gacc[u] = f4{0, 0, 0, 0};
+      case 0: gram_chunk_split<NT, 0, PB>(hs, ls, gd, r16, q); break;
+      case 1: gram_chunk_split<NT, 1, PB>(hs, ls, gd, r16, q); break;
+      case 2: gram_chunk_split<NT, 2, PB>(hs, ls, gd, r16, q); break;
+      default: gram_chunk_split<NT, 3, PB>(hs, ls, gd, r16, q); break;
     }
   }
   double *outp = part + (i64)blockIdx.x * 128 * 128;
