@@ -552,15 +552,62 @@ __device__ inline void tile_mma(const double *X, const double *Y, int ytrans, do
   for (int r = 0; r < 4; ++r) dst[(q + 4 * r) * kTP + r16] = acc[r];
 }
 
-// Blocked Cholesky G = L L^T and L^-1 in one workgroup (N <= 128, 16-wide
-// panels, right-looking).  Panel p: one wave factors the 16 x 16 diagonal
-// block and inverts it (elimination on [A_pp | I]); the panel L_ip = A_ip
-// L_pp^-T and the block row B_pj <- L_pp^-1 B_pj of B = L^-1 follow on MFMA;
-// then the trailing update A_ij -= L_ip L_jp^T and the eliminations
-// B_ij -= L_ip B_pj.  A tile slot holds A_ij until its panel is processed and
-// B_ij afterwards.  Padding rows beyond N carry an identity diagonal.
+// Value of a (wave-uniform) lane of v, as two scalar reads.
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// One wave: [A_pp | I] -> [L_pp^T | L_pp^-1] for a 16 x 16 diagonal block
+// (Gaussian elimination without pivoting).  Lane c < 32 holds column c of the
+// 16 x 32 augmented block in registers (all 16 rows), so row k of step k is
+// the lane's own register and the pivot and column k come from lane k by
+// scalar lane reads; lanes 32..63 carry zero columns.  L_pp^-1 goes to Li
+// (lower part; zeros above).  A pivot that is not above 1e-13 times the
+// block's original diagonal entry (dg) flags numerical rank deficiency in
+// *sbad.
+__device__ inline void chol_diag_block(const double *App, double *Li, const double *dg, int l,
+                                       int *sbad) {
+  const int c = l;
+  double v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (c < 16) v[r] = (c <= r) ? App[r * kTP + c] : App[c * kTP + r];
+    else v[r] = (c - 16 == r) ? 1.0 : 0.0;  // zero for c >= 32
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    double piv = readlane_f64(v[k], k);
+    if (!((piv > 1e-13 * dg[k]) && isfinite(piv))) {
+      if (l == 0) *sbad = 1;
+      piv = 1.0;
+    }
+    const double isp = 1.0 / sqrt(piv);
+    const double rk = v[k];
+    const double rki = rk * (isp * isp);
+    v[k] = rk * isp;
+#pragma unroll
+    for (int r = k + 1; r < 16; ++r) v[r] -= readlane_f64(v[r], k) * rki;
+  }
+  if (c >= 16 && c < 32) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Li[r * kTP + (c - 16)] = (c - 16 <= r) ? v[r] : 0.0;
+  }
+}
+
+// Blocked Cholesky G = L L^T and L^-1 in one workgroup (16-wide panels,
+// right-looking, one panel of lookahead).  Panel p: the panel L_ip = A_ip
+// L_pp^-T and the block row B_pj <- L_pp^-1 B_pj of B = L^-1 on MFMA; then
+// the trailing update A_ij -= L_ip L_jp^T and the eliminations B_ij -= L_ip
+// B_pj.  Wave 0 takes the update of the next diagonal block A_{p+1,p+1}
+// first and factors it (chol_diag_block) while the other waves do the rest
+// of the trailing update, so the serial diagonal factorisations overlap the
+// tile work.  A tile slot holds A_ij until its panel is processed and B_ij
+// afterwards.  Padding rows beyond N carry an identity diagonal.
 //
-// LDS_TILES: tiles live in LDS (N <= 128, ~100 KB); otherwise in the global
+// LDS_TILES: tiles live in LDS (N <= 128, ~105 KB); otherwise in the global
 // workspace ws (L2-resident; N <= 512: 528 tile slots plus 32 panel tiles).
 template <bool LDS_TILES, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict__ G, int N,
@@ -571,7 +618,7 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
                                                        double *__restrict__ ws) {
   __shared__ double slot_s[LDS_TILES ? 36 * kTile : 1];
   __shared__ double P_s[LDS_TILES ? 8 * kTile : 1];
-  __shared__ double Li[kTile];
+  __shared__ double Li2[2][kTile];
   __shared__ double sdg[512];
   __shared__ double sred[NTHR / 64];
   __shared__ int sbad;
@@ -582,30 +629,37 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
   const int NT = (N + 15) / 16;
   const int NP = 16 * NT;
   double m = 0.0;
-  // the lower triangle of G into the tile slots, 16 independent loads per
-  // thread in flight at a time
-  constexpr int kLB = 16;
-  for (int e0 = t; e0 < NP * NP; e0 += NTHR * kLB) {
-    double v[kLB];
+  // the lower triangle of G into the tile slots: wave w takes rows w, w + NW,
+  // ..., lanes take columns, ROWB rows per batch of independent loads
+  constexpr int CPR = LDS_TILES ? 2 : 8;       // 64-column chunks per row (NP <= 64 CPR)
+  constexpr int ROWB = LDS_TILES ? 8 : 2;
+  for (int r0 = w; r0 < NP; r0 += NW * ROWB) {
+    double v[ROWB][CPR];
 #pragma unroll
-    for (int u = 0; u < kLB; ++u) {
-      const int e = e0 + u * NTHR;
-      const int r = e / NP, c = e - (e / NP) * NP;
-      v[u] = (e < NP * NP && c <= r && r < N) ? G[(i64)r * N + c] : 0.0;
+    for (int u = 0; u < ROWB; ++u) {
+      const int r = r0 + NW * u;
+#pragma unroll
+      for (int j = 0; j < CPR; ++j) {
+        const int c = l + 64 * j;
+        v[u][j] = (r < N && c <= r) ? G[(i64)r * N + c] : 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < kLB; ++u) {
-      const int e = e0 + u * NTHR;
-      const int r = e / NP, c = e - (e / NP) * NP;
-      if (e < NP * NP && c <= r) {
-        double x = v[u];
-        if (r < N) {
-          const double d = x - (r == c ? 1.0 : 0.0);
-          m = isfinite(d) ? fmax(m, fabs(d)) : INFINITY;
-        } else {
-          x = (r == c) ? 1.0 : 0.0;
+    for (int u = 0; u < ROWB; ++u) {
+      const int r = r0 + NW * u;
+#pragma unroll
+      for (int j = 0; j < CPR; ++j) {
+        const int c = l + 64 * j;
+        if (r < NP && c <= r) {
+          double x = v[u][j];
+          if (r < N) {
+            const double d = x - (r == c ? 1.0 : 0.0);
+            m = isfinite(d) ? fmax(m, fabs(d)) : INFINITY;
+          } else {
+            x = (r == c) ? 1.0 : 0.0;
+          }
+          slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] = x;
         }
-        slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] = x;
       }
     }
   }
@@ -619,50 +673,11 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
     for (int k = 0; k < NW; ++k) mx = fmax(mx, sred[k]);
     info[1] = mx;
   }
+  if (w == 0) chol_diag_block(slot + tri_slot(0, 0) * kTile, Li2[0], sdg, l, &sbad);
+  __syncthreads();
   for (int p = 0; p < NT; ++p) {
-    // (a) one wave: [A_pp | I] -> [L_pp^T | L_pp^-1].  Lane l holds column
-    // c = l % 32 of the 16 x 32 augmented block, rows 2m + l / 32 (m < 8);
-    // pivot, row k and column k travel by cross-lane shuffles.
-    if (w == 0) {
-      const double *App = slot + tri_slot(p, p) * kTile;
-      const int c = l & 31, hi = l >> 5;
-      double v[8];
-#pragma unroll
-      for (int mm = 0; mm < 8; ++mm) {
-        const int r = 2 * mm + hi;
-        if (c < 16) v[mm] = (c <= r) ? App[r * kTP + c] : App[c * kTP + r];
-        else v[mm] = (c - 16 == r) ? 1.0 : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        double piv = __shfl(v[k >> 1], 32 * (k & 1) + k, 64);
-        const double rk = __shfl(v[k >> 1], 32 * (k & 1) + c, 64);
-        double ck[8];
-#pragma unroll
-        for (int mm = 0; mm < 8; ++mm) ck[mm] = __shfl(v[mm], 32 * hi + k, 64);
-        if (!((piv > 1e-13 * sdg[16 * p + k]) && isfinite(piv))) {
-          if (l == 0) sbad = 1;
-          piv = 1.0;
-        }
-        const double ip = 1.0 / piv, isp = 1.0 / sqrt(piv);
-        const double rki = rk * ip;
-#pragma unroll
-        for (int mm = 0; mm < 8; ++mm) {
-          const int r = 2 * mm + hi;
-          if (r == k) v[mm] = rk * isp;
-          else if (r > k) v[mm] -= ck[mm] * rki;
-        }
-      }
-      if (c >= 16) {
-#pragma unroll
-        for (int mm = 0; mm < 8; ++mm) {
-          const int r = 2 * mm + hi;
-          Li[r * kTP + (c - 16)] = (c - 16 <= r) ? v[mm] : 0.0;
-        }
-      }
-    }
-    __syncthreads();
-    // (b) panel L_ip = A_ip Li^T (i > p) into P[i]; (d) B_pj <- Li B_pj (j < p); B_pp = Li
+    const double *Li = Li2[p & 1];
+    // (b) panel L_ip = A_ip Li^T (i > p) into P[i]; B_pj <- Li B_pj (j < p); B_pp = Li
     {
       const int nb = NT - 1 - p;  // panel tiles
       const int nd = p;           // B row tiles
@@ -682,37 +697,53 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
       }
     }
     __syncthreads();
-    // (c) A_ij -= L_ip L_jp^T (p < j <= i); (e) B_ij -= L_ip B_pj (i > p, j <= p)
+    // (c) A_ij -= L_ip L_jp^T (p < j <= i); (e) B_ij -= L_ip B_pj (i > p, j <= p).
+    // With a next panel, wave 0 updates and factors A_{p+1,p+1} (task 0 of (c))
+    // and the other waves share the remaining tasks.
     {
       const int m1 = NT - 1 - p;
       const int nc = m1 * (m1 + 1) / 2;
       const int ne = m1 * (p + 1);
-      for (int task = w; task < nc + ne; task += NW) {
-        if (task < nc) {
-          // decode (i, j) with p < j <= i
-          int a = task, ii = 0;
-          while (a > ii) { a -= ii + 1; ++ii; }
-          const int i = p + 1 + ii, j = p + 1 + a;
-          double *Aij = slot + tri_slot(i, j) * kTile;
-          tile_mma(P + i * kTile, P + j * kTile, 1, -1.0, Aij, Aij, l);
-        } else {
-          const int a = task - nc;
-          const int i = p + 1 + a / (p + 1), j = a % (p + 1);
-          double *Bij = slot + tri_slot(i, j) * kTile;
-          tile_mma(P + i * kTile, slot + tri_slot(p, j) * kTile, 0, -1.0, j < p ? Bij : nullptr,
-                   Bij, l);
+      const bool look = (m1 > 0);
+      if (look && w == 0) {
+        double *A1 = slot + tri_slot(p + 1, p + 1) * kTile;
+        tile_mma(P + (p + 1) * kTile, P + (p + 1) * kTile, 1, -1.0, A1, A1, l);
+        __threadfence_block();
+        chol_diag_block(A1, Li2[(p + 1) & 1], sdg + 16 * (p + 1), l, &sbad);
+      }
+      const int first = look ? 1 : 0;                // task 0 is wave 0's when looking ahead
+      const int ww = look ? w - 1 : w, nww = look ? NW - 1 : NW;
+      if (ww >= 0) {
+        for (int task = first + ww; task < nc + ne; task += nww) {
+          if (task < nc) {
+            // decode (i, j) with p < j <= i
+            int a = task, ii = 0;
+            while (a > ii) { a -= ii + 1; ++ii; }
+            const int i = p + 1 + ii, j = p + 1 + a;
+            double *Aij = slot + tri_slot(i, j) * kTile;
+            tile_mma(P + i * kTile, P + j * kTile, 1, -1.0, Aij, Aij, l);
+          } else {
+            const int a = task - nc;
+            const int i = p + 1 + a / (p + 1), j = a % (p + 1);
+            double *Bij = slot + tri_slot(i, j) * kTile;
+            tile_mma(P + i * kTile, slot + tri_slot(p, j) * kTile, 0, -1.0, j < p ? Bij : nullptr,
+                     Bij, l);
+          }
         }
       }
     }
     __syncthreads();
   }
-  for (int e = t; e < N * N; e += NTHR) {
-    const int r = e / N, c = e % N;
-    const double v = (c <= r) ? slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] : 0.0;
-    Minv[e] = v;
-    const double d = v - (r == c ? 1.0 : 0.0);
-    D64[e] = d;
-    D32[e] = (float)d;
+  for (int r = w; r < N; r += NW) {
+    for (int c = l; c < N; c += 64) {
+      const double v =
+          (c <= r) ? slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] : 0.0;
+      const i64 e = (i64)r * N + c;
+      Minv[e] = v;
+      const double d = v - (r == c ? 1.0 : 0.0);
+      D64[e] = d;
+      D32[e] = (float)d;
+    }
   }
   if (t == 0) info[0] = sbad ? 1.0 : 0.0;
 }
@@ -1507,7 +1538,7 @@ hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, 
 hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
                                    double *info, double *ws, hipStream_t s) {
   if (N <= 128) {
-    hipLaunchKernelGGL((k_chol_blocked<true, kBlock>), dim3(1), dim3(kBlock), 0, s, G, N, Minv, D32,
+    hipLaunchKernelGGL((k_chol_blocked<true, 512>), dim3(1), dim3(512), 0, s, G, N, Minv, D32,
                        D64, info, ws);
     return hipGetLastError();
   }
