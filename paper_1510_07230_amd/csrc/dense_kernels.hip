@@ -1169,190 +1169,282 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
   }
 }
 
-// Transposed form of apply_compute: the MFMA operands are swapped, so that
-// acc[cc][r] holds (D X)^T, i.e. orbital 16*jt + lane%16 at grid point
-// 16*cc + 4*(lane/16) + r: four consecutive points of one orbital per lane.
-template <int NT, int W, int GC, int PITCH>
-__device__ inline void apply_compute_t(const float (*xs)[PITCH], const float (&a0)[4 * NT],
-                                       const float (&a1)[4 * NT], f4 (&acc0)[GC / 16],
-                                       f4 (&acc1)[GC / 16], int r16, int q) {
+// ---------------------------------------------------------------- 8-wave apply
+
+constexpr int kAB = 512;  // threads of the 8-wave apply kernels
+
+// One 16-point column group cc of the apply for wave pair W (row tiles W and
+// 7 - W): acc0/acc1 += D_tile X[:, 16 cc .. 16 cc + 15].  TRANS swaps the
+// MFMA operands, which leaves (D X)^T in the accumulators (lane l then holds
+// grid points 4 (l / 16) + r of orbital l % 16).
+template <typename T, int NT, int W, int PITCH, bool TRANS, typename Acc>
+__device__ inline void apply_cc(const T (*xs)[PITCH], const T (&a0)[4 * NT],
+                                const T (&a1)[4 * NT], Acc &acc0, Acc &acc1, int cc, int r16,
+                                int q) {
   constexpr int jt0 = W, jt1 = 7 - W;
   constexpr int ke0 = jt0 < NT ? 4 * (jt0 + 1) : 0;
   constexpr int ke1 = jt1 < NT ? 4 * (jt1 + 1) : 0;
   constexpr int ke = ke0 > ke1 ? ke0 : ke1;
 #pragma unroll
   for (int ks = 0; ks < ke; ++ks) {
-    float b[GC / 16];
-#pragma unroll
-    for (int cc = 0; cc < GC / 16; ++cc) b[cc] = xs[4 * ks + q][16 * cc + r16];
-    if (ks < ke0) {
-#pragma unroll
-      for (int cc = 0; cc < GC / 16; ++cc) acc0[cc] = mfma(b[cc], a0[ks], acc0[cc]);
-    }
-    if (ks < ke1) {
-#pragma unroll
-      for (int cc = 0; cc < GC / 16; ++cc) acc1[cc] = mfma(b[cc], a1[ks], acc1[cc]);
-    }
+    const T b = xs[4 * ks + q][16 * cc + r16];
+    if (ks < ke0) acc0 = TRANS ? mfma(b, a0[ks], acc0) : mfma(a0[ks], b, acc0);
+    if (ks < ke1) acc1 = TRANS ? mfma(b, a1[ks], acc1) : mfma(a1[ks], b, acc1);
   }
 }
 
-// Gram tiles of wave W over one 32-point chunk of W1 held in LDS as two BF16
-// pieces, W1 = hi + lo (hi = bf16(W1), lo = bf16(W1 - hi)).  Each tile sums
-// the four products lo lo^T, hi lo^T, lo hi^T, hi hi^T in FP32 on BF16 MFMA
-// (exact products, FP32 accumulation), which leaves only the rounding of lo
-// (2^-18 relative) and the FP32 sums; it is flushed into FP64 per chunk.
-// Tiles are visited column tile by column tile (ct = W .. 7), each with row
-// tiles W and, once ct >= 7 - W, 7 - W (the GramTile ownership).
-template <int NT, int W, int PB>
-__device__ inline void gram_chunk_split(const __bf16 (*hs)[PB], const __bf16 (*ls)[PB],
-                                        double (&gd)[9][4], int r16, int q) {
-  constexpr int nfirst = 8 - W;
-  bf8 rh0 = bf8{}, rl0 = bf8{}, rh1 = bf8{}, rl1 = bf8{};
-  if (W < NT) {
-    rh0 = *(const bf8 *)&hs[16 * W + r16][8 * q];
-    rl0 = *(const bf8 *)&ls[16 * W + r16][8 * q];
+// The 8-wave form of k_apply_small: out[j][g] = X[j][g] + sum_{i<=j} D[j][i]
+// X[i][g], D = L^-1 - I (N <= 128), optional fused density.  Wave w = (pair
+// p = w % 4, half h = w / 4) owns row tiles p and 7 - p (36 k-steps of 4 for
+// every pair) and the 16-point column group h of each 32-point block, so a
+// wave keeps half the accumulators of the 4-wave form and twice as many
+// waves share the CU.  Blocks of 32 grid points are staged through LDS; the
+// next two blocks are in flight in registers while a block is computed.
+template <typename T, int NT>
+__global__ __launch_bounds__(kAB) void k_apply8(const T *__restrict__ D, const T *__restrict__ X,
+                                                T *__restrict__ out, int N, i64 ng,
+                                                const double *__restrict__ occ,
+                                                double *__restrict__ rho) {
+  constexpr int GC = 32;
+  constexpr int ROWS = 16 * NT;
+  constexpr int PITCH = GC + 1;
+  constexpr int RSTEP = kAB / GC;
+  constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
+  __shared__ T xs[ROWS][PITCH];
+  __shared__ double srho[2][4][GC];
+  typedef typename AccOf<T>::type Acc;
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int pw = w & 3, h = w >> 2;
+  T a0[4 * NT], a1[4 * NT];
+  switch (pw) {
+    case 0: apply_load_a<T, NT, 0>(D, N, a0, a1, r16, q); break;
+    case 1: apply_load_a<T, NT, 1>(D, N, a0, a1, r16, q); break;
+    case 2: apply_load_a<T, NT, 2>(D, N, a0, a1, r16, q); break;
+    default: apply_load_a<T, NT, 3>(D, N, a0, a1, r16, q); break;
   }
-  if (7 - W < NT) {
-    rh1 = *(const bf8 *)&hs[16 * (7 - W) + r16][8 * q];
-    rl1 = *(const bf8 *)&ls[16 * (7 - W) + r16][8 * q];
-  }
+  const int jt0 = pw, jt1 = 7 - pw;
+  double occv[2][4];
 #pragma unroll
-  for (int ct = W; ct < 8; ++ct) {
-    if (ct >= NT) continue;
+  for (int u = 0; u < 2; ++u) {
+    const int jt = u == 0 ? jt0 : jt1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * jt + out_row<T>(q, r);
+      occv[u][r] = (rho != nullptr && jt < NT && j < N) ? occ[j] : 0.0;
+    }
+  }
+  const i64 nblk = (ng + GC - 1) / GC;
+  const int col = t % GC, row0 = t / GC;
+  const i64 G = gridDim.x;
+  T na[PER], nb[PER];
+  auto load = [&](T (&dst)[PER], i64 blk) {
+    const i64 g = blk * GC + col;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      dst[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : (T)0;
+    }
+  };
+  auto flush_rho = [&](i64 pblk, int pbuf) {
+    if (t < GC) {
+      const i64 g = pblk * GC + t;
+      if (g < ng)
+        rho[g] = srho[pbuf][0][t] + srho[pbuf][1][t] + srho[pbuf][2][t] + srho[pbuf][3][t];
+    }
+  };
+  i64 pending = -1;
+  int buf = 0;
+  i64 blk = blockIdx.x;
+  if (blk < nblk) load(na, blk);
+  if (blk + G < nblk) load(nb, blk + G);
+  for (; blk < nblk; blk += G) {
+    __syncthreads();
+    if (rho != nullptr && pending >= 0) flush_rho(pending, buf ^ 1);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int row = row0 + RSTEP * e;
+      if (row < ROWS) xs[row][col] = na[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) na[e] = nb[e];
+    if (blk + 2 * G < nblk) load(nb, blk + 2 * G);
+    Acc acc0 = Acc{0, 0, 0, 0}, acc1 = Acc{0, 0, 0, 0};
+    switch (pw) {
+      case 0: apply_cc<T, NT, 0, PITCH, false>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+      case 1: apply_cc<T, NT, 1, PITCH, false>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+      case 2: apply_cc<T, NT, 2, PITCH, false>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+      default: apply_cc<T, NT, 3, PITCH, false>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+    }
+    const i64 g = blk * GC + 16 * h + r16;
+    double rp = 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int jt = u == 0 ? jt0 : jt1;
+      if (jt >= NT) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * jt + out_row<T>(q, r);
+        if (j < N && g < ng) {
+          const T v = xs[j][16 * h + r16] + (u == 0 ? acc0[r] : acc1[r]);
+          out[(i64)j * ng + g] = v;
+          rp += occv[u][r] * ((double)v * (double)v);
+        }
+      }
+    }
+    if (rho != nullptr) {
+      rp += __shfl_xor(rp, 16, 64);
+      rp += __shfl_xor(rp, 32, 64);
+      if (q == 0) srho[buf][pw][16 * h + r16] = rp;
+      pending = blk;
+      buf ^= 1;
+    }
+  }
+  if (rho != nullptr && pending >= 0) {
+    __syncthreads();
+    flush_rho(pending, buf ^ 1);
+  }
+}
+
+// Gram tiles u in [U0, U1) of pair W (GramTile ownership: row tile W with
+// column tiles W..7, then row tile 7 - W with 7 - W..7) over one 32-point
+// chunk of W1 held in LDS as two BF16 pieces, W1 = hi + lo (hi = bf16(W1),
+// lo = bf16(W1 - hi)).  Each tile sums the four products lo lo^T, hi lo^T,
+// lo hi^T, hi hi^T in FP32 on BF16 MFMA (exact products, FP32 accumulation),
+// which leaves only the rounding of lo (2^-18 relative) and the FP32 sums; it
+// is flushed into FP64 per chunk.
+template <int NT, int W, int U0, int U1, int PB>
+__device__ inline void gram_tiles_split(const __bf16 (*hs)[PB], const __bf16 (*ls)[PB],
+                                        double (&gd)[U1 - U0][4], int r16, int q) {
+#pragma unroll
+  for (int u = U0; u < U1; ++u) {
+    constexpr int nfirst = 8 - W;
+    const int rt = u < nfirst ? W : 7 - W;
+    const int ct = u < nfirst ? W + u : (7 - W) + (u - nfirst);
+    if (rt >= NT || ct >= NT) continue;
+    const bf8 rh = *(const bf8 *)&hs[16 * rt + r16][8 * q];
+    const bf8 rl = *(const bf8 *)&ls[16 * rt + r16][8 * q];
     const bf8 ch = *(const bf8 *)&hs[16 * ct + r16][8 * q];
     const bf8 cl = *(const bf8 *)&ls[16 * ct + r16][8 * q];
-    {
-      f4 c = f4{0, 0, 0, 0};
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl0, cl, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh0, cl, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl0, ch, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh0, ch, c, 0, 0, 0);
-      const int u = ct - W;
+    f4 c = f4{0, 0, 0, 0};
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl, cl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh, cl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl, ch, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh, ch, c, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) gd[u][r] += (double)c[r];
-    }
-    if (ct >= 7 - W && 7 - W < NT) {
-      f4 c = f4{0, 0, 0, 0};
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl1, cl, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh1, cl, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl1, ch, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh1, ch, c, 0, 0, 0);
-      const int u = nfirst + (ct - (7 - W));
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gd[u][r] += (double)c[r];
-    }
+    for (int r = 0; r < 4; ++r) gd[u - U0][r] += (double)c[r];
   }
 }
 
 // First Cholesky-QR pass fused with the second Gram (FP32 orbitals, N <= 128):
-// W1 = X + (L1^-1 - I) X is formed block by block on FP32 MFMA as in
-// k_apply_small (with the operands swapped, so each lane ends up with four
-// consecutive grid points of one orbital), kept on chip as its BF16 hi/lo
-// pieces, and its partial Gram <W1^T W1> over the workgroup's blocks is
-// accumulated by gram_chunk_split (FP32-accurate) and flushed into FP64 after
-// every block.  part[blockIdx.x] holds the partial.
+// W1 never leaves the chip.  Wave (pair p,
+// half h) forms its row tiles p, 7 - p of W1 = X + (L1^-1 - I) X for the
+// column group h of each 32-point block (operands swapped, so the lane holds
+// consecutive points of one orbital), stores them in LDS as BF16 hi/lo
+// pieces, and after a barrier accumulates Gram tiles u in [0, 5) (h = 0) or
+// [5, 9) (h = 1) of pair p with the split-BF16 products, flushed into FP64
+// every block.  Two blocks of X are in flight in registers.
 template <int NT>
-__global__ __launch_bounds__(kBlock) void k_apply_gram(const float *__restrict__ D,
-                                                       const float *__restrict__ X, int N,
-                                                       i64 ng, double *__restrict__ part) {
+__global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D,
+                                                     const float *__restrict__ X, int N, i64 ng,
+                                                     double *__restrict__ part) {
   constexpr int GC = 32;
   constexpr int ROWS = 16 * NT;
   constexpr int PITCH = GC + 1;
-  constexpr int PB = GC + 8;  // BF16 row pitch: 80 bytes keeps 16-byte fragment reads aligned
-  constexpr int RSTEP = kBlock / GC;
+  constexpr int PB = GC + 8;
+  constexpr int RSTEP = kAB / GC;
   constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
-  constexpr int NC = GC / 16;
   __shared__ float xs[ROWS][PITCH];
   __shared__ __attribute__((aligned(16))) __bf16 hs[ROWS][PB];
   __shared__ __attribute__((aligned(16))) __bf16 ls[ROWS][PB];
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int pw = w & 3, h = w >> 2;
   float a0[4 * NT], a1[4 * NT];
-  switch (w) {
+  switch (pw) {
     case 0: apply_load_a<float, NT, 0>(D, N, a0, a1, r16, q); break;
     case 1: apply_load_a<float, NT, 1>(D, N, a0, a1, r16, q); break;
     case 2: apply_load_a<float, NT, 2>(D, N, a0, a1, r16, q); break;
     default: apply_load_a<float, NT, 3>(D, N, a0, a1, r16, q); break;
   }
-  const int jt0 = w, jt1 = 7 - w;
-  double gd[9][4];
+  const int jt0 = pw, jt1 = 7 - pw;
+  double gd[5][4];
 #pragma unroll
-  for (int u = 0; u < 9; ++u)
+  for (int u = 0; u < 5; ++u)
 #pragma unroll
     for (int r = 0; r < 4; ++r) gd[u][r] = 0.0;
   const i64 nblk = (ng + GC - 1) / GC;
   const int col = t % GC, row0 = t / GC;
-  float nxt[PER];
-  auto load = [&](i64 blk) {
+  const i64 G = gridDim.x;
+  float na[PER], nb[PER];
+  auto load = [&](float (&dst)[PER], i64 blk) {
     const i64 g = blk * GC + col;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
-      nxt[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : 0.0f;
+      dst[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : 0.0f;
     }
   };
   i64 blk = blockIdx.x;
-  if (blk < nblk) load(blk);
-  for (; blk < nblk; blk += gridDim.x) {
+  if (blk < nblk) load(na, blk);
+  if (blk + G < nblk) load(nb, blk + G);
+  for (; blk < nblk; blk += G) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
-      if (row < ROWS) xs[row][col] = nxt[e];
+      if (row < ROWS) xs[row][col] = na[e];
     }
     __syncthreads();
-    if (blk + gridDim.x < nblk) load(blk + gridDim.x);
-    f4 acc0[NC], acc1[NC];
 #pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-      acc0[cc] = f4{0, 0, 0, 0};
-      acc1[cc] = f4{0, 0, 0, 0};
+    for (int e = 0; e < PER; ++e) na[e] = nb[e];
+    if (blk + 2 * G < nblk) load(nb, blk + 2 * G);
+    f4 acc0 = f4{0, 0, 0, 0}, acc1 = f4{0, 0, 0, 0};
+    switch (pw) {
+      case 0: apply_cc<float, NT, 0, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+      case 1: apply_cc<float, NT, 1, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+      case 2: apply_cc<float, NT, 2, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+      default: apply_cc<float, NT, 3, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
     }
-    switch (w) {
-      case 0: apply_compute_t<NT, 0, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      case 1: apply_compute_t<NT, 1, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      case 2: apply_compute_t<NT, 2, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      default: apply_compute_t<NT, 3, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-    }
-    // W1 = X + D X as BF16 hi/lo pieces (rows beyond N are zero: X and D are)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int jt = u == 0 ? jt0 : jt1;
       if (jt >= NT) continue;
       const int j = 16 * jt + r16;
+      const int p0 = 16 * h + 4 * q;
+      __bf16 h4[4], l4[4];
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const int p0 = 16 * cc + 4 * q;
-        __bf16 h4[4], l4[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float v = xs[j][p0 + r] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
-          const __bf16 hv = (__bf16)v;
-          h4[r] = hv;
-          l4[r] = (__bf16)(v - (float)hv);
-        }
-        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
-        *(bf4 *)&hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
-        *(bf4 *)&ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
+      for (int r = 0; r < 4; ++r) {
+        const float v = xs[j][p0 + r] + (u == 0 ? acc0[r] : acc1[r]);
+        const __bf16 hv = (__bf16)v;
+        h4[r] = hv;
+        l4[r] = (__bf16)(v - (float)hv);
       }
+      typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+      *(bf4 *)&hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
+      *(bf4 *)&ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
     }
     __syncthreads();
-    switch (w) {
-      case 0: gram_chunk_split<NT, 0, PB>(hs, ls, gd, r16, q); break;
-      case 1: gram_chunk_split<NT, 1, PB>(hs, ls, gd, r16, q); break;
-      case 2: gram_chunk_split<NT, 2, PB>(hs, ls, gd, r16, q); break;
-      default: gram_chunk_split<NT, 3, PB>(hs, ls, gd, r16, q); break;
-    }
+#define POU_G8(P)                                                                      \
+  case P:                                                                              \
+    if (h == 0) gram_tiles_split<NT, P, 0, 5, PB>(hs, ls, gd, r16, q);                 \
+    else gram_tiles_split<NT, P, 5, 9, PB>(hs, ls, *(double(*)[4][4]) & gd, r16, q); \
+    break;
+    switch (pw) { POU_G8(0) POU_G8(1) POU_G8(2) POU_G8(3) }
+#undef POU_G8
   }
   double *outp = part + (i64)blockIdx.x * 128 * 128;
+  const int u0 = h == 0 ? 0 : 5, nu = h == 0 ? 5 : 4;
 #pragma unroll
-  for (int u = 0; u < 9; ++u) {
+  for (int uu = 0; uu < 5; ++uu) {
+    if (uu >= nu) continue;
     int rt, ct;
-    gram_tile_runtime(w, u, rt, ct);
+    gram_tile_runtime(pw, u0 + uu, rt, ct);
     if (rt < NT && ct < NT) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        outp[(16 * rt + 4 * q + r) * 128 + 16 * ct + r16] = gd[u][r];
+        outp[(16 * rt + 4 * q + r) * 128 + 16 * ct + r16] = gd[uu][r];
     }
   }
 }
@@ -1390,10 +1482,10 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
   }
 }
 
-// Workgroups of `kernel` (kBlock threads, static LDS only) that are resident
+// Workgroups of `kernel` (`block` threads, static LDS only) that are resident
 // on the current device at once: the grid of a kernel that walks its work in
 // a grid-stride loop.  Cached per kernel and device.
-int resident_workgroups(const void *kernel) {
+int resident_workgroups(const void *kernel, int block = kBlock) {
   static std::mutex mu;
   static std::map<std::pair<const void *, int>, int> cache;
   int dev = 0;
@@ -1406,7 +1498,7 @@ int resident_workgroups(const void *kernel) {
   if (it != cache.end()) return it->second;
   int cus = 0, per = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) {
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess) {
     (void)hipGetLastError();
     return 512;
   }
@@ -1440,7 +1532,7 @@ int gram_split(int N, bool fp32) {
     take((const void *)k_gram_small_bf16<K, 64, false>);                      \
     take((const void *)k_gram_small<float, K, 32, true>);                     \
     take((const void *)k_gram_small<float, K, 64, false>);                    \
-    take((const void *)k_apply_gram<K>);                                      \
+    g = std::min(g, resident_workgroups((const void *)k_apply_gram8<K>, kAB)); \
   } else {                                                                    \
     take((const void *)k_gram_small<double, K, 32, true>);                    \
     take((const void *)k_gram_small<double, K, 32, false>);                   \
@@ -1564,8 +1656,7 @@ hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, in
   if (N > 128) return hipErrorInvalidValue;
   const int NT = (N + 15) / 16;
 #define POU_AG(K)                                                                        \
-  hipLaunchKernelGGL((k_apply_gram<K>), dim3(nsplit), dim3(kBlock), 0, s, D32, X, N, ng, \
-                     part)
+  hipLaunchKernelGGL((k_apply_gram8<K>), dim3(nsplit), dim3(kAB), 0, s, D32, X, N, ng, part)
   POU_NT_SWITCH(NT, POU_AG)
 #undef POU_AG
   return hipGetLastError();
@@ -1586,12 +1677,19 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
     const int NT = (N + 15) / 16;
     constexpr int GC = sizeof(T) == 4 ? 32 : 16;
     i64 nblk = (ng + GC - 1) / GC;
-#define POU_APPLY_SMALL(K)                                                                  \
-  {                                                                                         \
-    const int grid = (int)std::min<i64>(                                                    \
-        nblk, resident_workgroups((const void *)k_apply_small<T, K, GC>));                  \
-    hipLaunchKernelGGL((k_apply_small<T, K, GC>), dim3(grid), dim3(kBlock), 0, s, D, X, out, \
-                       N, ng, occ, rho);                                                    \
+    // FP32: the 4-wave kernel (measured faster); FP64: the 8-wave kernel
+#define POU_APPLY_SMALL(K)                                                                    \
+  if (sizeof(T) == 4) {                                                                       \
+    const int grid = (int)std::min<i64>(                                                      \
+        nblk, resident_workgroups((const void *)k_apply_small<T, K, GC>));                    \
+    hipLaunchKernelGGL((k_apply_small<T, K, GC>), dim3(grid), dim3(kBlock), 0, s, D, X, out,   \
+                       N, ng, occ, rho);                                                      \
+  } else {                                                                                    \
+    const i64 nb8 = (ng + 31) / 32;                                                           \
+    const int grid =                                                                          \
+        (int)std::min<i64>(nb8, resident_workgroups((const void *)k_apply8<T, K>, kAB));      \
+    hipLaunchKernelGGL((k_apply8<T, K>), dim3(grid), dim3(kAB), 0, s, D, X, out, N, ng, occ,  \
+                       rho);                                                                  \
   }
     POU_NT_SWITCH(NT, POU_APPLY_SMALL)
 #undef POU_APPLY_SMALL
