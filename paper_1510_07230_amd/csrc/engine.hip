@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <string>
 #include <vector>
 
@@ -99,6 +100,7 @@ struct pou_ctx {
   void *eval_HU = nullptr;
   int last_cg_iters = 0;
   std::vector<double> rep_host;
+  double *h_step = nullptr;  // pinned: trial report | step scalars (8) | accept flags (2)
 
   // event timing
   unsigned prof_mask = 0;  // kernel groups timed (bit k for group k)
@@ -138,6 +140,7 @@ pou_status fail(pou_ctx *c, pou_status s, const std::string &msg) {
 void prof_begin(pou_ctx *c, int tag);
 void prof_end(pou_ctx *c);
 void prof_drain(pou_ctx *c);
+void prof_discard_last(pou_ctx *c, int tag);
 
 template <typename P>
 pou_status dalloc(pou_ctx *c, P **ptr, size_t bytes) {
@@ -155,6 +158,8 @@ pou_status dalloc(pou_ctx *c, P **ptr, size_t bytes) {
 void free_all(pou_ctx *c) {
   for (void *p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
+  if (c->h_step) (void)hipHostFree(c->h_step);
+  c->h_step = nullptr;
   c->d_occ = c->d_atoms = c->d_rho = c->d_vh = c->d_vext = c->d_veff = nullptr;
   c->d_veff32 = nullptr;
   c->d_rhoion = c->d_lam1 = nullptr;
@@ -210,6 +215,19 @@ void prof_end(pou_ctx *c) {
   }
   c->cur_tag = -1;
   c->cur_a = nullptr;
+}
+
+// Drop the newest timed launch of group `tag` (one that the device skipped:
+// a gated accept of a declined trial), so per-launch averages cover real work.
+void prof_discard_last(pou_ctx *c, int tag) {
+  for (auto it = c->pending.rbegin(); it != c->pending.rend(); ++it) {
+    if (it->tag == tag) {
+      c->pool.push_back(it->a);
+      c->pool.push_back(it->b);
+      c->pending.erase(std::next(it).base());
+      return;
+    }
+  }
 }
 
 // after a stream synchronisation every recorded event has completed
@@ -513,32 +531,55 @@ pou_status restart(pou_ctx *c, const T *W) {
   KL(POU_K_OTHER, pou::launch_zz<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_part, N, c->ng,
                                     c->nblk_orb, s));
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
-  KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, 0, c->p.tau_init, c->d_scal, s));
+  KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, 0, c->p.tau_init, c->d_scal, nullptr, s));
+  return POU_OK;
+}
+
+// Accept of the current trial (W <- W2, BB dot products, next tau_BB on the
+// device), gated on flags[0]: enqueued before the host knows the decision.
+template <typename T>
+pou_status enqueue_accept(pou_ctx *c, T *W, const double *gate) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  KL(POU_K_COMMIT, pou::launch_commit<T>(W, (const T *)c->d_HW, c->d_rep[0], (const T *)c->d_W2,
+                                         (const T *)c->d_HWt, c->d_rep[1], c->d_part, N, c->ng,
+                                         c->nblk_orb, gate, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 4, c->dv, s));
+  const int lnext = c->l + 1;
+  const int mode = (c->p.bb_mode == 1 || c->p.bb_mode == 2) ? c->p.bb_mode
+                                                             : ((lnext % 2 == 1) ? 1 : 2);
+  KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, mode, c->p.tau_init, c->d_scal, gate, s));
   return POU_OK;
 }
 
 // One iteration of Algorithm M.  tau_BB and ||Z||^2 of the current iterate
 // live on the device (d_scal); the trial kernels read tau = tau_BB * delta^s
-// from there, and the only host synchronisation per trial is the energy
-// report, which also returns tau_BB and ||Z||^2 for the test of eq. "ene-de".
+// from there.  After each trial the test of eq. "ene-de" runs on the device
+// and the accept is enqueued behind it, gated on its outcome, so the one host
+// synchronisation per trial (reading the report into pinned memory) does not
+// stall the stream; the host then only follows the device's decision.  If the
+// one-iteration Hartree solve missed its tolerance the device declines, and
+// the host finishes the solve, redoes the potentials and decides itself.
 template <typename T>
 pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
   hipStream_t s = c->stream;
   const int N = c->N;
   if (W != c->last_U || !c->cur_valid) CHK(restart<T>(c, W));
   const int passes = c->p.orth_passes;
+  const int RS = Report::size(N);
+  double *hrep = c->h_step, *hscal = c->h_step + RS, *hflag = c->h_step + RS + 5;
   pou_energy_terms et{};
   double tau = 0.0, tau_bb = 0.0, zz = 0.0;
   int s_acc = 0, cg_total = 0;
   bool accepted = false;
   double gram_dev = 0.0;
-  std::vector<double> &r = c->rep_host;
-  double scal[5];
   for (int sidx = 0; sidx <= c->p.s_max; ++sidx) {
     const double tscale = std::pow(c->p.delta, sidx);
+    const bool last = (sidx == c->p.s_max);
     s_acc = sidx;
     bool rho_done = false;
     double *rep_t = c->d_rep[1];
+    double *dflag = rep_t + RS + 5;  // written by the Armijo kernel, read by the gated accept
     if (N <= 128) {
       CHK(trial_orth_fused<T>(c, W, tscale, rep_t + 2 * N + 3));
       rho_done = true;
@@ -549,33 +590,58 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
                          &rho_done));
     }
     int it = 0;
-    CHK(eval_report<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, rho_done, r, scal, &it));
+    CHK(evaluate<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, rho_done, &it));
     cg_total += it;
-    tau_bb = scal[0];
-    zz = scal[1];
+    KL(POU_K_OTHER, pou::launch_armijo(rep_t, c->d_occ, N, c->p.terms, passes, Report::rr(N),
+                                       c->p.cg_rtol * c->p.cg_rtol, c->d_scal, tscale, c->C,
+                                       c->p.rho1, last ? 1 : 0, rep_t + RS, s));
+    HIPCHK(c, hipMemcpyAsync(hrep, rep_t, sizeof(double) * (RS + 7), hipMemcpyDeviceToHost, s));
+    CHK(enqueue_accept<T>(c, W, dflag));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (hflag[0] == 0.0) prof_discard_last(c, POU_K_COMMIT);
+    prof_drain(c);
+    tau_bb = hscal[0];
+    zz = hscal[1];
     tau = tau_bb * tscale;
+    const double rr = hrep[Report::rr(N)], bb = hrep[Report::rr(N) + 1];
+    if (!std::isfinite(rr) || !std::isfinite(bb))
+      return fail(c, POU_ERR_NONFINITE, "Poisson right-hand side or residual is not finite");
+    if (hflag[0] != 0.0) {
+      // accepted on the device: W, the BB history and tau_BB are updated
+      accepted = hflag[1] != 0.0;
+      terms_from_report(c, hrep, &et);
+      gram_dev = hrep[2 * N + 4];
+      break;
+    }
+    std::vector<double> &r = c->rep_host;
+    r.assign(hrep, hrep + RS);
+    const bool redo = rr > c->p.cg_rtol * c->p.cg_rtol * bb;
+    if (redo) {
+      // finish the Hartree solve with the checked solver and redo the potentials
+      int more = 0;
+      CHK(poisson(c, c->d_rho, c->d_vh, c->p.cg_rtol, c->p.cg_maxit, true, &more));
+      cg_total += more;
+      c->last_cg_iters = it + more;
+      CHK(potentials_and_h<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t));
+      CHK(sync_read(c, r.data(), rep_t, sizeof(double) * RS));
+    }
     for (int p = 0; p < passes; ++p)
       if (r[2 * N + 3 + 2 * p] != 0.0)
         return fail(c, POU_ERR_NOT_SPD, "trial Gram matrix is not positive definite (pass " +
                                              std::to_string(p) + ")");
-    gram_dev = r[2 * N + 4];
     terms_from_report(c, r.data(), &et);
     if (!std::isfinite(et.E)) return fail(c, POU_ERR_NONFINITE, "trial energy is not finite");
-    // eq. "ene-de": E(W(tau)) <= C - rho1 tau ||Z||_F^2
-    if (et.E <= c->C - c->p.rho1 * tau * zz) {
-      accepted = true;
+    gram_dev = r[2 * N + 4];
+    if (!redo && !last) continue;  // the device found eq. "ene-de" violated: backtrack
+    // host decision after a finished Hartree solve (or the last trial)
+    const bool pass = et.E <= c->C - c->p.rho1 * tau * zz;
+    if (pass || last) {
+      accepted = pass;
+      KL(POU_K_OTHER, pou::launch_set_flags(dflag, 1.0, pass ? 1.0 : 0.0, s));
+      CHK(enqueue_accept<T>(c, W, dflag));
       break;
     }
   }
-  // accept: U <- W2, and the dot products and step of the next iteration
-  KL(POU_K_COMMIT, pou::launch_commit<T>(W, (const T *)c->d_HW, c->d_rep[0], (const T *)c->d_W2,
-                                         (const T *)c->d_HWt, c->d_rep[1], c->d_part, N, c->ng,
-                                         c->nblk_orb, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 4, c->dv, s));
-  const int lnext = c->l + 1;
-  const int mode = (c->p.bb_mode == 1 || c->p.bb_mode == 2) ? c->p.bb_mode
-                                                             : ((lnext % 2 == 1) ? 1 : 2);
-  KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, mode, c->p.tau_init, c->d_scal, s));
   std::swap(c->d_HW, c->d_HWt);
   std::swap(c->d_rep[0], c->d_rep[1]);
   const double E_old = c->E;
@@ -600,7 +666,7 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
     info->Q = c->Q;
     info->gram_dev = gram_dev;
   }
-  c->l = lnext;
+  c->l = c->l + 1;
   return POU_OK;
 }
 
@@ -874,8 +940,15 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_Mcomb, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_red, sizeof(double) * (size_t)std::max(4 * norb, 4 * std::max(1, natoms)) + 64));
   CHK(dalloc(c, &c->d_scal, sizeof(double) * 8));
-  CHK(dalloc(c, &c->d_rep[0], sizeof(double) * Report::size(norb)));
-  CHK(dalloc(c, &c->d_rep[1], sizeof(double) * Report::size(norb)));
+  // each report is followed by 8 doubles: step scalars and the accept flags
+  CHK(dalloc(c, &c->d_rep[0], sizeof(double) * (Report::size(norb) + 8)));
+  CHK(dalloc(c, &c->d_rep[1], sizeof(double) * (Report::size(norb) + 8)));
+  if (hipHostMalloc((void **)&c->h_step, sizeof(double) * (Report::size(norb) + 10)) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    c->h_step = nullptr;
+    return fail(c, POU_ERR_OOM, "pinned host buffer for the step report");
+  }
   CHK(dalloc(c, &c->d_HW, bbytes));
   CHK(dalloc(c, &c->d_HWt, bbytes));
   CHK(dalloc(c, &c->d_Wt, bbytes));

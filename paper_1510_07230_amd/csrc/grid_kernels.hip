@@ -737,7 +737,9 @@ __global__ __launch_bounds__(kBlock) void k_commit(T *__restrict__ U, const T *_
                                                    const T *__restrict__ Wn,
                                                    const T *__restrict__ HWn,
                                                    const double *__restrict__ sign,
-                                                   double *__restrict__ part, i64 ng) {
+                                                   double *__restrict__ part, i64 ng,
+                                                   const double *__restrict__ gate) {
+  if (gate != nullptr && gate[0] == 0.0) return;
   __shared__ double red[4 * 4];
   const int orb = blockIdx.y;
   const double so = sig[orb], sn = sign[orb];
@@ -823,7 +825,9 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const T *__restrict__ x, i
 // 1 sy, 2 yy, 3 zz) or, in mode 0, zz per orbital in [i].  One wave, fixed
 // summation order.  out = (tau_BB, zz, ss, sy, yy).
 __global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, int N, int mode,
-                                                double tau_init, double *__restrict__ out) {
+                                                double tau_init, double *__restrict__ out,
+                                                const double *__restrict__ gate) {
+  if (gate != nullptr && gate[0] == 0.0) return;
   const int l = threadIdx.x;
   double ss = 0.0, sy = 0.0, yy = 0.0, zz = 0.0;
   // lane l sums orbitals l, l + 64, ...; the wave then combines in a fixed order
@@ -853,6 +857,48 @@ __global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, i
   out[2] = ss;
   out[3] = sy;
   out[4] = yy;
+}
+
+// Test of eq. "ene-de" for a trial on the device, so that the accept can be
+// enqueued before the host has read the trial's energy.  rep is the trial's
+// evaluation report (sigma N | kin N | e3 | orth info 2*npass... | rr, bb at
+// rr_off), scal = (tau_BB, ||Z||^2, ...).  The energy is assembled as the
+// host does (occupation-weighted kinetic sum in orbital order, then the
+// exchange, external and Hartree terms).  ext[0..4] receives a copy of scal
+// (so that one copy brings report, scalars and decision to the host);
+// ext[5] = 1 when the trial is to be accepted: the Hartree residual met its
+// target, every Cholesky pass was positive definite, E is finite, and
+// E <= C - rho1 tau ||Z||^2 (or force, the last backtrack); ext[6] = 1 when
+// the inequality itself held.
+__global__ void k_armijo(const double *__restrict__ rep, const double *__restrict__ occ, int N,
+                         unsigned terms, int npass, int rr_off, double rtol2,
+                         const double *__restrict__ scal, double tscale, double C, double rho1,
+                         int force, double *__restrict__ ext) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int k = 0; k < 5; ++k) ext[k] = scal[k];
+  double *flags = ext + 5;
+  const double rr = rep[rr_off], bb = rep[rr_off + 1];
+  bool ok = isfinite(rr) && isfinite(bb) && rr <= rtol2 * bb;
+  for (int p = 0; p < npass; ++p) ok = ok && rep[2 * N + 3 + 2 * p] == 0.0;
+  double ekin = 0.0;
+  for (int i = 0; i < N; ++i) ekin += occ[i] * rep[N + i];
+  const double cx = 0.73855876638202240;  // 3/4 (3/pi)^(1/3)
+  double E = (terms & 1u) ? ekin : 0.0;
+  E += (terms & 8u) ? -cx * rep[2 * N + 0] : 0.0;
+  E += (terms & 2u) ? rep[2 * N + 1] : 0.0;
+  E += (terms & 4u) ? 0.5 * rep[2 * N + 2] : 0.0;
+  ok = ok && isfinite(E);
+  const double tau = scal[0] * tscale;
+  const bool pass = E <= C - rho1 * tau * scal[1];
+  flags[0] = (ok && (pass || force != 0)) ? 1.0 : 0.0;
+  flags[1] = pass ? 1.0 : 0.0;
+}
+
+__global__ void k_set_flags(double *__restrict__ flags, double a, double b) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    flags[0] = a;
+    flags[1] = b;
+  }
 }
 
 inline int grid_for(i64 work, int cap = 4096) {
@@ -985,10 +1031,10 @@ hipError_t launch_trial(const T *W, const T *HW, const double *sig, const double
 template <typename T>
 hipError_t launch_commit(T *U, const T *HW, const double *sig, const T *Wn, const T *HWn,
                          const double *sign, double *part, int N, i64 ng, int nblk,
-                         hipStream_t s) {
+                         const double *gate, hipStream_t s) {
   dim3 grid(nblk, N);
   hipLaunchKernelGGL(k_commit<T>, grid, dim3(kBlock), 0, s, U, HW, sig, Wn, HWn, sign, part,
-                     ng);
+                     ng, gate);
   return hipGetLastError();
 }
 
@@ -1023,8 +1069,21 @@ hipError_t launch_nonfinite(const T *x, i64 count, int *flag, hipStream_t s) {
 }
 
 hipError_t launch_bb_tau(const double *red, int N, int mode, double tau_init, double *out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_bb_tau, dim3(1), dim3(64), 0, s, red, N, mode, tau_init, out);
+                         const double *gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_bb_tau, dim3(1), dim3(64), 0, s, red, N, mode, tau_init, out, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_armijo(const double *rep, const double *occ, int N, unsigned terms, int npass,
+                         int rr_off, double rtol2, const double *scal, double tscale, double C,
+                         double rho1, int force, double *ext, hipStream_t s) {
+  hipLaunchKernelGGL(k_armijo, dim3(1), dim3(64), 0, s, rep, occ, N, terms, npass, rr_off, rtol2,
+                     scal, tscale, C, rho1, force, ext);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_flags(double *flags, double a, double b, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, flags, a, b);
   return hipGetLastError();
 }
 
@@ -1052,7 +1111,7 @@ hipError_t launch_ion_forces(const double *atoms, int M, const double *vh, doubl
                                       double, T *, int, i64, hipStream_t);                  \
   template hipError_t launch_commit<T>(T *, const T *, const double *, const T *, const T *, \
                                        const double *, double *, int, i64, int,             \
-                                       hipStream_t);                                        \
+                                       const double *, hipStream_t);                        \
   template hipError_t launch_zz<T>(const T *, const T *, const double *, double *, int, i64, \
                                    int, hipStream_t);                                       \
   template hipError_t launch_backward_scale<T>(const T *, const double *, double, T *, int, \

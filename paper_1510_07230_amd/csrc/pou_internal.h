@@ -137,16 +137,24 @@ hipError_t launch_poisson_residual(const double *x, const double *rho, const dou
 template <typename T>
 hipError_t launch_trial(const T *W, const T *HW, const double *sig, const double *dtau,
                         double tscale, T *Wt, int N, i64 ng, hipStream_t s);
-// Barzilai-Borwein step on the device: out = (tau_BB, zz, ss, sy, yy)
+// Barzilai-Borwein step on the device: out = (tau_BB, zz, ss, sy, yy); does
+// nothing when gate is non-null and gate[0] == 0
 hipError_t launch_bb_tau(const double *red, int N, int mode, double tau_init, double *out,
-                         hipStream_t s);
+                         const double *gate, hipStream_t s);
+// device test of eq. "ene-de" for a trial report: ext[0..4] = scal, ext[5] = accept,
+// ext[6] = inequality held
+hipError_t launch_armijo(const double *rep, const double *occ, int N, unsigned terms, int npass,
+                         int rr_off, double rtol2, const double *scal, double tscale, double C,
+                         double rho1, int force, double *ext, hipStream_t s);
+hipError_t launch_set_flags(double *flags, double a, double b, hipStream_t s);
 // accept: U <- Wn; partials per (orbital, block) of
 //   s.s, s.y, y.y, zn.zn  with s = Wn - W, y = zn - z,
 //   z = HW - sig W, zn = HWn - sign Wn
+// (nothing when gate is non-null and gate[0] == 0)
 template <typename T>
 hipError_t launch_commit(T *U, const T *HW, const double *sig, const T *Wn, const T *HWn,
                          const double *sign, double *part, int N, i64 ng, int nblk,
-                         hipStream_t s);
+                         const double *gate, hipStream_t s);
 // z.z partials for z = HW - sig W
 template <typename T>
 hipError_t launch_zz(const T *W, const T *HW, const double *sig, double *part, int N,
