@@ -37,6 +37,14 @@ __device__ inline int out_row(int q, int r) {
   return sizeof(T) == 8 ? q + 4 * r : 4 * q + r;
 }
 
+// BF16 pieces of an FP32 value: hi = bf16(v), lo = bf16(v - hi); hi + lo
+// equals v to about 2^-17 relative.  The same rounding (to nearest even) is
+// used wherever a split value has to be reproduced.
+__device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
 template <typename T> struct AccOf;
 template <> struct AccOf<double> { typedef d4 type; };
 template <> struct AccOf<float> { typedef f4 type; };
@@ -280,13 +288,16 @@ __global__ __launch_bounds__(1024) void k_cholesky_inverse(double *__restrict__ 
 
 // M = A B for lower-triangular A, B (N x N, zeros above the diagonal), with
 // D64 = M - I and D32 its FP32 copy: the combined factor of two Cholesky-QR
-// passes.  One wave per 16 x 16 output tile (I, J) on FP64 MFMA, summing the
-// tile products A_IK B_KJ for J <= K <= I; tiles above the diagonal are zero.
+// passes.  With split_b, B is replaced by the value the fused first apply
+// used: I + Dh + Dl with Dh/Dl the BF16 pieces of (float)(B - I).  One wave
+// per 16 x 16 output tile (I, J) on FP64 MFMA, summing the tile products
+// A_IK B_KJ for J <= K <= I; tiles above the diagonal are zero.
 __global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict__ A,
                                                         const double *__restrict__ B,
                                                         double *__restrict__ M,
                                                         double *__restrict__ D64,
-                                                        float *__restrict__ D32, int N) {
+                                                        float *__restrict__ D32, int N,
+                                                        int split_b) {
   const int NT = (N + 15) / 16;
   const int I = blockIdx.x / NT, J = blockIdx.x % NT;
   const int l = threadIdx.x, r16 = l & 15, q = l >> 4;
@@ -299,7 +310,14 @@ __global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict
       for (int s4 = 0; s4 < 4; ++s4) {
         const int k = 16 * K + 4 * s4 + q;
         a[s4] = (ia < N && k < N) ? A[(i64)ia * N + k] : 0.0;
-        b[s4] = (jb < N && k < N) ? B[(i64)k * N + jb] : 0.0;
+        double bv = (jb < N && k < N) ? B[(i64)k * N + jb] : 0.0;
+        if (split_b && jb < N && k < N) {
+          const double dlt = (k == jb) ? 1.0 : 0.0;
+          __bf16 hi, lo;
+          split_bf16((float)(bv - dlt), hi, lo);
+          bv = dlt + ((double)(float)hi + (double)(float)lo);
+        }
+        b[s4] = bv;
       }
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) acc = mfma(a[s4], b[s4], acc);
@@ -1338,13 +1356,21 @@ __device__ inline void gram_tiles_split(const __bf16 (*hs)[PB], const __bf16 (*l
 }
 
 // First Cholesky-QR pass fused with the second Gram (FP32 orbitals, N <= 128):
-// W1 never leaves the chip.  Wave (pair p,
-// half h) forms its row tiles p, 7 - p of W1 = X + (L1^-1 - I) X for the
-// column group h of each 32-point block (operands swapped, so the lane holds
-// consecutive points of one orbital), stores them in LDS as BF16 hi/lo
-// pieces, and after a barrier accumulates Gram tiles u in [0, 5) (h = 0) or
-// [5, 9) (h = 1) of pair p with the split-BF16 products, flushed into FP64
-// every block.  Two blocks of X are in flight in registers.
+// W1 never leaves the chip.  The first factor enters as its split value
+// I + (Dh + Dl), Dh/Dl the BF16 pieces of D = L1^-1 - I (the combined factor
+// of the two passes is formed from that same split value, so the second pass
+// measures exactly the transform that is applied; the first factor comes from
+// a BF16 Gram and is approximate anyway).  Per 32-point block:
+//  * each thread loads 8 consecutive orbitals at one point (two blocks in
+//    flight in registers), stores them in LDS in FP32 and, transposed, as
+//    BF16 hi/lo pieces (one 16-byte write each);
+//  * wave (pair p, half h) forms (D X)^T for row tiles p, 7 - p and the 16
+//    points 16h .. 16h + 15 as the four BF16 MFMA products Dh Xh, Dh Xl,
+//    Dl Xh, Dl Xl with FP32 accumulation, adds X in FP32 and stores W1 as
+//    BF16 hi/lo pieces;
+//  * after a barrier, the wave accumulates Gram tiles u in [0, 5) (h = 0) or
+//    [5, 9) (h = 1) of pair p with the split products (gram_tiles_split),
+//    flushed into FP64 every block.
 template <int NT>
 __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D,
                                                      const float *__restrict__ X, int N, i64 ng,
@@ -1352,37 +1378,61 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   constexpr int GC = 32;
   constexpr int ROWS = 16 * NT;
   constexpr int PITCH = GC + 1;
-  constexpr int PB = GC + 8;
-  constexpr int RSTEP = kAB / GC;
-  constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
+  constexpr int PB = GC + 8;        // W1 pieces: [orbital][point]
+  constexpr int NCH = (ROWS + 31) / 32;  // K chunks of 32 orbitals
+  constexpr int PX = 32 * NCH + 8;       // X pieces: [point][orbital], 16-byte aligned rows
   __shared__ float xs[ROWS][PITCH];
+  __shared__ __attribute__((aligned(16))) __bf16 xh[GC][PX];
+  __shared__ __attribute__((aligned(16))) __bf16 xl[GC][PX];
   __shared__ __attribute__((aligned(16))) __bf16 hs[ROWS][PB];
   __shared__ __attribute__((aligned(16))) __bf16 ls[ROWS][PB];
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
   const int pw = w & 3, h = w >> 2;
-  float a0[4 * NT], a1[4 * NT];
-  switch (pw) {
-    case 0: apply_load_a<float, NT, 0>(D, N, a0, a1, r16, q); break;
-    case 1: apply_load_a<float, NT, 1>(D, N, a0, a1, r16, q); break;
-    case 2: apply_load_a<float, NT, 2>(D, N, a0, a1, r16, q); break;
-    default: apply_load_a<float, NT, 3>(D, N, a0, a1, r16, q); break;
-  }
   const int jt0 = pw, jt1 = 7 - pw;
+  // orbitals ROWS .. 32 NCH - 1 of the last K chunk are never loaded: keep their
+  // pieces zero (an uninitialised NaN pattern times a zero D entry is NaN)
+  if (32 * NCH > ROWS) {
+    constexpr int PAD = 32 * NCH - ROWS;
+    for (int e = t; e < GC * PAD; e += kAB) {
+      xh[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
+      xl[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
+    }
+  }
+  // B operands: D^T fragments, lane = (output orbital 16 jt + r16, orbitals 32 kc + 8q .. +7)
+  bf8 dh[2][NCH], dl[2][NCH];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int jt = u == 0 ? jt0 : jt1;
+    const int j = 16 * jt + r16;
+#pragma unroll
+    for (int kc = 0; kc < NCH; ++kc) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int i = 32 * kc + 8 * q + e;
+        const float d = (jt < NT && j < N && i < N) ? D[(i64)j * N + i] : 0.0f;
+        __bf16 a, b;
+        split_bf16(d, a, b);
+        dh[u][kc][e] = a;
+        dl[u][kc][e] = b;
+      }
+    }
+  }
   double gd[5][4];
 #pragma unroll
   for (int u = 0; u < 5; ++u)
 #pragma unroll
     for (int r = 0; r < 4; ++r) gd[u][r] = 0.0;
   const i64 nblk = (ng + GC - 1) / GC;
-  const int col = t % GC, row0 = t / GC;
+  const int col = t % GC, rg = t / GC;  // rg < 16: orbitals 8 rg .. 8 rg + 7
+  const bool loader = 8 * rg < ROWS;
   const i64 G = gridDim.x;
-  float na[PER], nb[PER];
-  auto load = [&](float (&dst)[PER], i64 blk) {
+  float na[8], nb[8];
+  auto load = [&](float (&dst)[8], i64 blk) {
     const i64 g = blk * GC + col;
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int row = row0 + RSTEP * e;
+    for (int e = 0; e < 8; ++e) {
+      const int row = 8 * rg + e;
       dst[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : 0.0f;
     }
   };
@@ -1391,22 +1441,43 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   if (blk + G < nblk) load(nb, blk + G);
   for (; blk < nblk; blk += G) {
     __syncthreads();
+    if (loader) {
+      bf8 vh, vl;
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int row = row0 + RSTEP * e;
-      if (row < ROWS) xs[row][col] = na[e];
+      for (int e = 0; e < 8; ++e) {
+        xs[8 * rg + e][col] = na[e];
+        __bf16 a, b;
+        split_bf16(na[e], a, b);
+        vh[e] = a;
+        vl[e] = b;
+      }
+      *(bf8 *)&xh[col][8 * rg] = vh;
+      *(bf8 *)&xl[col][8 * rg] = vl;
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < PER; ++e) na[e] = nb[e];
+    for (int e = 0; e < 8; ++e) na[e] = nb[e];
     if (blk + 2 * G < nblk) load(nb, blk + 2 * G);
-    f4 acc0 = f4{0, 0, 0, 0}, acc1 = f4{0, 0, 0, 0};
-    switch (pw) {
-      case 0: apply_cc<float, NT, 0, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
-      case 1: apply_cc<float, NT, 1, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
-      case 2: apply_cc<float, NT, 2, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
-      default: apply_cc<float, NT, 3, PITCH, true>(xs, a0, a1, acc0, acc1, h, r16, q); break;
+    // (D X)^T for this wave's row tiles and points 16 h .. 16 h + 15
+    f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+#pragma unroll
+    for (int kc = 0; kc < NCH; ++kc) {
+      const bf8 ah = *(const bf8 *)&xh[16 * h + r16][32 * kc + 8 * q];
+      const bf8 al = *(const bf8 *)&xl[16 * h + r16][32 * kc + 8 * q];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int jt = u == 0 ? jt0 : jt1;
+        // chunk kc holds orbitals >= 32 kc; tile jt needs orbitals <= 16 jt + 15
+        if (jt >= NT || 32 * kc > 16 * jt + 15) continue;
+        f4 c = acc[u];
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, dl[u][kc], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, dl[u][kc], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, dh[u][kc], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, dh[u][kc], c, 0, 0, 0);
+        acc[u] = c;
+      }
     }
+    // W1 = X + (D X) as BF16 hi/lo pieces (rows beyond N are zero: X and D are)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int jt = u == 0 ? jt0 : jt1;
@@ -1415,12 +1486,7 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
       const int p0 = 16 * h + 4 * q;
       __bf16 h4[4], l4[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float v = xs[j][p0 + r] + (u == 0 ? acc0[r] : acc1[r]);
-        const __bf16 hv = (__bf16)v;
-        h4[r] = hv;
-        l4[r] = (__bf16)(v - (float)hv);
-      }
+      for (int r = 0; r < 4; ++r) split_bf16(xs[j][p0 + r] + acc[u][r], h4[r], l4[r]);
       typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
       *(bf4 *)&hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
       *(bf4 *)&ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
@@ -1663,10 +1729,11 @@ hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, in
 }
 
 hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
-                                  float *D32, int N, hipStream_t s) {
+                                  float *D32, int N, bool split_b, hipStream_t s) {
   if (N > 512) return hipErrorInvalidValue;
   const int NT = (N + 15) / 16;
-  hipLaunchKernelGGL(k_combine_factors, dim3(NT * NT), dim3(64), 0, s, A, B, M, D64, D32, N);
+  hipLaunchKernelGGL(k_combine_factors, dim3(NT * NT), dim3(64), 0, s, A, B, M, D64, D32, N,
+                     split_b ? 1 : 0);
   return hipGetLastError();
 }
 

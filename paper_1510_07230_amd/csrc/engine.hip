@@ -500,7 +500,7 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv2, c->d_D32, c->d_D64, c->N,
                                                     info + 2, c->d_cholws, s));
     KL(POU_K_CHOLESKY, pou::launch_combine_factors(c->d_Minv2, c->d_Minv, c->d_Mcomb, c->d_D64,
-                                                   c->d_D32, c->N, s));
+                                                   c->d_D32, c->N, mixed, s));
   }
   KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), (const T *)c->d_Wt,
                                              (T *)c->d_W2, c->N, c->ng, c->d_occ, c->d_rho, s));

@@ -196,9 +196,11 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const d
 // partial Gram of X + D32 X over nsplit workgroups into part (nothing else written)
 hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, int nsplit,
                              double *part, hipStream_t s);
-// M = A B (lower-triangular), D64 = M - I, D32 = (float) D64
+// M = A B (lower-triangular), D64 = M - I, D32 = (float) D64; with split_b, B is
+// taken as I + the BF16 hi/lo split of (float)(B - I) (the first factor as the
+// fused mixed-precision apply uses it)
 hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
-                                  float *D32, int N, hipStream_t s);
+                                  float *D32, int N, bool split_b, hipStream_t s);
 // G = dv * sum of partials (full symmetric N x N)
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s);
