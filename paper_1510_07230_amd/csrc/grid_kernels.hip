@@ -61,25 +61,25 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   const int gx = x0 + tx;
   const bool vx = gx < n;
   const int gxw = wrap(gx, n);
-  int gyw[kNB];
+  // in-plane offsets (32-bit: n <= 1024) of this thread's rows and halo cells
+  const int nn = n * n;
+  int offr[kNB];
   bool valid[kNB];
 #pragma unroll
   for (int r = 0; r < kNB; ++r) {
     const int gy = y0 + 4 * trow + r;
-    gyw[r] = wrap(gy, n);
+    offr[r] = wrap(gy, n) * n + gxw;
     valid[r] = vx && gy < n;
   }
   // halo assignments (independent of z)
   const int hx_row = threadIdx.x >> 3;  // 0..31
   const int hx_c = threadIdx.x & 7;     // 0..7
   const int hx_lc = hx_c < 4 ? hx_c - 4 : kTX + hx_c - 4;
-  const int hx_gx = wrap(x0 + hx_lc, n);
-  const int hx_gy = wrap(y0 + hx_row, n);
+  const int off_hx = wrap(y0 + hx_row, n) * n + wrap(x0 + hx_lc, n);
   const int hy_col = threadIdx.x & 31;
   const int hy_r = threadIdx.x >> 5;  // 0..7
   const int hy_lr = hy_r < 4 ? hy_r - 4 : kTY + hy_r - 4;
-  const int hy_gy = wrap(y0 + hy_lr, n);
-  const int hy_gx = wrap(x0 + hy_col, n);
+  const int off_hy = wrap(y0 + hy_lr, n) * n + wrap(x0 + hy_col, n);
 
   const int z0 = zc * a.zlen;
   const int z1 = min(n, z0 + a.zlen);
@@ -87,9 +87,9 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   T q[kNB][2 * kRad + 1];
 #pragma unroll
   for (int m = 0; m < 2 * kRad; ++m) {
-    const int zz = wrap(z0 - kRad + m, n);
+    const T *pz = u + (i64)wrap(z0 - kRad + m, n) * nn;
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) q[r][m] = u[((i64)zz * n + gyw[r]) * n + gxw];
+    for (int r = 0; r < kNB; ++r) q[r][m] = pz[offr[r]];
   }
   const T c1 = (T)FD8::c1, c2 = (T)FD8::c2, c3 = (T)FD8::c3, c4 = (T)FD8::c4;
   const T cm[5] = {(T)0, c1, c2, c3, c4};
@@ -103,15 +103,16 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   constexpr int kPD = 2;
   T nhx[kPD], nhy[kPD], nq[kPD][kNB], nvf[kPD][kNB];
   auto issue = [&](int slot, int zz) {
-    const i64 pl = (i64)zz * n;
-    const T hx = u[(pl + hx_gy) * n + hx_gx];
-    const T hy = u[(pl + hy_gy) * n + hy_gx];
-    const i64 pq = (i64)wrap(zz + kRad, n) * n;
+    const T *pz = u + (i64)zz * nn;
+    const T *pq = u + (i64)wrap(zz + kRad, n) * nn;
+    const T *pv = veff + (i64)zz * nn;
+    const T hx = pz[off_hx];
+    const T hy = pz[off_hy];
     T qq[kNB], vv[kNB];
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) qq[r] = u[(pq + gyw[r]) * n + gxw];
+    for (int r = 0; r < kNB; ++r) qq[r] = pq[offr[r]];
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) vv[r] = veff[(pl + gyw[r]) * n + gxw];
+    for (int r = 0; r < kNB; ++r) vv[r] = pv[offr[r]];
 #pragma unroll
     for (int k = 0; k < kPD; ++k) {
       if (k == slot) {
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
     for (int k = 0; k < kPD; ++k) {
       const int z = zb + k;
       if (z < z1) {
-        const i64 plane = (i64)z * n;
+        T *hz = hu + (i64)z * nn;
         T vf[kNB];
 #pragma unroll
         for (int r = 0; r < kNB; ++r) {
@@ -151,6 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
         T col[kNB + 2 * kRad];
 #pragma unroll
         for (int kk = 0; kk < kNB + 2 * kRad; ++kk) col[kk] = s[4 * trow + kk][tx + kRad];
+        // sigma and kinetic partials of this plane's four points in T, then FP64
+        T psig = (T)0, pkin = (T)0;
 #pragma unroll
         for (int r = 0; r < kNB; ++r) {
           const int ly = 4 * trow + r + kRad;
@@ -166,13 +169,14 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
           }
           const T ku = mh * lap;
           if (valid[r]) {
-            const i64 g = (plane + gyw[r]) * n + gxw;
             const T h = ku + vf[r] * c0;
-            hu[g] = h;
-            acc_sig += (double)c0 * (double)h;
-            acc_kin += (double)c0 * (double)ku;
+            hz[offr[r]] = h;
+            psig += c0 * h;
+            pkin += c0 * ku;
           }
         }
+        acc_sig += (double)psig;
+        acc_kin += (double)pkin;
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < 2 * kRad; ++m) {
