@@ -84,12 +84,15 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   const int z0 = zc * a.zlen;
   const int z1 = min(n, z0 + a.zlen);
 
-  T q[kNB][2 * kRad + 1];
+  // z neighbours: a circular register queue, plane p in slot (p - z0) mod 9;
+  // the z loop is unrolled by 9 so every slot index is a compile-time constant
+  constexpr int kQ = 2 * kRad + 1;
+  T q[kNB][kQ];
 #pragma unroll
   for (int m = 0; m < 2 * kRad; ++m) {
     const T *pz = u + (i64)wrap(z0 - kRad + m, n) * nn;
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) q[r][m] = pz[offr[r]];
+    for (int r = 0; r < kNB; ++r) q[r][(m - kRad + kQ) % kQ] = pz[offr[r]];
   }
   const T c1 = (T)FD8::c1, c2 = (T)FD8::c2, c3 = (T)FD8::c3, c4 = (T)FD8::c4;
   const T cm[5] = {(T)0, c1, c2, c3, c4};
@@ -98,9 +101,10 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
 
   // Loads for plane zz are issued kPD planes ahead of their use into a ring
   // of register sets (the halo of plane zz, the queue head zz + 4 and V_eff
-  // on plane zz), so kPD planes of loads are in flight per workgroup.  The
-  // z loop is unrolled by kPD so every ring index is a compile-time constant.
-  constexpr int kPD = 2;
+  // on plane zz), so kPD planes of loads are in flight per workgroup; kPD
+  // divides the unroll factor, so ring slots are compile-time constants too.
+  constexpr int kPD = 3;
+  static_assert(kQ % kPD == 0, "prefetch ring must divide the z unroll");
   T nhx[kPD], nhy[kPD], nq[kPD][kNB], nvf[kPD][kNB];
   auto issue = [&](int slot, int zz) {
     const T *pz = u + (i64)zz * nn;
@@ -130,23 +134,24 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   for (int k = 0; k < kPD; ++k)
     if (z0 + k < z1) issue(k, z0 + k);
 
-  for (int zb = z0; zb < z1; zb += kPD) {
+  for (int zb = z0; zb < z1; zb += kQ) {
 #pragma unroll
-    for (int k = 0; k < kPD; ++k) {
+    for (int k = 0; k < kQ; ++k) {
       const int z = zb + k;
       if (z < z1) {
         T *hz = hu + (i64)z * nn;
+        const int ps = k % kPD;
         T vf[kNB];
 #pragma unroll
         for (int r = 0; r < kNB; ++r) {
-          q[r][2 * kRad] = nq[k][r];
-          vf[r] = nvf[k][r];
+          q[r][(k + kRad) % kQ] = nq[ps][r];
+          vf[r] = nvf[ps][r];
         }
 #pragma unroll
-        for (int r = 0; r < kNB; ++r) s[4 * trow + r + kRad][tx + kRad] = q[r][kRad];
-        s[hx_row + kRad][hx_lc + kRad] = nhx[k];
-        s[hy_lr + kRad][hy_col + kRad] = nhy[k];
-        if (z + kPD < z1) issue(k, z + kPD);
+        for (int r = 0; r < kNB; ++r) s[4 * trow + r + kRad][tx + kRad] = q[r][k % kQ];
+        s[hx_row + kRad][hx_lc + kRad] = nhx[ps];
+        s[hy_lr + kRad][hy_col + kRad] = nhy[ps];
+        if (z + kPD < z1) issue(ps, z + kPD);
         __syncthreads();
         // y column of this thread: rows 4 trow - 4 .. 4 trow + 7 (local + kRad offset)
         T col[kNB + 2 * kRad];
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
           for (int m = 1; m <= kRad; ++m) {
             const T dxm = (s[ly][lx + m] - c0) + (s[ly][lx - m] - c0);
             const T dym = (col[r + kRad + m] - c0) + (col[r + kRad - m] - c0);
-            const T dzm = (q[r][kRad + m] - c0) + (q[r][kRad - m] - c0);
+            const T dzm = (q[r][(k + m) % kQ] - c0) + (q[r][(k - m + kQ) % kQ] - c0);
             lap += cm[m] * ((dxm + dym) + dzm);
           }
           const T ku = mh * lap;
@@ -178,11 +183,6 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
         acc_sig += (double)psig;
         acc_kin += (double)pkin;
         __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 2 * kRad; ++m) {
-#pragma unroll
-          for (int r = 0; r < kNB; ++r) q[r][m] = q[r][m + 1];
-        }
       }
     }
   }
