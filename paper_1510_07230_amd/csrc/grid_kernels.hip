@@ -885,6 +885,7 @@ __global__ void k_armijo(const double *__restrict__ rep, const double *__restric
   bool ok = isfinite(rr) && isfinite(bb) && rr <= rtol2 * bb;
   for (int p = 0; p < npass; ++p) ok = ok && rep[2 * N + 3 + 2 * p] == 0.0;
   double ekin = 0.0;
+#pragma unroll 16
   for (int i = 0; i < N; ++i) ekin += occ[i] * rep[N + i];
   const double cx = 0.73855876638202240;  // 3/4 (3/pi)^(1/3)
   double E = (terms & 1u) ? ekin : 0.0;
