@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Follows section 3 in its own order, with n_org = 1 (orthonormalise every step,
-as in Table 1 and Table 2) and subspace diagonalisation switched off:
+Follows section 3 in its own order.  By default n_org = 1 (orthonormalise
+every step, as in Table 1 and Table 2) and subspace diagonalisation is off;
+the two modifications of section 3.3 are described at the end of this note.
 
   * start: W^(0) = Orth(U^(0)) (Algorithm B step 1 asks for orthonormal
     data; the raw start is orthonormalised first), C^(0) = E(W^(0)), Q^(0) = 1;
@@ -31,6 +32,30 @@ design notes of the build):
     and the step is flagged as not accepted.
   * a non-finite or non-positive BB value falls back to tau_init.
 
+Modifications (section 3.3, Algorithm M):
+  * n_org > 1: on iterations with l mod n_org != 0 the step is the plain
+    W <- W - tau_BB Z (no orthonormalisation, no energy test, no backtracking);
+    the energy test, backtracking and Orth only run when l mod n_org == 0.
+    H = H(rho(W)) is still rebuilt after every step for the next direction.
+  * n_diag > 0: after an orthonormalising step that produces iterate l (the
+    index after the increment) with l mod n_diag == 0, Sigma = <(H W)^T W> is
+    diagonalised, P^T Sigma P = Gamma (eigenvalues ascending), and
+    W <- W P, H W <- (H W) P (H depends on rho only, and rho(W P) = rho(W) when
+    every occupation is the same), sigma_ii <- <(H W)_i, W_i>.
+  * full-Sigma residual: the Stiefel gradient H W - W Sigma of eq. "gra"
+    (section 2.2) with Sigma = <(H W)^T W>, and its norm
+    sqrt(tr<R^T R>) as reported in section 4.1.
+
+Readings for the modifications (also listed with the design notes):
+  * plain steps do not update C, Q or the df history; df is the relative
+    change between consecutive orthonormalised iterates, and the stopping
+    rule averages the last three of those;
+  * the BB step of the iteration after a rotation is computed from the
+    unrotated pair (S, Y of the step that produced the rotated iterate; the
+    traces are invariant under W -> W P), and the history restarts from the
+    rotated iterate; ||Z||_F^2 is that of the rotated iterate;
+  * subspace rotation requires equal occupations (otherwise rho changes).
+
 Parity: trajectory values have no published reference (the paper prints none
 for a reproducible system): "parity unpinned" for the tau / s / E sequences
 themselves.  The converged results are pinned by closed forms and dense
@@ -56,6 +81,8 @@ class Params:
     bb_mode: int = 0
     tau_init: float = 0.0     # <= 0: 1 / lambda_max(K)
     s_max: int = 10
+    n_org: int = 1            # orthonormalise (and test the energy) every n_org steps
+    n_diag: int = 0           # subspace diagonalisation every n_diag steps (0: off)
 
 
 def lambda_max_kinetic(h):
@@ -77,6 +104,8 @@ class StepRecord:
     C: float
     Q: float
     trials: list
+    orthonormalized: bool = True
+    rotated: bool = False
 
 
 class AlgorithmM:
@@ -101,7 +130,10 @@ class AlgorithmM:
         self.l = 0
         self.Wp = None
         self.Zp = None
+        self.tau_pending = None
         self.df_hist = []
+        if self.p.n_diag > 0 and np.ptp(np.asarray(sys.occ, dtype=float)) != 0.0:
+            raise ValueError("subspace rotation needs equal occupations")
 
     def _dot(self, a, b):
         return float(np.sum(ks.inner(a, b, self.h)))
@@ -110,15 +142,19 @@ class AlgorithmM:
         return self.HW - self.sig[:, None, None, None] * self.W
 
     def bb_step(self, Z):
-        p = self.p
+        if self.tau_pending is not None:
+            tau, self.tau_pending = self.tau_pending, None
+            return tau
         if self.l == 0 or self.Wp is None:
             return self.tau_init
-        S = self.W - self.Wp
-        Y = Z - self.Zp
+        return self._bb_value(self.W - self.Wp, Z - self.Zp, self.l)
+
+    def _bb_value(self, S, Y, l):
+        p = self.p
         ss = self._dot(S, S)
         sy = abs(self._dot(S, Y))
         yy = self._dot(Y, Y)
-        mode = p.bb_mode if p.bb_mode in (1, 2) else (1 if self.l % 2 == 1 else 2)
+        mode = p.bb_mode if p.bb_mode in (1, 2) else (1 if l % 2 == 1 else 2)
         try:
             tau = ss / sy if mode == 1 else sy / yy
         except ZeroDivisionError:
@@ -132,6 +168,8 @@ class AlgorithmM:
         Z = self.direction()
         zz = self._dot(Z, Z)
         tau_bb = self.bb_step(Z)
+        if p.n_org > 1 and self.l % p.n_org != 0:
+            return self._plain_step(Z, zz, tau_bb)
         trials = []
         accepted = False
         for s in range(p.s_max + 1):
@@ -151,9 +189,52 @@ class AlgorithmM:
         self.Q = Qn
         df = abs(E_old - self.E) / (abs(E_old) + 1.0)
         self.df_hist.append(df)
-        rec = StepRecord(self.l, s, accepted, self.E, tau_bb, tau, zz, df, self.C, self.Q, trials)
+        rotated = False
+        if p.n_diag > 0 and (self.l + 1) % p.n_diag == 0:
+            # the next BB step from the unrotated pair, then rotate
+            self.tau_pending = self._bb_value(self.W - self.Wp, self.direction() - self.Zp,
+                                              self.l + 1)
+            self.rotate()
+            self.Wp = self.Zp = None
+            rotated = True
+        rec = StepRecord(self.l, s, accepted, self.E, tau_bb, tau, zz, df, self.C, self.Q,
+                         trials, True, rotated)
         self.l += 1
         return rec
+
+    def _plain_step(self, Z, zz, tau_bb):
+        """W <- W - tau_BB Z without orthonormalisation or energy test."""
+        self.Wp, self.Zp = self.W, Z
+        self.W = self.W - tau_bb * Z
+        self.terms, self.HW, self.sig = ks.energy_and_h(self.W, self.sys, self.vext)
+        rec = StepRecord(self.l, 0, True, self.terms.E, tau_bb, tau_bb, zz, float("nan"),
+                         self.C, self.Q, [(tau_bb, self.terms.E)], False, False)
+        self.l += 1
+        return rec
+
+    def sigma_full(self):
+        """Sigma = <(H W)^T W>, Sigma_ij = <(H W)_i, W_j>."""
+        h = self.h
+        N = self.W.shape[0]
+        return h ** 3 * self.HW.reshape(N, -1) @ self.W.reshape(N, -1).T
+
+    def rotate(self):
+        """Subspace diagonalisation: P^T Sigma P = Gamma, W <- W P, H W <- (H W) P."""
+        S = self.sigma_full()
+        _, P = np.linalg.eigh(0.5 * (S + S.T))
+        N = self.W.shape[0]
+        shape = self.W.shape
+        self.W = (P.T @ self.W.reshape(N, -1)).reshape(shape)
+        self.HW = (P.T @ self.HW.reshape(N, -1)).reshape(shape)
+        self.sig = ks.inner(self.HW, self.W, self.h)
+        return P
+
+    def residual(self):
+        """||H W - W Sigma||_F in the grid inner product, Sigma = <(H W)^T W>."""
+        N = self.W.shape[0]
+        S = self.sigma_full()
+        R = self.HW.reshape(N, -1) - S.T @ self.W.reshape(N, -1)
+        return float(np.sqrt(self.h ** 3 * np.sum(R * R)))
 
     def converged(self, tol):
         return len(self.df_hist) >= 3 and float(np.mean(self.df_hist[-3:])) < tol
