@@ -37,9 +37,10 @@ Modifications (section 3.3, Algorithm M):
     W <- W - tau_BB Z (no orthonormalisation, no energy test, no backtracking);
     the energy test, backtracking and Orth only run when l mod n_org == 0.
     H = H(rho(W)) is still rebuilt after every step for the next direction.
-  * n_diag > 0: after an orthonormalising step that produces iterate l (the
-    index after the increment) with l mod n_diag == 0, Sigma = <(H W)^T W> is
-    diagonalised, P^T Sigma P = Gamma (eigenvalues ascending), and
+  * n_diag > 0: after the orthonormalising step of iteration l (the index
+    before the increment) with l mod n_diag == 0, Sigma = <(H W)^T W> of the
+    new iterate W^(l+1) is diagonalised, P^T Sigma P = Gamma (eigenvalues
+    ascending), and
     W <- W P, H W <- (H W) P (H depends on rho only, and rho(W P) = rho(W) when
     every occupation is the same), sigma_ii <- <(H W)_i, W_i>.
   * full-Sigma residual: the Stiefel gradient H W - W Sigma of eq. "gra"
@@ -54,7 +55,11 @@ Readings for the modifications (also listed with the design notes):
     unrotated pair (S, Y of the step that produced the rotated iterate; the
     traces are invariant under W -> W P), and the history restarts from the
     rotated iterate; ||Z||_F^2 is that of the rotated iterate;
-  * subspace rotation requires equal occupations (otherwise rho changes).
+  * subspace rotation requires equal occupations (otherwise rho changes);
+  * the test "mod(l, n_diag) = 0" of Algorithm M is read with the index of the
+    iteration that produced W^(l+1), before the increment: with the reading
+    after the increment, an even n_diag and n_org = 2 (the setting of Fig. 2)
+    would never rotate, since orthonormalising steps then end on odd indices.
 
 Parity: trajectory values have no published reference (the paper prints none
 for a reproducible system): "parity unpinned" for the tau / s / E sequences
@@ -190,7 +195,7 @@ class AlgorithmM:
         df = abs(E_old - self.E) / (abs(E_old) + 1.0)
         self.df_hist.append(df)
         rotated = False
-        if p.n_diag > 0 and (self.l + 1) % p.n_diag == 0:
+        if p.n_diag > 0 and self.l % p.n_diag == 0:
             # the next BB step from the unrotated pair, then rotate
             self.tau_pending = self._bb_value(self.W - self.Wp, self.direction() - self.Zp,
                                               self.l + 1)

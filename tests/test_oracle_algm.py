@@ -161,12 +161,10 @@ def test_orthonormalise_every_n_org_steps_reaches_dense_minimum(n_org):
 def test_subspace_rotation_diagonalises_sigma_and_keeps_energy():
     sys_, cfg, w = _free_box(7, 43)
     A = algm.AlgorithmM(synth.orbitals(cfg), sys_, algm.Params(n_diag=3))
-    for _ in range(2):
-        A.step()
+    recs = [A.step() for _ in range(4)]
+    assert [r.rotated for r in recs] == [True, False, False, True]
     E_before = A.terms.E
     S_before = A.sigma_full()
-    r = A.step()   # produces iterate 3: rotated
-    assert r.rotated
     S = A.sigma_full()
     off = S - np.diag(np.diag(S))
     assert np.max(np.abs(off)) < 1e-12 * np.max(np.abs(S))
