@@ -91,6 +91,14 @@ typedef struct {
                        if it is missed, finish with CG preconditioned by that
                        inverse */
   unsigned terms;   /* energy-term mask, POU_TERM_*                              */
+  int n_org;        /* orthonormalise, test eq. "ene-de" and backtrack only when
+                       l mod n_org == 0; other iterations take the plain step
+                       W <- W - tau_BB Z (section 3.3, Algorithm M); <= 0 -> 1   */
+  int n_diag;       /* subspace diagonalisation of the new iterate after the
+                       orthonormalising step of iteration l when l mod n_diag
+                       == 0 (section 3.3; l counted before the increment):
+                       W <- W P, P^T <(HW)^T W> P diagonal; 0 = off.  Needs
+                       equal occupations                                        */
 } pou_params;
 
 typedef struct {
@@ -110,6 +118,10 @@ typedef struct {
   double df;        /* |E^(l) - E^(l+1)| / (|E^(l)| + 1)                          */
   double C, Q;      /* non-monotone reference values after the update            */
   double gram_dev;  /* max |G - I| of the first Gram of the accepted trial       */
+  int orthonormalized; /* 1: orthonormalising step with the energy test; 0: plain
+                          step (n_org > 1), whose E is that of the non-orthonormal
+                          iterate and whose df is NaN                            */
+  int rotated;      /* 1 if the new iterate was rotated by subspace diagonalisation */
 } pou_step_info;
 
 /* Fill *p with the paper's constants (rho1 = 1e-4, delta = 0.1, eta = 0.85;
@@ -160,6 +172,13 @@ pou_status pou_energy_backward(pou_ctx *ctx, const void *U, double gE, void *dU,
                                double *dR, double *dsigma);
 
 /* ---- diagnostics and utilities (same stream, same error model) ---------- */
+
+/* Norm of the Stiefel gradient of eq. "gra" (section 2.2) with the full
+   Lagrange multiplier: Sigma = <(H U)^T U> (H = H(rho(U)), U evaluated as by
+   pou_energy) and resid = sqrt(tr<R^T R>), R = H U - U Sigma, the residual
+   reported in section 4.1.  Sigma (host double [norb][norb], nullable)
+   receives the symmetrised Sigma.  U is not modified. */
+pou_status pou_residual(pou_ctx *ctx, const void *U, double *resid, double *Sigma);
 
 /* H U for the potentials of the last pou_energy / step evaluation; also
    sigma_ii = <u_i, H u_i> into sigma (host, nullable, [norb]). */

@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
                 ("bb_mode", ctypes.c_int), ("tau_init", ctypes.c_double), ("s_max", ctypes.c_int),
                 ("orth_passes", ctypes.c_int), ("cg_rtol", ctypes.c_double),
                 ("cg_maxit", ctypes.c_int), ("cg_precond", ctypes.c_int),
-                ("terms", ctypes.c_uint)]
+                ("terms", ctypes.c_uint), ("n_org", ctypes.c_int), ("n_diag", ctypes.c_int)]
 
 
 class EnergyTerms(ctypes.Structure):
@@ -54,7 +54,8 @@ class StepInfo(ctypes.Structure):
     _fields_ = [("l", ctypes.c_int), ("s", ctypes.c_int), ("accepted", ctypes.c_int),
                 ("cg_iters", ctypes.c_int), ("E", ctypes.c_double), ("tau_bb", ctypes.c_double),
                 ("tau", ctypes.c_double), ("zz", ctypes.c_double), ("df", ctypes.c_double),
-                ("C", ctypes.c_double), ("Q", ctypes.c_double), ("gram_dev", ctypes.c_double)]
+                ("C", ctypes.c_double), ("Q", ctypes.c_double), ("gram_dev", ctypes.c_double),
+                ("orthonormalized", ctypes.c_int), ("rotated", ctypes.c_int)]
 
 
 _LIB = None
@@ -68,6 +69,7 @@ _SIGNATURES = {
     "pou_set_system": (_i, [_vp, ctypes.POINTER(Grid), _i, _dp, _dp, _dp, _i, _dp, _i,
                             ctypes.POINTER(Params)]),
     "pou_energy": (_i, [_vp, _vp, ctypes.POINTER(EnergyTerms)]),
+    "pou_residual": (_i, [_vp, _vp, _dp, _dp]),
     "pou_orthonormalize": (_i, [_vp, _vp, _dp]),
     "pou_orbital_update_step": (_i, [_vp, _vp, ctypes.POINTER(StepInfo)]),
     "pou_energy_backward": (_i, [_vp, _vp, _d, _vp, _vp, _vp]),
@@ -216,6 +218,13 @@ class System:
         info = StepInfo()
         self._check(lib().pou_orbital_update_step(self._h, self._block(U), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in StepInfo._fields_}
+
+    def residual(self, U):
+        """(||H U - U Sigma||, Sigma) with Sigma = <(H U)^T U> (eq. "gra")."""
+        r = ctypes.c_double(0.0)
+        S = np.zeros((self.N, self.N))
+        self._check(lib().pou_residual(self._h, self._block(U), ctypes.byref(r), _dptr(S)))
+        return r.value, S
 
     def hamiltonian(self, U):
         HU = self.torch.empty_like(U)

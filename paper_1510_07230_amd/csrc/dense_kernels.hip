@@ -1515,6 +1515,104 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   }
 }
 
+// ---------------------------------------------------------------- subspace rotation
+
+// Partial cross products C = A B^T over a contiguous range of grid points for
+// one 32 x 32 output tile (blockIdx.y = tile, row-major over the N x N
+// tiles): part[split][i][j] = sum_g A[i][g] B[j][g], FP64 accumulation.  A
+// plain tiled kernel: it serves the subspace diagonalisation and the
+// residual, which run every n_diag steps or on request.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cross_gram(const T *__restrict__ A,
+                                                       const T *__restrict__ B, int N, i64 ng,
+                                                       i64 kper, double *__restrict__ part) {
+  constexpr int TB = 32, KC = 32;
+  __shared__ double sa[TB][KC + 1];
+  __shared__ double sb[TB][KC + 1];
+  const int nt = (N + TB - 1) / TB;
+  const int ti = blockIdx.y / nt, tj = blockIdx.y % nt;
+  const int t = threadIdx.x;
+  const int ci = t / 8, cj0 = (t % 8) * 4;  // this thread: row ci, columns cj0 .. cj0 + 3
+  const i64 k_beg = (i64)blockIdx.x * kper;
+  const i64 k_end = min(ng, k_beg + kper);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
+    for (int e = t; e < TB * KC; e += kBlock) {
+      const int r = e / KC, k = e % KC;
+      const i64 g = k0 + k;
+      const int ia = TB * ti + r, jb = TB * tj + r;
+      sa[r][k] = (ia < N && g < k_end) ? (double)A[(i64)ia * ng + g] : 0.0;
+      sb[r][k] = (jb < N && g < k_end) ? (double)B[(i64)jb * ng + g] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < KC; ++k) {
+      const double a = sa[ci][k];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += a * sb[cj0 + u][k];
+    }
+    __syncthreads();
+  }
+  const int i = TB * ti + ci;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = TB * tj + cj0 + u;
+    if (i < N && j < N) part[((i64)blockIdx.x * N + i) * N + j] = acc[u];
+  }
+}
+
+// S_ij = dv/2 sum over splits (part_ij + part_ji): the symmetrised product.
+__global__ __launch_bounds__(kBlock) void k_cross_reduce(const double *__restrict__ part, int N,
+                                                         int nsplit, double dv,
+                                                         double *__restrict__ S) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+    const int i = e / N, j = e % N;
+    double a = 0.0, b = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+      a += part[((i64)sp * N + i) * N + j];
+      b += part[((i64)sp * N + j) * N + i];
+    }
+    S[e] = 0.5 * dv * (a + b);
+  }
+}
+
+// out[j][g] = sum_i P[i][j] X[i][g] (out = P^T X, i.e. the block X times P in
+// the orbital index), FP64 accumulation.  Thread: one grid point, 16 output
+// orbitals; P's 16 columns staged in LDS in chunks of 64 rows.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rotate(const double *__restrict__ P,
+                                                   const T *__restrict__ X, T *__restrict__ out,
+                                                   int N, i64 ng) {
+  constexpr int JB = 16, IC = 64;
+  __shared__ double sp[IC][JB];
+  const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.y * JB;
+  double acc[JB];
+#pragma unroll
+  for (int u = 0; u < JB; ++u) acc[u] = 0.0;
+  for (int i0 = 0; i0 < N; i0 += IC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < IC * JB; e += blockDim.x) {
+      const int i = i0 + e / JB, j = j0 + e % JB;
+      sp[e / JB][e % JB] = (i < N && j < N) ? P[(i64)i * N + j] : 0.0;
+    }
+    __syncthreads();
+    if (g < ng) {
+      const int ie = min(IC, N - i0);
+      for (int ii = 0; ii < ie; ++ii) {
+        const double x = (double)X[(i64)(i0 + ii) * ng + g];
+#pragma unroll
+        for (int u = 0; u < JB; ++u) acc[u] += sp[ii][u] * x;
+      }
+    }
+  }
+  if (g < ng) {
+#pragma unroll
+    for (int u = 0; u < JB; ++u)
+      if (j0 + u < N) out[(i64)(j0 + u) * ng + g] = (T)acc[u];
+  }
+}
+
 // G = dv * sum over splits of the 128 x 128 partial upper triangles; both
 // halves.  Lane = element (coalesced over the 128 x 128 partial), the four
 // waves of a workgroup take every fourth split and combine through LDS.
@@ -1786,5 +1884,45 @@ template hipError_t launch_apply_lower<double>(const double *, const double *, c
 template hipError_t launch_apply_lower<float>(const double *, const float *, const float *,
                                               float *, int, i64, const double *, double *,
                                               hipStream_t);
+
+
+int cross_gram_split(int N) {
+  const i64 per = (i64)N * N;
+  i64 sp = (i64)(32 << 20) / (per * 8);  // at most 32 MiB of partials
+  if (sp > 64) sp = 64;
+  if (sp < 1) sp = 1;
+  return (int)sp;
+}
+
+template <typename T>
+hipError_t launch_cross_gram(const T *A, const T *B, int N, i64 ng, double dv, double *part,
+                             double *S, hipStream_t s) {
+  const int nsplit = cross_gram_split(N);
+  i64 kper = (ng + nsplit - 1) / nsplit;
+  kper = ((kper + 31) / 32) * 32;
+  const int nt = (N + 31) / 32;
+  hipLaunchKernelGGL(k_cross_gram<T>, dim3(nsplit, nt * nt), dim3(kBlock), 0, s, A, B, N, ng, kper,
+                     part);
+  int blocks = (N * N + kBlock - 1) / kBlock;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_cross_reduce, dim3(blocks), dim3(kBlock), 0, s, part, N, nsplit, dv, S);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rotate(const double *P, const T *X, T *out, int N, i64 ng, hipStream_t s) {
+  dim3 grid((unsigned)((ng + kBlock - 1) / kBlock), (unsigned)((N + 15) / 16));
+  hipLaunchKernelGGL(k_rotate<T>, grid, dim3(kBlock), 0, s, P, X, out, N, ng);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cross_gram<double>(const double *, const double *, int, i64, double,
+                                              double *, double *, hipStream_t);
+template hipError_t launch_cross_gram<float>(const float *, const float *, int, i64, double,
+                                             double *, double *, hipStream_t);
+template hipError_t launch_rotate<double>(const double *, const double *, double *, int, i64,
+                                          hipStream_t);
+template hipError_t launch_rotate<float>(const double *, const float *, float *, int, i64,
+                                         hipStream_t);
 
 }  // namespace pou

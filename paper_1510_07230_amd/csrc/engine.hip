@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <iterator>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -83,6 +84,7 @@ struct pou_ctx {
   float *d_D32 = nullptr;
   double *d_cholws = nullptr;  // blocked Cholesky tiles when N > 128
   double *d_red = nullptr;     // small reduction outputs
+  double *d_S = nullptr, *d_P = nullptr, *d_xpart = nullptr;  // subspace rotation / residual
   double *d_scal = nullptr;    // (tau_BB, zz, ss, sy, yy) of the current step
   double *d_rep[2] = {nullptr, nullptr};  // evaluation reports (current, trial)
   void *d_HW = nullptr, *d_HWt = nullptr, *d_Wt = nullptr, *d_W1 = nullptr, *d_W2 = nullptr;
@@ -167,6 +169,7 @@ void free_all(pou_ctx *c) {
   c->d_fft0 = c->d_fft1 = nullptr;
   c->d_sc = c->d_part = c->d_gpart = c->d_G = c->d_Minv = c->d_Minv2 = c->d_Mcomb = nullptr;
   c->d_red = nullptr;
+  c->d_S = c->d_P = c->d_xpart = nullptr;
   c->d_scal = nullptr;
   c->d_D64 = nullptr;
   c->d_D32 = nullptr;
@@ -507,6 +510,126 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
   return POU_OK;
 }
 
+// ------------------------------------------------------------------ subspace rotation
+
+template <typename T>
+pou_status energy_impl(pou_ctx *c, const T *U, pou_energy_terms *out);
+
+// Eigen-decomposition of a symmetric N x N matrix (row-major A, destroyed) by
+// cyclic Jacobi rotations: A V = V diag(w), w ascending, V orthogonal with
+// each column's largest-magnitude entry positive.  Sweeps end when the
+// off-diagonal mass falls to rounding level; near-diagonal input (the usual
+// case after earlier rotations) takes two or three sweeps.
+void jacobi_eigh(int N, std::vector<double> &A, std::vector<double> &V, std::vector<double> &w) {
+  V.assign((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i) V[(size_t)i * N + i] = 1.0;
+  auto a = [&](int i, int j) -> double & { return A[(size_t)i * N + j]; };
+  double fro = 0.0;
+  for (double x : A) fro += x * x;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) off += a(i, j) * a(i, j);
+    if (off <= 1e-32 * fro || off == 0.0) break;
+    for (int pp = 0; pp < N - 1; ++pp) {
+      for (int qq = pp + 1; qq < N; ++qq) {
+        const double apq = a(pp, qq);
+        if (apq == 0.0) continue;
+        const double theta = (a(qq, qq) - a(pp, pp)) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        // A <- J^T A J with J the rotation in the (pp, qq) plane
+        for (int k = 0; k < N; ++k) {
+          const double akp = a(k, pp), akq = a(k, qq);
+          a(k, pp) = cs * akp - sn * akq;
+          a(k, qq) = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double apk = a(pp, k), aqk = a(qq, k);
+          a(pp, k) = cs * apk - sn * aqk;
+          a(qq, k) = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < N; ++k) {
+          double &vkp = V[(size_t)k * N + pp], &vkq = V[(size_t)k * N + qq];
+          const double x = vkp, y = vkq;
+          vkp = cs * x - sn * y;
+          vkq = sn * x + cs * y;
+        }
+      }
+    }
+  }
+  std::vector<int> ord(N);
+  for (int i = 0; i < N; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
+  std::vector<double> V2((size_t)N * N);
+  w.resize(N);
+  for (int jn = 0; jn < N; ++jn) {
+    const int jo = ord[jn];
+    w[jn] = a(jo, jo);
+    int imax = 0;
+    for (int i = 1; i < N; ++i)
+      if (std::fabs(V[(size_t)i * N + jo]) > std::fabs(V[(size_t)imax * N + jo])) imax = i;
+    const double sg = V[(size_t)imax * N + jo] < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < N; ++i) V2[(size_t)i * N + jn] = sg * V[(size_t)i * N + jo];
+  }
+  V.swap(V2);
+}
+
+// Subspace diagonalisation of the current iterate (section 3.3): Sigma =
+// <(H W)^T W> (symmetrised), P^T Sigma P = Gamma, W <- W P and H W <- (H W) P,
+// sigma_ii <- <(H W)_i, W_i>, and ||Z||^2 of the rotated iterate into the step
+// scalars (the BB step already computed for the next iteration is kept: its
+// traces are invariant under the rotation).
+template <typename T>
+pou_status rotate_subspace(pou_ctx *c, T *W) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  KL(POU_K_OTHER, pou::launch_cross_gram<T>((const T *)c->d_HW, (const T *)W, N, c->ng, c->dv,
+                                            c->d_xpart, c->d_S, s));
+  std::vector<double> A((size_t)N * N), V, w;
+  CHK(sync_read(c, A.data(), c->d_S, sizeof(double) * A.size()));
+  for (double x : A)
+    if (!std::isfinite(x)) return fail(c, POU_ERR_NONFINITE, "subspace matrix is not finite");
+  jacobi_eigh(N, A, V, w);
+  HIPCHK(c, hipMemcpyAsync(c->d_P, V.data(), sizeof(double) * V.size(), hipMemcpyHostToDevice, s));
+  KL(POU_K_OTHER, pou::launch_rotate<T>(c->d_P, (const T *)W, (T *)c->d_W2, N, c->ng, s));
+  HIPCHK(c, hipMemcpyAsync(W, c->d_W2, sizeof(T) * (size_t)N * c->ng, hipMemcpyDeviceToDevice, s));
+  KL(POU_K_OTHER, pou::launch_rotate<T>(c->d_P, (const T *)c->d_HW, (T *)c->d_HWt, N, c->ng, s));
+  std::swap(c->d_HW, c->d_HWt);
+  // sigma of the rotated iterate into the report of the current iterate
+  KL(POU_K_OTHER, pou::launch_rowdot<T>((const T *)c->d_HW, (const T *)W, false, c->d_part, N,
+                                        c->ng, c->nblk_orb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_rep[0], N, c->nblk_orb, 1, c->dv, s));
+  KL(POU_K_OTHER, pou::launch_zz<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_part, N, c->ng,
+                                    c->nblk_orb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
+  KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, 3, c->p.tau_init, c->d_scal, nullptr, s));
+  c->eval_HU = c->d_HW;
+  return POU_OK;
+}
+
+// Norm of the Stiefel gradient H U - U Sigma with Sigma = <(H U)^T U>.
+template <typename T>
+pou_status residual_impl(pou_ctx *c, const T *U, double *resid, double *Sigma) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  if (c->eval_ptr != U) CHK(energy_impl<T>(c, U, nullptr));
+  const T *HU = (const T *)c->eval_HU;
+  KL(POU_K_OTHER, pou::launch_cross_gram<T>(HU, U, N, c->ng, c->dv, c->d_xpart, c->d_S, s));
+  KL(POU_K_OTHER, pou::launch_rotate<T>(c->d_S, U, (T *)c->d_Wt, N, c->ng, s));
+  KL(POU_K_OTHER, pou::launch_rowdot<T>(HU, (const T *)c->d_Wt, true, c->d_part, N, c->ng,
+                                        c->nblk_orb, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
+  std::vector<double> r(N);
+  CHK(sync_read(c, r.data(), c->d_red, sizeof(double) * N));
+  double acc = 0.0;
+  for (double x : r) acc += x;
+  if (!std::isfinite(acc)) return fail(c, POU_ERR_NONFINITE, "residual is not finite");
+  if (resid) *resid = std::sqrt(acc);
+  if (Sigma) CHK(sync_read(c, Sigma, c->d_S, sizeof(double) * (size_t)N * N));
+  return POU_OK;
+}
+
 // ------------------------------------------------------------------ step
 template <typename T>
 pou_status restart(pou_ctx *c, const T *W) {
@@ -552,6 +675,69 @@ pou_status enqueue_accept(pou_ctx *c, T *W, const double *gate) {
   return POU_OK;
 }
 
+// A step of Algorithm M with l mod n_org != 0 (section 3.3): the plain
+// W <- W - tau_BB Z, no orthonormalisation, no energy test, no backtracking.
+// H(rho(W)) of the new iterate is still formed (for the next direction) and
+// the accept kernel updates U and the BB history as after any step; C, Q and
+// the energy of the last orthonormal iterate are left alone.
+template <typename T>
+pou_status plain_step(pou_ctx *c, T *W, pou_step_info *info) {
+  hipStream_t s = c->stream;
+  const int N = c->N;
+  const int RS = Report::size(N);
+  double *rep_t = c->d_rep[1];
+  double *hrep = c->h_step, *hscal = c->h_step + RS;
+  KL(POU_K_TRIAL, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, 1.0,
+                                       (T *)c->d_W2, N, c->ng, s));
+  int it = 0;
+  CHK(evaluate<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, false, &it));
+  HIPCHK(c, hipMemcpyAsync(hrep, rep_t, sizeof(double) * RS, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(hscal, c->d_scal, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  prof_drain(c);
+  const double tau_bb = hscal[0], zz = hscal[1];
+  const double rr = hrep[Report::rr(N)], bb = hrep[Report::rr(N) + 1];
+  if (!std::isfinite(rr) || !std::isfinite(bb))
+    return fail(c, POU_ERR_NONFINITE, "Poisson right-hand side or residual is not finite");
+  std::vector<double> &r = c->rep_host;
+  r.assign(hrep, hrep + RS);
+  if (rr > c->p.cg_rtol * c->p.cg_rtol * bb) {
+    int more = 0;
+    CHK(poisson(c, c->d_rho, c->d_vh, c->p.cg_rtol, c->p.cg_maxit, true, &more));
+    it += more;
+    c->last_cg_iters = it;
+    CHK(potentials_and_h<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t));
+    CHK(sync_read(c, r.data(), rep_t, sizeof(double) * RS));
+  }
+  pou_energy_terms et{};
+  terms_from_report(c, r.data(), &et);
+  if (!std::isfinite(et.E)) return fail(c, POU_ERR_NONFINITE, "energy of the plain step is not finite");
+  CHK(enqueue_accept<T>(c, W, nullptr));
+  std::swap(c->d_HW, c->d_HWt);
+  std::swap(c->d_rep[0], c->d_rep[1]);
+  c->hist = true;
+  c->eval_ptr = W;
+  c->eval_HU = c->d_HW;
+  if (info) {
+    info->l = c->l;
+    info->s = 0;
+    info->accepted = 1;
+    info->cg_iters = it;
+    info->E = et.E;
+    info->tau_bb = tau_bb;
+    info->tau = tau_bb;
+    info->zz = zz;
+    info->df = std::numeric_limits<double>::quiet_NaN();
+    info->C = c->C;
+    info->Q = c->Q;
+    info->gram_dev = 0.0;
+    info->orthonormalized = 0;
+    info->rotated = 0;
+  }
+  c->l = c->l + 1;
+  return POU_OK;
+}
+
 // One iteration of Algorithm M.  tau_BB and ||Z||^2 of the current iterate
 // live on the device (d_scal); the trial kernels read tau = tau_BB * delta^s
 // from there.  After each trial the test of eq. "ene-de" runs on the device
@@ -565,6 +751,7 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
   hipStream_t s = c->stream;
   const int N = c->N;
   if (W != c->last_U || !c->cur_valid) CHK(restart<T>(c, W));
+  if (c->p.n_org > 1 && c->l % c->p.n_org != 0) return plain_step<T>(c, W, info);
   const int passes = c->p.orth_passes;
   const int RS = Report::size(N);
   double *hrep = c->h_step, *hscal = c->h_step + RS, *hflag = c->h_step + RS + 5;
@@ -652,7 +839,15 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
   c->hist = true;
   c->eval_ptr = W;
   c->eval_HU = c->d_HW;
+  // subspace diagonalisation of the new iterate after iteration l, l mod n_diag == 0
+  bool rotated = false;
+  if (c->p.n_diag > 0 && c->l % c->p.n_diag == 0) {
+    CHK(rotate_subspace<T>(c, W));
+    rotated = true;
+  }
   if (info) {
+    info->orthonormalized = 1;
+    info->rotated = rotated ? 1 : 0;
     info->l = c->l;
     info->s = s_acc;
     info->accepted = accepted ? 1 : 0;
@@ -797,6 +992,8 @@ void pou_default_params(pou_params *p) {
   p->cg_maxit = 0;
   p->cg_precond = 1;
   p->terms = POU_TERM_ALL;
+  p->n_org = 1;
+  p->n_diag = 0;
 }
 
 pou_status pou_create(pou_ctx **out, int device, void *hip_stream) {
@@ -864,10 +1061,15 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   if (p.orth_passes <= 0) p.orth_passes = (prec == POU_FP64) ? 1 : 2;
   if (p.cg_rtol <= 0.0) p.cg_rtol = 1e-12;
   if (p.cg_maxit <= 0) p.cg_maxit = 2000;
+  if (p.n_org <= 0) p.n_org = 1;
   if (!(p.delta > 0.0 && p.delta < 1.0) || !(p.rho1 >= 0.0) || !(p.eta >= 0.0 && p.eta <= 1.0) ||
       p.s_max < 0 || p.s_max > 60 || p.orth_passes > 2 || p.bb_mode < 0 || p.bb_mode > 2 ||
-      !std::isfinite(p.tau_init))
+      !std::isfinite(p.tau_init) || p.n_diag < 0)
     return fail(c, POU_ERR_ARG, "bad algorithm parameters");
+  if (p.n_diag > 0)
+    for (int i = 1; i < norb; ++i)
+      if (occ[i] != occ[0])
+        return fail(c, POU_ERR_ARG, "subspace diagonalisation (n_diag > 0) needs equal occupations");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, POU_ERR_HIP, "hipSetDevice failed");
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_all(c);
@@ -935,6 +1137,10 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   if (pou::chol_workspace_doubles(norb) > 0)
     CHK(dalloc(c, &c->d_cholws, sizeof(double) * pou::chol_workspace_doubles(norb)));
   CHK(dalloc(c, &c->d_G, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_S, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_P, sizeof(double) * (size_t)norb * norb));
+  CHK(dalloc(c, &c->d_xpart,
+             sizeof(double) * (size_t)pou::cross_gram_split(norb) * norb * norb));
   CHK(dalloc(c, &c->d_Minv, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Minv2, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Mcomb, sizeof(double) * (size_t)norb * norb));
@@ -999,6 +1205,13 @@ pou_status pou_energy(pou_ctx *c, const void *U, pou_energy_terms *out) {
   if (!U) return fail(c, POU_ERR_ARG, "null U");
   if (c->prec == POU_FP64) return energy_impl<double>(c, (const double *)U, out);
   return energy_impl<float>(c, (const float *)U, out);
+}
+
+pou_status pou_residual(pou_ctx *c, const void *U, double *resid, double *Sigma) {
+  NEED_SYSTEM(c);
+  if (!U) return fail(c, POU_ERR_ARG, "null U");
+  if (c->prec == POU_FP64) return residual_impl<double>(c, (const double *)U, resid, Sigma);
+  return residual_impl<float>(c, (const float *)U, resid, Sigma);
 }
 
 pou_status pou_orthonormalize(pou_ctx *c, void *U, double *orth_err) {

@@ -792,6 +792,25 @@ __global__ __launch_bounds__(kBlock) void k_zz(const T *__restrict__ W, const T 
   if (threadIdx.x == 0) part[(i64)orb * gridDim.x + blockIdx.x] = v[0];
 }
 
+// Per (orbital, block) partials of <a_i, b_i> (diff == 0) or of
+// |a_i - b_i|^2 (diff != 0), FP64 accumulation.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rowdot(const T *__restrict__ A, const T *__restrict__ B,
+                                                   int diff, double *__restrict__ part, i64 ng) {
+  __shared__ double red[4];
+  const int orb = blockIdx.y;
+  const i64 off = (i64)orb * ng;
+  double acc = 0.0;
+  for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (i64)gridDim.x * blockDim.x) {
+    const double a = (double)A[off + g], b = (double)B[off + g];
+    acc += diff ? (a - b) * (a - b) : a * b;
+  }
+  double v[1] = {acc};
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) part[(i64)orb * gridDim.x + blockIdx.x] = v[0];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_backward_scale(const T *__restrict__ HU,
                                                            const double *__restrict__ occ,
@@ -836,7 +855,7 @@ __global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, i
   double ss = 0.0, sy = 0.0, yy = 0.0, zz = 0.0;
   // lane l sums orbitals l, l + 64, ...; the wave then combines in a fixed order
   for (int i = l; i < N; i += 64) {
-    if (mode == 0) {
+    if (mode == 0 || mode == 3) {
       zz += red[i];
     } else {
       ss += red[i];
@@ -850,6 +869,10 @@ __global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, i
   yy = wave_sum(yy);
   zz = wave_sum(zz);
   if (l != 0) return;
+  if (mode == 3) {  // ||Z||^2 only (after a subspace rotation); tau_BB is kept
+    out[1] = zz;
+    return;
+  }
   double tau = tau_init;
   if (mode != 0) {
     const double asy = fabs(sy);
@@ -1052,6 +1075,14 @@ hipError_t launch_zz(const T *W, const T *HW, const double *sig, double *part, i
 }
 
 template <typename T>
+hipError_t launch_rowdot(const T *A, const T *B, bool diff, double *part, int N, i64 ng, int nblk,
+                         hipStream_t s) {
+  dim3 grid(nblk, N);
+  hipLaunchKernelGGL(k_rowdot<T>, grid, dim3(kBlock), 0, s, A, B, diff ? 1 : 0, part, ng);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_backward_scale(const T *HU, const double *occ, double scale, T *dU, int N,
                                  i64 ng, hipStream_t s) {
   dim3 grid(grid_for(ng, 1024), N);
@@ -1119,6 +1150,8 @@ hipError_t launch_ion_forces(const double *atoms, int M, const double *vh, doubl
                                        const double *, hipStream_t);                        \
   template hipError_t launch_zz<T>(const T *, const T *, const double *, double *, int, i64, \
                                    int, hipStream_t);                                       \
+  template hipError_t launch_rowdot<T>(const T *, const T *, bool, double *, int, i64, int,   \
+                                       hipStream_t);                                        \
   template hipError_t launch_backward_scale<T>(const T *, const double *, double, T *, int, \
                                                i64, hipStream_t);                           \
   template hipError_t launch_nonfinite<T>(const T *, i64, int *, hipStream_t);

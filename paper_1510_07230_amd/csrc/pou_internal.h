@@ -138,7 +138,8 @@ template <typename T>
 hipError_t launch_trial(const T *W, const T *HW, const double *sig, const double *dtau,
                         double tscale, T *Wt, int N, i64 ng, hipStream_t s);
 // Barzilai-Borwein step on the device: out = (tau_BB, zz, ss, sy, yy); does
-// nothing when gate is non-null and gate[0] == 0
+// nothing when gate is non-null and gate[0] == 0.  mode 0: tau_init and the zz
+// of red[0..N); 1, 2: tau1 / tau2 from red[0..4N); 3: only out[1] = zz of red[0..N)
 hipError_t launch_bb_tau(const double *red, int N, int mode, double tau_init, double *out,
                          const double *gate, hipStream_t s);
 // device test of eq. "ene-de" for a trial report: ext[0..4] = scal, ext[5] = accept,
@@ -155,6 +156,10 @@ template <typename T>
 hipError_t launch_commit(T *U, const T *HW, const double *sig, const T *Wn, const T *HWn,
                          const double *sign, double *part, int N, i64 ng, int nblk,
                          const double *gate, hipStream_t s);
+// per (orbital, block) partials of <a_i, b_i> or, with diff, |a_i - b_i|^2
+template <typename T>
+hipError_t launch_rowdot(const T *A, const T *B, bool diff, double *part, int N, i64 ng, int nblk,
+                         hipStream_t s);
 // z.z partials for z = HW - sig W
 template <typename T>
 hipError_t launch_zz(const T *W, const T *HW, const double *sig, double *part, int N,
@@ -213,6 +218,16 @@ hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *
 size_t chol_workspace_doubles(int N);
 // doubles needed by the Gram partial buffer
 size_t gram_partial_doubles(int N, int nsplit);
+// ---- subspace rotation and residual (rare: every n_diag steps or on request)
+// splits of the cross product; its partial buffer holds split * N * N doubles
+int cross_gram_split(int N);
+// S = dv/2 (A B^T + B A^T) over the grid (A, B: [N][ng]); part: scratch
+template <typename T>
+hipError_t launch_cross_gram(const T *A, const T *B, int N, i64 ng, double dv, double *part,
+                             double *S, hipStream_t s);
+// out = P^T X in the orbital index: out[j] = sum_i P[i][j] X[i] (P: FP64 N x N)
+template <typename T>
+hipError_t launch_rotate(const double *P, const T *X, T *out, int N, i64 ng, hipStream_t s);
 // Number of K splits (workgroups) of the N <= 128 Gram kernels: as many as are
 // resident on the device at once, clamped to [256, 1024]; 0 for N > 128.
 int gram_split(int N, bool fp32);
