@@ -1518,46 +1518,61 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
 // ---------------------------------------------------------------- subspace rotation
 
 // Partial cross products C = A B^T over a contiguous range of grid points for
-// one 32 x 32 output tile (blockIdx.y = tile, row-major over the N x N
-// tiles): part[split][i][j] = sum_g A[i][g] B[j][g], FP64 accumulation.  A
-// plain tiled kernel: it serves the subspace diagonalisation and the
-// residual, which run every n_diag steps or on request.
+// one 64 x 64 output tile (blockIdx.y = tile, row-major over the N x N
+// tiles): part[split][i][j] = sum_g A[i][g] B[j][g], FP64 accumulation; each
+// thread keeps a 4 x 4 block of the tile.  A plain tiled kernel: it serves
+// the subspace diagonalisation and the residual, which run every n_diag
+// steps or on request.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cross_gram(const T *__restrict__ A,
                                                        const T *__restrict__ B, int N, i64 ng,
                                                        i64 kper, double *__restrict__ part) {
-  constexpr int TB = 32, KC = 32;
-  __shared__ double sa[TB][KC + 1];
-  __shared__ double sb[TB][KC + 1];
+  constexpr int TB = 64, KC = 32;
+  __shared__ double sa[KC][TB + 1];
+  __shared__ double sb[KC][TB + 1];
   const int nt = (N + TB - 1) / TB;
   const int ti = blockIdx.y / nt, tj = blockIdx.y % nt;
   const int t = threadIdx.x;
-  const int ci = t / 8, cj0 = (t % 8) * 4;  // this thread: row ci, columns cj0 .. cj0 + 3
+  const int r0 = 4 * (t / 16), c0 = 4 * (t % 16);  // this thread: rows r0.., columns c0..
   const i64 k_beg = (i64)blockIdx.x * kper;
   const i64 k_end = min(ng, k_beg + kper);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
   for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
     for (int e = t; e < TB * KC; e += kBlock) {
       const int r = e / KC, k = e % KC;
       const i64 g = k0 + k;
       const int ia = TB * ti + r, jb = TB * tj + r;
-      sa[r][k] = (ia < N && g < k_end) ? (double)A[(i64)ia * ng + g] : 0.0;
-      sb[r][k] = (jb < N && g < k_end) ? (double)B[(i64)jb * ng + g] : 0.0;
+      sa[k][r] = (ia < N && g < k_end) ? (double)A[(i64)ia * ng + g] : 0.0;
+      sb[k][r] = (jb < N && g < k_end) ? (double)B[(i64)jb * ng + g] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
     for (int k = 0; k < KC; ++k) {
-      const double a = sa[ci][k];
+      double a[4], b[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += a * sb[cj0 + u][k];
+      for (int u = 0; u < 4; ++u) {
+        a[u] = sa[k][r0 + u];
+        b[u] = sb[k][c0 + u];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
     }
     __syncthreads();
   }
-  const int i = TB * ti + ci;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int j = TB * tj + cj0 + u;
-    if (i < N && j < N) part[((i64)blockIdx.x * N + i) * N + j] = acc[u];
+  for (int x = 0; x < 4; ++x) {
+    const int i = TB * ti + r0 + x;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int j = TB * tj + c0 + y;
+      if (i < N && j < N) part[((i64)blockIdx.x * N + i) * N + j] = acc[x][y];
+    }
   }
 }
 
@@ -1889,7 +1904,7 @@ template hipError_t launch_apply_lower<float>(const double *, const float *, con
 int cross_gram_split(int N) {
   const i64 per = (i64)N * N;
   i64 sp = (i64)(32 << 20) / (per * 8);  // at most 32 MiB of partials
-  if (sp > 64) sp = 64;
+  if (sp > 256) sp = 256;
   if (sp < 1) sp = 1;
   return (int)sp;
 }
@@ -1900,7 +1915,7 @@ hipError_t launch_cross_gram(const T *A, const T *B, int N, i64 ng, double dv, d
   const int nsplit = cross_gram_split(N);
   i64 kper = (ng + nsplit - 1) / nsplit;
   kper = ((kper + 31) / 32) * 32;
-  const int nt = (N + 31) / 32;
+  const int nt = (N + 63) / 64;
   hipLaunchKernelGGL(k_cross_gram<T>, dim3(nsplit, nt * nt), dim3(kBlock), 0, s, A, B, N, ng, kper,
                      part);
   int blocks = (N * N + kBlock - 1) / kBlock;
