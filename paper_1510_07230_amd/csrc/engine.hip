@@ -515,64 +515,115 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
 template <typename T>
 pou_status energy_impl(pou_ctx *c, const T *U, pou_energy_terms *out);
 
-// Eigen-decomposition of a symmetric N x N matrix (row-major A, destroyed) by
-// cyclic Jacobi rotations: A V = V diag(w), w ascending, V orthogonal with
-// each column's largest-magnitude entry positive.  Sweeps end when the
-// off-diagonal mass falls to rounding level; near-diagonal input (the usual
-// case after earlier rotations) takes two or three sweeps.
-void jacobi_eigh(int N, std::vector<double> &A, std::vector<double> &V, std::vector<double> &w) {
-  V.assign((size_t)N * N, 0.0);
-  for (int i = 0; i < N; ++i) V[(size_t)i * N + i] = 1.0;
+// Eigen-decomposition of a symmetric N x N matrix (row-major A, destroyed):
+// A V = V diag(w), w ascending, V orthogonal with each column's largest-
+// magnitude entry positive.  Householder reduction to tridiagonal form
+// (A = Q T Q^T), then implicit symmetric QR steps with Wilkinson shifts on T
+// (deflating off-diagonals below rounding level), the plane rotations
+// accumulated into Q; all updates run along contiguous rows.
+void symm_eigh(int N, std::vector<double> &A, std::vector<double> &V, std::vector<double> &w) {
   auto a = [&](int i, int j) -> double & { return A[(size_t)i * N + j]; };
-  double fro = 0.0;
-  for (double x : A) fro += x * x;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int i = 0; i < N; ++i)
-      for (int j = i + 1; j < N; ++j) off += a(i, j) * a(i, j);
-    if (off <= 1e-32 * fro || off == 0.0) break;
-    for (int pp = 0; pp < N - 1; ++pp) {
-      for (int qq = pp + 1; qq < N; ++qq) {
-        const double apq = a(pp, qq);
-        if (apq == 0.0) continue;
-        const double theta = (a(qq, qq) - a(pp, pp)) / (2.0 * apq);
-        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        // A <- J^T A J with J the rotation in the (pp, qq) plane
-        for (int k = 0; k < N; ++k) {
-          const double akp = a(k, pp), akq = a(k, qq);
-          a(k, pp) = cs * akp - sn * akq;
-          a(k, qq) = sn * akp + cs * akq;
-        }
-        for (int k = 0; k < N; ++k) {
-          const double apk = a(pp, k), aqk = a(qq, k);
-          a(pp, k) = cs * apk - sn * aqk;
-          a(qq, k) = sn * apk + cs * aqk;
-        }
-        for (int k = 0; k < N; ++k) {
-          double &vkp = V[(size_t)k * N + pp], &vkq = V[(size_t)k * N + qq];
-          const double x = vkp, y = vkq;
-          vkp = cs * x - sn * y;
-          vkq = sn * x + cs * y;
-        }
+  std::vector<double> Mt((size_t)N * N, 0.0);  // rows: columns of the accumulated orthogonal factor
+  for (int i = 0; i < N; ++i) Mt[(size_t)i * N + i] = 1.0;
+  std::vector<double> v(N), p(N), wv(N);
+  // 1. A = Q T Q^T, Householder reflections on the trailing columns
+  for (int k = 0; k + 2 < N; ++k) {
+    const int m = N - k - 1;  // length of x = A[k+1 .., k]
+    double sigma = 0.0;
+    for (int i = 1; i < m; ++i) sigma += a(k + 1 + i, k) * a(k + 1 + i, k);
+    const double x0 = a(k + 1, k);
+    if (sigma == 0.0) continue;  // already tridiagonal in this column
+    const double mu = std::sqrt(x0 * x0 + sigma);
+    const double v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
+    const double beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+    v[0] = 1.0;
+    for (int i = 1; i < m; ++i) v[i] = a(k + 1 + i, k) / v0;
+    // p = beta * A22 v ; w = p - (beta p.v / 2) v
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      const double *row = &A[(size_t)(k + 1 + i) * N + k + 1];
+      for (int j = 0; j < m; ++j) acc += row[j] * v[j];
+      p[i] = beta * acc;
+    }
+    double pv = 0.0;
+    for (int i = 0; i < m; ++i) pv += p[i] * v[i];
+    for (int i = 0; i < m; ++i) wv[i] = p[i] - 0.5 * beta * pv * v[i];
+    for (int i = 0; i < m; ++i) {
+      double *row = &A[(size_t)(k + 1 + i) * N + k + 1];
+      for (int j = 0; j < m; ++j) row[j] -= v[i] * wv[j] + wv[i] * v[j];
+    }
+    a(k + 1, k) = mu;
+    a(k, k + 1) = mu;
+    for (int i = 1; i < m; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
+    // Mt <- H_k Mt (rows k+1 ..)
+    std::fill(p.begin(), p.end(), 0.0);  // p <- v^T Mt[k+1 .., :]
+    for (int i = 0; i < m; ++i) {
+      const double *row = &Mt[(size_t)(k + 1 + i) * N];
+      for (int j = 0; j < N; ++j) p[j] += v[i] * row[j];
+    }
+    for (int i = 0; i < m; ++i) {
+      double *row = &Mt[(size_t)(k + 1 + i) * N];
+      const double f = beta * v[i];
+      for (int j = 0; j < N; ++j) row[j] -= f * p[j];
+    }
+  }
+  std::vector<double> d(N), e(N, 0.0);
+  for (int i = 0; i < N; ++i) d[i] = a(i, i);
+  for (int i = 0; i + 1 < N; ++i) e[i] = a(i + 1, i);
+  // 2. implicit symmetric QR steps with Wilkinson shifts on T = tridiag(d, e)
+  const double eps = 2.220446049250313e-16;
+  int hi = N - 1, guard = 0;
+  while (hi > 0 && guard < 60 * N) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    if (lo > 0) e[lo - 1] = 0.0;
+    ++guard;
+    const double g = (d[hi - 1] - d[hi]) / (2.0 * e[hi - 1]);
+    const double r0 = std::hypot(g, 1.0);
+    const double mu = d[hi] - e[hi - 1] / (g + std::copysign(r0, g));
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      const double c = (r == 0.0) ? 1.0 : x / r, s = (r == 0.0) ? 0.0 : -z / r;
+      if (k > lo) e[k - 1] = r;
+      const double aa = d[k], bb = e[k], cc = d[k + 1];
+      d[k] = c * c * aa - 2.0 * c * s * bb + s * s * cc;
+      d[k + 1] = s * s * aa + 2.0 * c * s * bb + c * c * cc;
+      e[k] = c * s * aa + (c * c - s * s) * bb - c * s * cc;
+      if (k + 1 < hi) {
+        z = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      x = e[k];
+      double *rk = &Mt[(size_t)k * N], *rk1 = &Mt[(size_t)(k + 1) * N];
+      for (int j = 0; j < N; ++j) {
+        const double u = rk[j], t = rk1[j];
+        rk[j] = c * u - s * t;
+        rk1[j] = s * u + c * t;
       }
     }
   }
+  // eigenvalues ascending; column j of V = row of Mt; largest entry positive
   std::vector<int> ord(N);
   for (int i = 0; i < N; ++i) ord[i] = i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
-  std::vector<double> V2((size_t)N * N);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
+  V.assign((size_t)N * N, 0.0);
   w.resize(N);
   for (int jn = 0; jn < N; ++jn) {
     const int jo = ord[jn];
-    w[jn] = a(jo, jo);
+    w[jn] = d[jo];
+    const double *row = &Mt[(size_t)jo * N];
     int imax = 0;
     for (int i = 1; i < N; ++i)
-      if (std::fabs(V[(size_t)i * N + jo]) > std::fabs(V[(size_t)imax * N + jo])) imax = i;
-    const double sg = V[(size_t)imax * N + jo] < 0.0 ? -1.0 : 1.0;
-    for (int i = 0; i < N; ++i) V2[(size_t)i * N + jn] = sg * V[(size_t)i * N + jo];
+      if (std::fabs(row[i]) > std::fabs(row[imax])) imax = i;
+    const double sg = row[imax] < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < N; ++i) V[(size_t)i * N + jn] = sg * row[i];
   }
-  V.swap(V2);
 }
 
 // Subspace diagonalisation of the current iterate (section 3.3): Sigma =
@@ -590,7 +641,7 @@ pou_status rotate_subspace(pou_ctx *c, T *W) {
   CHK(sync_read(c, A.data(), c->d_S, sizeof(double) * A.size()));
   for (double x : A)
     if (!std::isfinite(x)) return fail(c, POU_ERR_NONFINITE, "subspace matrix is not finite");
-  jacobi_eigh(N, A, V, w);
+  symm_eigh(N, A, V, w);
   HIPCHK(c, hipMemcpyAsync(c->d_P, V.data(), sizeof(double) * V.size(), hipMemcpyHostToDevice, s));
   KL(POU_K_OTHER, pou::launch_rotate<T>(c->d_P, (const T *)W, (T *)c->d_W2, N, c->ng, s));
   HIPCHK(c, hipMemcpyAsync(W, c->d_W2, sizeof(T) * (size_t)N * c->ng, hipMemcpyDeviceToDevice, s));
