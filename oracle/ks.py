@@ -27,6 +27,9 @@ Potentials:
   * Exchange (section 2.1 eps_xc, LDA as in section 4; exchange only):
     E_x = -C_x h^3 sum rho^(4/3),  v_x = -(3/pi)^(1/3) rho^(1/3),
     C_x = 3/4 (3/pi)^(1/3).
+  * Correlation, opt in with TERM_CORR (the LDA of section 4 cites the
+    Perdew-Zunger parametrisation): E_c = h^3 sum rho eps_c(r_s), v_c =
+    d(rho eps_c)/d rho, spin-unpolarised; see correlation_density().
 
 Parity: every function here is pinned by CPU tests (closed forms, continuum
 limits, brute force, finite differences); see tests/test_oracle_ks.py.
@@ -42,6 +45,8 @@ FD8 = (-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0)
 
 TERM_KIN, TERM_EXT, TERM_HARTREE, TERM_XC = 1, 2, 4, 8
 TERM_ALL = TERM_KIN | TERM_EXT | TERM_HARTREE | TERM_XC
+# LDA correlation (Perdew-Zunger form, spin-unpolarised): opt in, not part of TERM_ALL
+TERM_CORR = 16
 
 CX = 0.75 * (3.0 / np.pi) ** (1.0 / 3.0)
 VX = (3.0 / np.pi) ** (1.0 / 3.0)
@@ -160,6 +165,41 @@ def exchange(rho, h):
     return ex, vx
 
 
+# Perdew-Zunger fit of the correlation energy per electron of the uniform
+# electron gas (spin-unpolarised), the LDA of section 4 (ref. PeZu):
+#   r_s >= 1:  eps_c = G / (1 + B1 sqrt(r_s) + B2 r_s)
+#   r_s <  1:  eps_c = A ln r_s + B + C r_s ln r_s + D r_s
+# with r_s = (3 / (4 pi rho))^(1/3); the potential is d(rho eps_c)/d rho =
+# eps_c - (r_s / 3) d eps_c / d r_s.
+PZ_G, PZ_B1, PZ_B2 = -0.1423, 1.0529, 0.3334
+PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116
+
+
+def correlation_density(rho):
+    """(eps_c, v_c) pointwise; both vanish where rho <= 0."""
+    rho = np.asarray(rho, dtype=np.float64)
+    pos = rho > 0.0
+    rs = np.where(pos, np.cbrt(3.0 / (4.0 * np.pi * np.where(pos, rho, 1.0))), 1.0)
+    sq = np.sqrt(rs)
+    den = 1.0 + PZ_B1 * sq + PZ_B2 * rs
+    eps_hi = PZ_G / den
+    # -(r_s/3) d eps/d r_s = eps * (B1 sqrt(r_s)/2 + B2 r_s) / (3 den)
+    v_hi = eps_hi + eps_hi * (0.5 * PZ_B1 * sq + PZ_B2 * rs) / (3.0 * den)
+    lr = np.log(rs)
+    eps_lo = PZ_A * lr + PZ_B + PZ_C * rs * lr + PZ_D * rs
+    # d eps/d r_s = A / r_s + C (ln r_s + 1) + D
+    v_lo = eps_lo - (PZ_A + PZ_C * rs * (lr + 1.0) + PZ_D * rs) / 3.0
+    eps = np.where(rs >= 1.0, eps_hi, eps_lo)
+    v = np.where(rs >= 1.0, v_hi, v_lo)
+    return np.where(pos, eps, 0.0), np.where(pos, v, 0.0)
+
+
+def correlation(rho, h):
+    """LDA correlation: (E_c, v_c) = (h^3 sum rho eps_c, d(rho eps_c)/d rho)."""
+    eps, v = correlation_density(rho)
+    return float(h ** 3 * np.sum(np.maximum(rho, 0.0) * eps)), v
+
+
 # ---------------------------------------------------------------- energy, H
 
 @dataclasses.dataclass
@@ -169,10 +209,11 @@ class EnergyTerms:
     E_ext: float
     E_H: float
     E_x: float
+    E_c: float = 0.0
 
 
 def potentials(U, sys: System, vext=None):
-    """(rho, V_H, v_x, V_eff, E_x) for orbitals U [N, n, n, n]."""
+    """(rho, V_H, v_xc, V_eff, E_x, V_ext, E_c) for orbitals U [N, n, n, n]."""
     h = sys.h
     rho = density(U, sys.occ)
     zeros = np.zeros_like(rho)
@@ -181,30 +222,34 @@ def potentials(U, sys: System, vext=None):
         ex, vx = exchange(rho, h)
     else:
         ex, vx = 0.0, zeros
+    ec = 0.0
+    if sys.terms & TERM_CORR:
+        ec, vc = correlation(rho, h)
+        vx = vx + vc
     if vext is None:
         vext = external_potential(sys) if sys.terms & TERM_EXT else zeros
     veff = vx + VH + vext
     if not sys.terms & TERM_EXT:
         veff = vx + VH
-    return rho, VH, vx, veff, ex, vext
+    return rho, VH, vx, veff, ex, vext, ec
 
 
 def energy(U, sys: System, vext=None) -> EnergyTerms:
     """Total energy, eq. "energy" of section 2.1, on the grid."""
     h = sys.h
-    rho, VH, vx, veff, ex, vext = potentials(U, sys, vext)
+    rho, VH, vx, veff, ex, vext, ec = potentials(U, sys, vext)
     ekin = 0.0
     if sys.terms & TERM_KIN:
         ekin = float(np.sum(sys.occ * inner(U, kinetic(U, h), h)))
     eext = float(inner(rho, vext, h)) if sys.terms & TERM_EXT else 0.0
     eh = float(0.5 * inner(rho, VH, h)) if sys.terms & TERM_HARTREE else 0.0
-    E = ekin + eext + eh + ex
-    return EnergyTerms(E, ekin, eext, eh, float(ex))
+    E = ekin + eext + eh + ex + ec
+    return EnergyTerms(E, ekin, eext, eh, float(ex), float(ec))
 
 
 def hamiltonian_apply(U, sys: System, vext=None):
     """H(rho) u_i = K u_i + V_eff u_i  (section 2.1), rho from U itself."""
-    _, _, _, veff, _, _ = potentials(U, sys, vext)
+    _, _, _, veff, _, _, _ = potentials(U, sys, vext)
     out = veff[None] * U
     if sys.terms & TERM_KIN:
         out = out + kinetic(U, sys.h)
@@ -268,12 +313,12 @@ def orth_error(W, h):
 def energy_and_h(U, sys: System, vext=None):
     """(EnergyTerms, H U, sigma_ii = <u_i, H u_i>) from one set of potentials."""
     h = sys.h
-    rho, VH, vx, veff, ex, vext = potentials(U, sys, vext)
+    rho, VH, vx, veff, ex, vext, ec = potentials(U, sys, vext)
     KU = kinetic(U, h) if sys.terms & TERM_KIN else np.zeros_like(U)
     ekin = float(np.sum(sys.occ * inner(U, KU, h)))
     eext = float(inner(rho, vext, h)) if sys.terms & TERM_EXT else 0.0
     eh = float(0.5 * inner(rho, VH, h)) if sys.terms & TERM_HARTREE else 0.0
-    terms = EnergyTerms(ekin + eext + eh + ex, ekin, eext, eh, float(ex))
+    terms = EnergyTerms(ekin + eext + eh + ex + ec, ekin, eext, eh, float(ex), float(ec))
     HU = KU + veff[None] * U
     sigma = inner(U, HU, h)
     return terms, HU, sigma

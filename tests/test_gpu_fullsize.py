@@ -22,7 +22,7 @@ def setup():
 def test_fullsize_energy_fields_and_sampled_hamiltonian(setup):
     cfg, so, W = setup
     print("[full] energy + fields + sampled H u", flush=True)
-    rho, VH, vx, veff, ex, vext = ks.potentials(W, so)
+    rho, VH, vx, veff, ex, vext, _ = ks.potentials(W, so)
     terms = ks.energy(W, so, vext)
     g = gpu_system(cfg, "fp64")
     U = g.new_block(W)

@@ -36,7 +36,7 @@ def test_fields_energy_hamiltonian(cfg):
     g = gpu_system(cfg)
     U = g.new_block(W)
     e = g.energy(U)
-    rho, VH, vx, veff, ex, vext = ks.potentials(W, so)
+    rho, VH, vx, veff, ex, vext, _ = ks.potentials(W, so)
     terms = ks.energy(W, so, vext)
     f = g.fields()
     assert rel(to_np(f["vext"]), vext) < 1e-11

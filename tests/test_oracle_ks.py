@@ -195,3 +195,46 @@ def test_energy_terms_free_box_plane_wave():
     sys_ = ks.System(n, L, np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.array([2.0]), ks.TERM_KIN)
     E = ks.energy(u[None], sys_).E
     assert abs(E - 2 * 0.5 * k * k) < 1e-9
+
+
+# ---- LDA correlation (opt-in term; Perdew-Zunger parametrisation)
+
+def test_correlation_potential_is_the_derivative_of_the_energy_density():
+    rho = np.array([1e-4, 3e-3, 0.02, 0.2, 0.239, 0.25, 1.0, 5.0, 40.0])   # r_s from ~13 to ~0.18
+    eps, v = ks.correlation_density(rho)
+    d = 1e-6 * rho
+    ep, _ = ks.correlation_density(rho + d)
+    em, _ = ks.correlation_density(rho - d)
+    fd = ((rho + d) * ep - (rho - d) * em) / (2 * d)
+    assert np.max(np.abs(fd - v) / np.abs(v)) < 1e-7
+
+
+def test_correlation_high_density_limit_and_branch_continuity():
+    # high density: eps_c -> A ln r_s + B with A = (1 - ln 2) / pi^2 (random-phase
+    # approximation coefficient, Gell-Mann and Brueckner)
+    assert abs(ks.PZ_A - (1 - np.log(2)) / np.pi ** 2) < 2e-5
+    # the two branches of the fit meet at r_s = 1 to within the fit's precision
+    rs = np.array([1.0 - 1e-12, 1.0 + 1e-12])
+    rho = 3.0 / (4.0 * np.pi * rs ** 3)
+    eps, v = ks.correlation_density(rho)
+    assert abs(eps[0] - eps[1]) < 1e-4 and abs(v[0] - v[1]) < 1e-3
+    # zero density: no energy, no potential; low density: eps_c -> G / (B2 r_s)
+    e0, v0 = ks.correlation_density(np.array([0.0]))
+    assert e0[0] == 0.0 and v0[0] == 0.0
+    rs_big = 1e10   # the next term is B1 / (B2 sqrt(r_s)) ~ 3e-5 of the leading one
+    e_big, _ = ks.correlation_density(np.array([3.0 / (4.0 * np.pi * rs_big ** 3)]))
+    assert abs(e_big[0] * rs_big * ks.PZ_B2 / ks.PZ_G - 1.0) < 1e-4
+
+
+def test_energy_gradient_with_correlation_matches_central_differences():
+    sys_, cfg = _small_system(terms=ks.TERM_ALL | ks.TERM_CORR)
+    U = synth.orbitals(cfg) * 0.05
+    G = ks.energy_gradient(U, sys_)
+    t = ks.energy(U, sys_)
+    assert t.E_c < 0.0 and abs(t.E - (t.E_kin + t.E_ext + t.E_H + t.E_x + t.E_c)) < 1e-12 * abs(t.E)
+    for seed in (31, 32):
+        D = synth.random_direction(U.shape, seed)
+        eps = 1e-5
+        fd = (ks.energy(U + eps * D, sys_).E - ks.energy(U - eps * D, sys_).E) / (2 * eps)
+        an = float(np.sum(G * D))
+        assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (fd, an)
