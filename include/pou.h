@@ -16,11 +16,13 @@
  * Orbital blocks are [norb][n][n][n], orbital-major, contiguous.
  *
  * Energy: E = sum_i f_i <u_i, -1/2 Lap u_i> + <rho, V_ext> + 1/2 <rho, V_H>
- *           + E_x,  rho = sum_i f_i u_i^2;  V_H = P[rho], V_ext = -P[rho_ion],
+ *           + E_x (+ E_c),  rho = sum_i f_i u_i^2;  V_H = P[rho], V_ext = -P[rho_ion],
  * P[f] = 4 pi (-Lap)^+ (f - mean f) (periodic Hartree potential with a
  * neutralising background), rho_ion = sum of normalised Gaussian charges
  * Z_I (pi s_I^2)^-3/2 exp(-|r-R_I|^2/s_I^2) (the periodic form of the local
- * pseudopotential -Z erf(r/s)/r), E_x the LDA exchange energy.
+ * pseudopotential -Z erf(r/s)/r), E_x the LDA exchange energy, E_c (opt in,
+ * POU_TERM_CORR) the LDA correlation energy of the Perdew-Zunger fit that the
+ * LDA of section 4 cites (spin-unpolarised).
  *
  * Conventions for every call:
  *   - Returns pou_status; POU_OK == 0.  On failure pou_last_error() gives a
@@ -66,7 +68,8 @@ enum {
   POU_TERM_EXT = 2,
   POU_TERM_HARTREE = 4,
   POU_TERM_XC = 8,
-  POU_TERM_ALL = 15
+  POU_TERM_ALL = 15,   /* the default model: exchange-only LDA */
+  POU_TERM_CORR = 16   /* add LDA correlation (not part of POU_TERM_ALL) */
 };
 
 typedef struct {
@@ -104,6 +107,7 @@ typedef struct {
 typedef struct {
   double E, E_kin, E_ext, E_H, E_x;
   int cg_iters;     /* iterations of the Hartree solve for this evaluation */
+  double E_c;       /* LDA correlation energy (0 unless POU_TERM_CORR) */
 } pou_energy_terms;
 
 typedef struct {

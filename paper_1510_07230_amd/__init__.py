@@ -24,6 +24,7 @@ STATUS = {0: "POU_OK", -1: "POU_ERR_ARG", -2: "POU_ERR_STATE", -3: "POU_ERR_HIP"
           -7: "POU_ERR_NONFINITE"}
 FP64, MIXED = 0, 1
 TERM_KIN, TERM_EXT, TERM_HARTREE, TERM_XC, TERM_ALL = 1, 2, 4, 8, 15
+TERM_CORR = 16  # LDA correlation, opt in
 
 
 class PouError(RuntimeError):
@@ -47,7 +48,8 @@ class Params(ctypes.Structure):
 
 class EnergyTerms(ctypes.Structure):
     _fields_ = [("E", ctypes.c_double), ("E_kin", ctypes.c_double), ("E_ext", ctypes.c_double),
-                ("E_H", ctypes.c_double), ("E_x", ctypes.c_double), ("cg_iters", ctypes.c_int)]
+                ("E_H", ctypes.c_double), ("E_x", ctypes.c_double), ("cg_iters", ctypes.c_int),
+                ("E_c", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -207,7 +209,7 @@ class System:
         t = EnergyTerms()
         self._check(lib().pou_energy(self._h, self._block(U), ctypes.byref(t)))
         return {"E": t.E, "E_kin": t.E_kin, "E_ext": t.E_ext, "E_H": t.E_H, "E_x": t.E_x,
-                "cg_iters": t.cg_iters}
+                "E_c": t.E_c, "cg_iters": t.cg_iters}
 
     def orthonormalize_(self, U):
         err = ctypes.c_double(0.0)

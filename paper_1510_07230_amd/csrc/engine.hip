@@ -27,10 +27,12 @@ namespace {
 
 struct Report {
   // device layout of one evaluation report:
-  // [sigma N | kin N | e3 | orth info 2*kMaxPass | Poisson rr, bb]
+  // [sigma N | kin N | e4 | orth info 2*kMaxPass | Poisson rr, bb]
+  // e4 = (sum rho^(4/3), sum rho V_ext, sum rho V_H, sum rho eps_c) * h^3
   static constexpr int kMaxPass = 4;
-  static int size(int N) { return 2 * N + 3 + 2 * kMaxPass + 2; }
-  static int rr(int N) { return 2 * N + 3 + 2 * kMaxPass; }
+  static int orth(int N) { return 2 * N + 4; }
+  static int size(int N) { return 2 * N + 4 + 2 * kMaxPass + 2; }
+  static int rr(int N) { return 2 * N + 4 + 2 * kMaxPass; }
 };
 
 double lambda1(int n, double h, int k) {
@@ -347,7 +349,7 @@ pou_status potentials_and_h(pou_ctx *c, const T *W, T *HWout, double *rep) {
   KL(POU_K_XC, pou::launch_xc_veff(c->d_rho, c->d_vh, c->d_vext, c->d_veff,
                                    sizeof(T) == 4 ? c->d_veff32 : nullptr, c->d_part, c->ng,
                                    c->p.terms, c->nblk_field, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep + 2 * N, 1, c->nblk_field, 3, c->dv, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep + 2 * N, 1, c->nblk_field, 4, c->dv, s));
   const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
   KL(POU_K_HAMILTONIAN, pou::launch_hamiltonian<T>(W, veff, HWout, c->d_part, N, c->st, s));
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep, N, c->st.ntile * c->st.nzc, 2, c->dv, s));
@@ -423,7 +425,8 @@ void terms_from_report(const pou_ctx *c, const double *rep, pou_energy_terms *t)
   t->E_x = (c->p.terms & POU_TERM_XC) ? ex : 0.0;
   t->E_ext = (c->p.terms & POU_TERM_EXT) ? eext : 0.0;
   t->E_H = (c->p.terms & POU_TERM_HARTREE) ? eh : 0.0;
-  t->E = t->E_kin + t->E_x + t->E_ext + t->E_H;
+  t->E_c = (c->p.terms & POU_TERM_CORR) ? rep[2 * N + 3] : 0.0;
+  t->E = t->E_kin + t->E_x + t->E_ext + t->E_H + t->E_c;
   t->cg_iters = c->last_cg_iters;
 }
 
@@ -819,18 +822,19 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
     double *rep_t = c->d_rep[1];
     double *dflag = rep_t + RS + 5;  // written by the Armijo kernel, read by the gated accept
     if (N <= 128) {
-      CHK(trial_orth_fused<T>(c, W, tscale, rep_t + 2 * N + 3));
+      CHK(trial_orth_fused<T>(c, W, tscale, rep_t + Report::orth(N)));
       rho_done = true;
     } else {
       KL(POU_K_TRIAL, pou::launch_trial<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, tscale,
                                            (T *)c->d_Wt, N, c->ng, s));
-      CHK(orth_passes<T>(c, (const T *)c->d_Wt, (T *)c->d_W2, passes, rep_t + 2 * N + 3, true,
+      CHK(orth_passes<T>(c, (const T *)c->d_Wt, (T *)c->d_W2, passes, rep_t + Report::orth(N), true,
                          &rho_done));
     }
     int it = 0;
     CHK(evaluate<T>(c, (const T *)c->d_W2, (T *)c->d_HWt, rep_t, rho_done, &it));
     cg_total += it;
-    KL(POU_K_OTHER, pou::launch_armijo(rep_t, c->d_occ, N, c->p.terms, passes, Report::rr(N),
+    KL(POU_K_OTHER, pou::launch_armijo(rep_t, c->d_occ, N, c->p.terms, passes, Report::orth(N),
+                                       Report::rr(N),
                                        c->p.cg_rtol * c->p.cg_rtol, c->d_scal, tscale, c->C,
                                        c->p.rho1, last ? 1 : 0, rep_t + RS, s));
     HIPCHK(c, hipMemcpyAsync(hrep, rep_t, sizeof(double) * (RS + 7), hipMemcpyDeviceToHost, s));
@@ -848,7 +852,7 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
       // accepted on the device: W, the BB history and tau_BB are updated
       accepted = hflag[1] != 0.0;
       terms_from_report(c, hrep, &et);
-      gram_dev = hrep[2 * N + 4];
+      gram_dev = hrep[Report::orth(N) + 1];
       break;
     }
     std::vector<double> &r = c->rep_host;
@@ -864,12 +868,12 @@ pou_status step_impl(pou_ctx *c, T *W, pou_step_info *info) {
       CHK(sync_read(c, r.data(), rep_t, sizeof(double) * RS));
     }
     for (int p = 0; p < passes; ++p)
-      if (r[2 * N + 3 + 2 * p] != 0.0)
+      if (r[Report::orth(N) + 2 * p] != 0.0)
         return fail(c, POU_ERR_NOT_SPD, "trial Gram matrix is not positive definite (pass " +
                                              std::to_string(p) + ")");
     terms_from_report(c, r.data(), &et);
     if (!std::isfinite(et.E)) return fail(c, POU_ERR_NONFINITE, "trial energy is not finite");
-    gram_dev = r[2 * N + 4];
+    gram_dev = r[Report::orth(N) + 1];
     if (!redo && !last) continue;  // the device found eq. "ene-de" violated: backtrack
     // host decision after a finished Hartree solve (or the last trial)
     const bool pass = et.E <= c->C - c->p.rho1 * tau * zz;
@@ -1115,7 +1119,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   if (p.n_org <= 0) p.n_org = 1;
   if (!(p.delta > 0.0 && p.delta < 1.0) || !(p.rho1 >= 0.0) || !(p.eta >= 0.0 && p.eta <= 1.0) ||
       p.s_max < 0 || p.s_max > 60 || p.orth_passes > 2 || p.bb_mode < 0 || p.bb_mode > 2 ||
-      !std::isfinite(p.tau_init) || p.n_diag < 0)
+      !std::isfinite(p.tau_init) || p.n_diag < 0 || (p.terms & ~31u) != 0)
     return fail(c, POU_ERR_ARG, "bad algorithm parameters");
   if (p.n_diag > 0)
     for (int i = 1; i < norb; ++i)
@@ -1179,7 +1183,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_fft1, 2 * fbytes));
   CHK(dalloc(c, &c->d_sc, sizeof(double) * 16));
   c->part_len = std::max<size_t>({(size_t)2 * norb * c->st.ntile * c->st.nzc,
-                                  (size_t)3 * c->nblk_field, (size_t)4 * norb * c->nblk_orb,
+                                  (size_t)4 * c->nblk_field, (size_t)4 * norb * c->nblk_orb,
                                   (size_t)4 * std::max(1, natoms) * 256, (size_t)16});
   CHK(dalloc(c, &c->d_part, sizeof(double) * c->part_len));
   CHK(dalloc(c, &c->d_gpart, sizeof(double) * pou::gram_partial_doubles(norb, c->nsplit)));

@@ -226,6 +226,30 @@ __global__ __launch_bounds__(kBlock) void k_density(const T *__restrict__ U,
 
 // LDA exchange (section 2.1 v_xc, exchange part only):
 //   e_x density = -C_x rho^(4/3), v_x = -(3/pi)^(1/3) rho^(1/3).
+// LDA correlation per electron of the uniform gas, Perdew-Zunger fit
+// (spin-unpolarised), and its potential d(rho eps_c)/d rho, for rho > 0 with
+// r13 = rho^(1/3): r_s = (3 / (4 pi))^(1/3) / r13;
+//   r_s >= 1: eps = G / (1 + B1 sqrt(r_s) + B2 r_s),
+//             v = eps (1 + 7/6 B1 sqrt(r_s) + 4/3 B2 r_s) / (1 + B1 sqrt(r_s) + B2 r_s)
+//   r_s <  1: eps = A ln r_s + B + C r_s ln r_s + D r_s,
+//             v = A ln r_s + (B - A/3) + 2/3 C r_s ln r_s + (2 D - C)/3 r_s
+__device__ inline void pz_correlation(double rho, double r13, double &eps, double &v) {
+  const double rs = 0.62035049089940001667 / r13;  // (3/(4 pi))^(1/3) rho^(-1/3)
+  if (rs >= 1.0) {
+    const double G = -0.1423, B1 = 1.0529, B2 = 0.3334;
+    const double sq = sqrt(rs);
+    const double den = 1.0 + B1 * sq + B2 * rs;
+    eps = G / den;
+    v = eps * (1.0 + (7.0 / 6.0) * B1 * sq + (4.0 / 3.0) * B2 * rs) / den;
+  } else {
+    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+    const double lr = log(rs);
+    eps = A * lr + B + C * rs * lr + D * rs;
+    v = A * lr + (B - A / 3.0) + (2.0 / 3.0) * C * rs * lr + ((2.0 * D - C) / 3.0) * rs;
+  }
+  (void)rho;
+}
+
 __global__ __launch_bounds__(kBlock) void k_xc_veff(const double *__restrict__ rho,
                                                     const double *__restrict__ vh,
                                                     const double *__restrict__ vext,
@@ -233,9 +257,9 @@ __global__ __launch_bounds__(kBlock) void k_xc_veff(const double *__restrict__ r
                                                     float *__restrict__ veff32,
                                                     double *__restrict__ part, i64 ng,
                                                     unsigned terms) {
-  __shared__ double red[4 * 3];
+  __shared__ double red[4 * 4];
   const double kv = 0.98474502184269640;  // (3/pi)^(1/3)
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
        g += (i64)gridDim.x * blockDim.x) {
     const double r = rho[g];
@@ -244,6 +268,12 @@ __global__ __launch_bounds__(kBlock) void k_xc_veff(const double *__restrict__ r
     if (terms & 8u) {
       v -= kv * r13;
       a0 += r * r13;
+    }
+    if ((terms & 16u) && r > 0.0) {
+      double eps, vc;
+      pz_correlation(r, r13, eps, vc);
+      v += vc;
+      a3 += r * eps;
     }
     if (terms & 4u) {
       v += vh[g];
@@ -256,12 +286,13 @@ __global__ __launch_bounds__(kBlock) void k_xc_veff(const double *__restrict__ r
     veff[g] = v;
     if (veff32) veff32[g] = (float)v;
   }
-  double vals[3] = {a0, a1, a2};
-  block_sum<3>(vals, red);
+  double vals[4] = {a0, a1, a2, a3};
+  block_sum<4>(vals, red);
   if (threadIdx.x == 0) {
-    part[3 * blockIdx.x + 0] = vals[0];
-    part[3 * blockIdx.x + 1] = vals[1];
-    part[3 * blockIdx.x + 2] = vals[2];
+    part[4 * blockIdx.x + 0] = vals[0];
+    part[4 * blockIdx.x + 1] = vals[1];
+    part[4 * blockIdx.x + 2] = vals[2];
+    part[4 * blockIdx.x + 3] = vals[3];
   }
 }
 
@@ -888,8 +919,8 @@ __global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, i
 
 // Test of eq. "ene-de" for a trial on the device, so that the accept can be
 // enqueued before the host has read the trial's energy.  rep is the trial's
-// evaluation report (sigma N | kin N | e3 | orth info 2*npass... | rr, bb at
-// rr_off), scal = (tau_BB, ||Z||^2, ...).  The energy is assembled as the
+// evaluation report (sigma N | kin N | e4 | orth info 2*npass at orth_off |
+// rr, bb at rr_off), scal = (tau_BB, ||Z||^2, ...).  The energy is assembled as the
 // host does (occupation-weighted kinetic sum in orbital order, then the
 // exchange, external and Hartree terms).  ext[0..4] receives a copy of scal
 // (so that one copy brings report, scalars and decision to the host);
@@ -898,7 +929,7 @@ __global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, i
 // E <= C - rho1 tau ||Z||^2 (or force, the last backtrack); ext[6] = 1 when
 // the inequality itself held.
 __global__ void k_armijo(const double *__restrict__ rep, const double *__restrict__ occ, int N,
-                         unsigned terms, int npass, int rr_off, double rtol2,
+                         unsigned terms, int npass, int orth_off, int rr_off, double rtol2,
                          const double *__restrict__ scal, double tscale, double C, double rho1,
                          int force, double *__restrict__ ext) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -906,7 +937,7 @@ __global__ void k_armijo(const double *__restrict__ rep, const double *__restric
   double *flags = ext + 5;
   const double rr = rep[rr_off], bb = rep[rr_off + 1];
   bool ok = isfinite(rr) && isfinite(bb) && rr <= rtol2 * bb;
-  for (int p = 0; p < npass; ++p) ok = ok && rep[2 * N + 3 + 2 * p] == 0.0;
+  for (int p = 0; p < npass; ++p) ok = ok && rep[orth_off + 2 * p] == 0.0;
   double ekin = 0.0;
 #pragma unroll 16
   for (int i = 0; i < N; ++i) ekin += occ[i] * rep[N + i];
@@ -915,6 +946,7 @@ __global__ void k_armijo(const double *__restrict__ rep, const double *__restric
   E += (terms & 8u) ? -cx * rep[2 * N + 0] : 0.0;
   E += (terms & 2u) ? rep[2 * N + 1] : 0.0;
   E += (terms & 4u) ? 0.5 * rep[2 * N + 2] : 0.0;
+  E += (terms & 16u) ? rep[2 * N + 3] : 0.0;
   ok = ok && isfinite(E);
   const double tau = scal[0] * tscale;
   const bool pass = E <= C - rho1 * tau * scal[1];
@@ -1111,10 +1143,11 @@ hipError_t launch_bb_tau(const double *red, int N, int mode, double tau_init, do
 }
 
 hipError_t launch_armijo(const double *rep, const double *occ, int N, unsigned terms, int npass,
-                         int rr_off, double rtol2, const double *scal, double tscale, double C,
-                         double rho1, int force, double *ext, hipStream_t s) {
-  hipLaunchKernelGGL(k_armijo, dim3(1), dim3(64), 0, s, rep, occ, N, terms, npass, rr_off, rtol2,
-                     scal, tscale, C, rho1, force, ext);
+                         int orth_off, int rr_off, double rtol2, const double *scal,
+                         double tscale, double C, double rho1, int force, double *ext,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_armijo, dim3(1), dim3(64), 0, s, rep, occ, N, terms, npass, orth_off,
+                     rr_off, rtol2, scal, tscale, C, rho1, force, ext);
   return hipGetLastError();
 }
 

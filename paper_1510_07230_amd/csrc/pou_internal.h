@@ -93,8 +93,8 @@ template <typename T>
 hipError_t launch_density(const T *U, const double *occ, double *rho, int N, i64 ng,
                           hipStream_t s);
 
-// xc + effective potential + energy partials.  part[3*b + {0,1,2}] =
-// partial sums of (rho^(4/3), rho*vext, rho*vh).  veff32 nullable.
+// xc + effective potential + energy partials.  part[4*b + {0,1,2,3}] =
+// partial sums of (rho^(4/3), rho*vext, rho*vh, rho*eps_c).  veff32 nullable.
 hipError_t launch_xc_veff(const double *rho, const double *vh, const double *vext,
                           double *veff, float *veff32, double *part, i64 ng,
                           unsigned terms, int nblk, hipStream_t s);
@@ -145,8 +145,9 @@ hipError_t launch_bb_tau(const double *red, int N, int mode, double tau_init, do
 // device test of eq. "ene-de" for a trial report: ext[0..4] = scal, ext[5] = accept,
 // ext[6] = inequality held
 hipError_t launch_armijo(const double *rep, const double *occ, int N, unsigned terms, int npass,
-                         int rr_off, double rtol2, const double *scal, double tscale, double C,
-                         double rho1, int force, double *ext, hipStream_t s);
+                         int orth_off, int rr_off, double rtol2, const double *scal,
+                         double tscale, double C, double rho1, int force, double *ext,
+                         hipStream_t s);
 hipError_t launch_set_flags(double *flags, double a, double b, hipStream_t s);
 // accept: U <- Wn; partials per (orbital, block) of
 //   s.s, s.y, y.y, zn.zn  with s = Wn - W, y = zn - z,
