@@ -194,37 +194,40 @@ def run(args):
 
     # variant: mixed with one FP32-accurate Cholesky-QR pass instead of the
     # BF16 Gram + CholeskyQR2 of the specified mixed form (reported, not the value)
-    g1 = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="mixed",
-                   params=pk.default_params(orth_passes=1))
-    U1 = W0.to(torch.float32).contiguous()
-    g1.orthonormalize_(U1)
-    t1, _, _, _, _ = timed(g1, U1, args.steps, args.warmup, 4)
-    progress(f"mixed, one FP32 Cholesky-QR pass: {args.steps / t1:.1f} it/s")
-    del g1, U1
+    extras = not args.no_extras
+    if extras:
+        g1 = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="mixed",
+                       params=pk.default_params(orth_passes=1))
+        U1 = W0.to(torch.float32).contiguous()
+        g1.orthonormalize_(U1)
+        t1, _, _, _, _ = timed(g1, U1, args.steps, args.warmup, 4)
+        progress(f"mixed, one FP32 Cholesky-QR pass: {args.steps / t1:.1f} it/s")
+        del g1, U1
 
     # cost of the section 3.3 modifications that keep the iteration unchanged:
     # subspace diagonalisation (here after every step, n_diag = 1, to time it;
     # the paper's runs use n_diag = 100) and one full-Sigma residual of eq. "gra"
-    g2 = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="mixed",
-                   params=pk.default_params(n_diag=1))
-    U2 = W0.to(torch.float32).contiguous()
-    g2.orthonormalize_(U2)
-    n_rot = 10
-    for _ in range(2):
-        g2.step_(U2)
-    torch.cuda.synchronize()
-    t0r = time.perf_counter()
-    for _ in range(n_rot):
-        g2.step_(U2)
-    torch.cuda.synchronize()
-    t_rot_step = (time.perf_counter() - t0r) / n_rot
-    t0r = time.perf_counter()
-    res2, _ = g2.residual(U2)
-    torch.cuda.synchronize()
-    t_res = time.perf_counter() - t0r
-    rot_ms = 1000.0 * (t_rot_step - t32 / args.steps)
-    progress(f"subspace rotation: {rot_ms:.2f} ms each; residual {1000 * t_res:.2f} ms")
-    del g2, U2
+    if extras:
+        g2 = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="mixed",
+                       params=pk.default_params(n_diag=1))
+        U2 = W0.to(torch.float32).contiguous()
+        g2.orthonormalize_(U2)
+        n_rot = 10
+        for _ in range(2):
+            g2.step_(U2)
+        torch.cuda.synchronize()
+        t0r = time.perf_counter()
+        for _ in range(n_rot):
+            g2.step_(U2)
+        torch.cuda.synchronize()
+        t_rot_step = (time.perf_counter() - t0r) / n_rot
+        t0r = time.perf_counter()
+        res2, _ = g2.residual(U2)
+        torch.cuda.synchronize()
+        t_res = time.perf_counter() - t0r
+        rot_ms = 1000.0 * (t_rot_step - t32 / args.steps)
+        progress(f"subspace rotation: {rot_ms:.2f} ms each; residual {1000 * t_res:.2f} ms")
+        del g2, U2
 
     # roofline of the dominant kernel group of the mixed run, from the events
     # of the timed pass
@@ -251,28 +254,31 @@ def run(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "mixed96: 96^3 periodic grid, L=24 bohr, 64 Gaussian ions Z=4 "
-                               "sigma=0.5, N=128 orbitals (f=2), atom-centred seeded start; "
+        "config": {"workload": f"{cfg.name}: {cfg.n}^3 periodic grid, L={cfg.L:g} bohr, "
+                               f"{cfg.natoms} Gaussian ions Z={cfg.Z} sigma={cfg.sigma}, "
+                               f"N={N} orbitals (f=2), {cfg.start}-start seeded; "
                                "mixed = FP32 orbitals/stencil, BF16-MFMA first Gram, FP32 second "
                                "Gram and apply, FP64 Cholesky and reductions",
                    "n": cfg.n, "L": cfg.L, "norb": N, "natoms": cfg.natoms},
         "fp64": {"value": round(args.steps / t64, 3), "unit": "iters/s",
                  "ms_per_step": round(1000.0 * t64 / args.steps, 4)},
         "speedup_mixed_over_fp64": round(t64 / t32, 3),
-        "mixed_one_pass_fp32_gram": {"value": round(args.steps / t1, 3), "unit": "iters/s",
-                                     "note": "one FP32-accurate Cholesky-QR pass instead of "
-                                             "BF16 Gram + CholeskyQR2"},
-        "section_3_3": {"subspace_rotation_ms": round(rot_ms, 3),
-                        "rotation_per_step_at_n_diag_100_ms": round(rot_ms / 100.0, 4),
-                        "residual_ms": round(1000.0 * t_res, 3), "residual": res2,
-                        "note": "rotation cost = mixed step time with n_diag = 1 minus the "
-                                "mixed step time; n_org = 2 is not timed (plain BB steps "
-                                "without a safeguard diverge on this workload)"},
         "mean_trials_per_step": {"mixed": float(np.mean([i["s"] + 1 for i in inf32])),
                                  "fp64": float(np.mean([i["s"] + 1 for i in inf64]))},
         "roofline": roofline,
     }
 
+    if extras:
+        out["mixed_one_pass_fp32_gram"] = {
+            "value": round(args.steps / t1, 3), "unit": "iters/s",
+            "note": "one FP32-accurate Cholesky-QR pass instead of BF16 Gram + CholeskyQR2"}
+        out["section_3_3"] = {
+            "subspace_rotation_ms": round(rot_ms, 3),
+            "rotation_per_step_at_n_diag_100_ms": round(rot_ms / 100.0, 4),
+            "residual_ms": round(1000.0 * t_res, 3), "residual": res2,
+            "note": "rotation cost = mixed step time with n_diag = 1 minus the mixed step "
+                    "time; n_org = 2 is not timed (plain BB steps without a safeguard diverge "
+                    "on this workload)"}
     if args.calibrate_copy:
         # a plain copy kernel of known size (one FP32 block, read once and
         # written once) for scaling the FETCH_SIZE / WRITE_SIZE counters
@@ -346,6 +352,8 @@ def main():
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the one-pass variant and the section 3.3 timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

@@ -286,6 +286,18 @@ __global__ __launch_bounds__(1024) void k_cholesky_inverse(double *__restrict__ 
   if (t == 0) info[0] = sbad ? 1.0 : 0.0;
 }
 
+// D64 = Minv - I and D32 its FP32 copy (after the single-workgroup Cholesky).
+__global__ __launch_bounds__(kBlock) void k_minv_to_d(const double *__restrict__ Minv, int N,
+                                                      double *__restrict__ D64,
+                                                      float *__restrict__ D32) {
+  const i64 total = (i64)N * N;
+  for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < total; e += (i64)gridDim.x * kBlock) {
+    const double d = Minv[e] - ((e / N) == (e % N) ? 1.0 : 0.0);
+    D64[e] = d;
+    D32[e] = (float)d;
+  }
+}
+
 // M = A B for lower-triangular A, B (N x N, zeros above the diagonal), with
 // D64 = M - I and D32 its FP32 copy: the combined factor of two Cholesky-QR
 // passes.  With split_b, B is replaced by the value the fused first apply
@@ -1661,6 +1673,413 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
   }
 }
 
+// ---------------------------------------------------------------- N > 128, FP32
+
+constexpr int kBB = 128;  // row block of the N > 128 Gram and apply kernels
+constexpr int kBP = 40;   // LDS pitch (BF16) of a 32-wide chunk: 80-byte, 16-byte aligned rows
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+// Work item of workgroup b when items come in groups of `per` that read the
+// same grid points: dispatch sends workgroup b to XCD b mod 8, so the members
+// of a group take consecutive slots on one XCD and meet in its L2.
+__device__ inline void xcd_group(int b, int per, int &group, int &member) {
+  const int x = b & 7, j = b >> 3;
+  group = x + 8 * (j / per);
+  member = j % per;
+}
+
+// Gram of FP32 orbitals for N > 128 on BF16 MFMA: 128 x 128 output blocks
+// (bi <= bj) over nsplit contiguous ranges of kper grid points (the grid is
+// padded to a multiple of 8 ranges; the block pairs of one range share an XCD).
+// Eight waves in a 4 x 2 grid: wave (rw, cw) holds rows 32 rw .. 32 rw + 31 and
+// columns 64 cw .. 64 cw + 63 of the block (2 x 4 tiles of 16 x 16).  Per
+// 64-point chunk the rows of both blocks are loaded as float4 (the next chunk
+// in flight while the current one is multiplied), rounded to BF16 and stored in
+// LDS as [row][point], double-buffered; each tile takes two 16x16x32 MFMAs per
+// chunk, or with SPLIT the four products of the hi/lo pieces (FP32-accurate),
+// whose FP32 sums are flushed into FP64 every chunk.  Without SPLIT (the first
+// Cholesky-QR pass, whose factor is refined by the second) the FP32 sums run
+// over the whole range: that keeps the kernel at two workgroups per CU.  On a
+// diagonal block the wave whose tiles all lie below the diagonal skips the
+// products (the reduction reads the upper triangle only).
+template <bool SPLIT, bool VEC>
+__global__ __launch_bounds__(kAB) __attribute__((amdgpu_waves_per_eu(SPLIT ? 2 : 4)))
+void k_gram_big(const float *__restrict__ A, int N, i64 ng,
+                                                  i64 kper, int nsplit, int npairs,
+                                                  double *__restrict__ part) {
+  constexpr int KC = 64;       // points per chunk
+  constexpr int PG = KC + 8;   // LDS pitch (BF16): 144-byte rows, conflict-free 16-byte reads
+  constexpr int NV = 2 * kBB * KC / 4 / kAB;  // float4 loads per thread per chunk (8)
+  __shared__ __attribute__((aligned(16))) __bf16 sh[2][2][kBB][PG];
+  __shared__ __attribute__((aligned(16))) __bf16 sl[2][SPLIT ? 2 : 1][SPLIT ? kBB : 1][PG];
+  int split, pair;
+  xcd_group(blockIdx.x, npairs, split, pair);
+  if (split >= nsplit) return;  // padding to a multiple of 8 ranges (before any barrier)
+  const int nb = (N + kBB - 1) / kBB;
+  int bi, bj;
+  decode_pair(pair, nb, bi, bj);
+  const bool diag = bi == bj;
+  const i64 k_beg = (i64)split * kper;
+  const i64 k_end = min(ng, k_beg + kper);
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int rw = w >> 1, cw = w & 1;
+  const bool idle = diag && cw == 0 && rw >= 2;
+  // loader slot e: float4 f = t + 512 e, row f / 16 (block bi for e < NV / 2, bj
+  // after), points 4 (f % 16) .. + 3.  Loads read clamped (always valid)
+  // addresses and zero what lies outside, with non-short-circuit tests: no
+  // branch, so they all stay in flight (a diagonal block loads its rows twice;
+  // the second copy comes from the caches).
+  float4 v[NV];
+  auto load = [&](i64 k0) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int f = t + kAB * e;
+      const int row = f >> 4, c4 = (f & 15) * 4;
+      const int grow = row < kBB ? bi * kBB + row : bj * kBB + row - kBB;
+      const bool rok = grow < N;
+      const float *p = A + (i64)min(grow, N - 1) * ng;
+      const i64 g = k0 + c4;
+      float4 x;
+      if (VEC) {
+        x = *(const float4 *)(p + min(g, ng - 4));
+        const bool ok = rok & (g < k_end);
+        x.x = ok ? x.x : 0.f;
+        x.y = ok ? x.y : 0.f;
+        x.z = ok ? x.z : 0.f;
+        x.w = ok ? x.w : 0.f;
+      } else {
+        x.x = p[min(g, ng - 1)];
+        x.y = p[min(g + 1, ng - 1)];
+        x.z = p[min(g + 2, ng - 1)];
+        x.w = p[min(g + 3, ng - 1)];
+        x.x = (rok & (g < k_end)) ? x.x : 0.f;
+        x.y = (rok & (g + 1 < k_end)) ? x.y : 0.f;
+        x.z = (rok & (g + 2 < k_end)) ? x.z : 0.f;
+        x.w = (rok & (g + 3 < k_end)) ? x.w : 0.f;
+      }
+      v[e] = x;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int f = t + kAB * e;
+      const int row = f >> 4, c4 = (f & 15) * 4;
+      const int blk = row >= kBB ? 1 : 0, r = row & (kBB - 1);
+      const float x[4] = {v[e].x, v[e].y, v[e].z, v[e].w};
+      bf4 hv, lv;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        __bf16 hh, ll;
+        split_bf16(x[k], hh, ll);
+        hv[k] = hh;
+        lv[k] = ll;
+      }
+      *(bf4 *)&sh[b][blk][r][c4] = hv;
+      if (SPLIT) *(bf4 *)&sl[b][SPLIT ? blk : 0][SPLIT ? r : 0][c4] = lv;
+    }
+  };
+  f4 acc[2][4];
+  double gd[SPLIT ? 2 : 1][SPLIT ? 4 : 1][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = f4{0, 0, 0, 0};
+  if (SPLIT) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gd[SPLIT ? a : 0][SPLIT ? c : 0][r] = 0.0;
+  }
+  auto compute = [&](int b) {
+    if (idle) return;
+#pragma unroll
+    for (int ks = 0; ks < KC / 32; ++ks) {
+      const int k8 = 32 * ks + 8 * q;
+      bf8 ah[2], bh[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) ah[a] = *(const bf8 *)&sh[b][0][32 * rw + 16 * a + r16][k8];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bh[c] = *(const bf8 *)&sh[b][1][64 * cw + 16 * c + r16][k8];
+      if (SPLIT) {
+        bf8 al[2], bl[4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          al[a] = *(const bf8 *)&sl[b][0][SPLIT ? 32 * rw + 16 * a + r16 : 0][k8];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          bl[c] = *(const bf8 *)&sl[b][SPLIT ? 1 : 0][SPLIT ? 64 * cw + 16 * c + r16 : 0][k8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            f4 x = acc[a][c];
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bl[c], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[c], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[c], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[c], x, 0, 0, 0);
+            acc[a][c] = x;
+          }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
+      }
+    }
+    if (SPLIT) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gd[SPLIT ? a : 0][SPLIT ? c : 0][r] += (double)acc[a][c][r];
+          acc[a][c] = f4{0, 0, 0, 0};
+        }
+    }
+  };
+  // the last chunk is peeled off the loop so that the loads and stores of the
+  // next chunk are unconditional there: guarded by a shared test they would be
+  // merged into one block ahead of the products, waiting on the loads at once
+  const i64 nchunk = k_end > k_beg ? (k_end - k_beg + KC - 1) / KC : 0;
+  if (nchunk > 0) {
+    load(k_beg);
+    stash(0);
+  }
+  __syncthreads();
+  int b = 0;
+  for (i64 ch = 0; ch + 1 < nchunk; ++ch, b ^= 1) {
+    load(k_beg + KC * (ch + 1));
+    compute(b);
+    __builtin_amdgcn_sched_barrier(0);
+    stash(b ^ 1);
+    __syncthreads();
+  }
+  if (nchunk > 0) compute(b);
+  if (idle) return;
+  double *out = part + ((i64)split * npairs + pair) * kBB * kBB;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(32 * rw + 16 * a + 4 * q + r) * kBB + 64 * cw + 16 * c + r16] =
+            SPLIT ? gd[SPLIT ? a : 0][SPLIT ? c : 0][r] : (double)acc[a][c][r];
+}
+
+// G = dv * sum over splits of the 128 x 128 block partials of k_gram_big; one
+// thread per element of the upper block triangle, both halves of G written.
+__global__ __launch_bounds__(kBlock) void k_gram_reduce_big(const double *__restrict__ part,
+                                                            int N, int nsplit, int npairs,
+                                                            double dv, double *__restrict__ G) {
+  const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
+  const i64 stride = (i64)npairs * kBB * kBB;
+  if (e >= stride) return;
+  const int pair = (int)(e / (kBB * kBB)), rc = (int)(e % (kBB * kBB));
+  const int ri = rc / kBB, cj = rc % kBB;
+  int bi, bj;
+  decode_pair(pair, (N + kBB - 1) / kBB, bi, bj);
+  if (bi == bj && ri > cj) return;
+  const int i = bi * kBB + ri, j = bj * kBB + cj;
+  if (i >= N || j >= N) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int sp = 0;
+  for (; sp + 3 < nsplit; sp += 4) {
+    a0 += part[(i64)sp * stride + e];
+    a1 += part[(i64)(sp + 1) * stride + e];
+    a2 += part[(i64)(sp + 2) * stride + e];
+    a3 += part[(i64)(sp + 3) * stride + e];
+  }
+  for (; sp < nsplit; ++sp) a0 += part[(i64)sp * stride + e];
+  const double val = ((a0 + a1) + (a2 + a3)) * dv;
+  G[(i64)i * N + j] = val;
+  G[(i64)j * N + i] = val;
+}
+
+// BF16 hi/lo pieces of the factor for k_apply_big, padded to whole 128-row
+// blocks and 32-column chunks (zeros outside N x N, so the apply loads them
+// without bounds tests): the correction D, or M = I + D (formed in FP32) when
+// ginfo[1] = max |G - I| of the Gram the factor came from is 0.25 or more.
+// Pieces are [NR][NC] with NR = N rounded up to 128, NC = N rounded up to 32.
+__global__ __launch_bounds__(kBlock) void k_split_factor(const float *__restrict__ D,
+                                                         const double *__restrict__ ginfo,
+                                                         int N, __bf16 *__restrict__ Dh,
+                                                         __bf16 *__restrict__ Dl) {
+  const int NR = (N + kBB - 1) / kBB * kBB, NC = (N + 31) / 32 * 32;
+  const float diag1 = (ginfo == nullptr || !(ginfo[1] >= 0.25)) ? 0.0f : 1.0f;
+  const i64 total = (i64)NR * NC;
+  for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < total; e += (i64)gridDim.x * kBlock) {
+    const int r = (int)(e / NC), c = (int)(e % NC);
+    float d = 0.0f;
+    if (r < N && c < N) d = D[(i64)r * N + c] + (r == c ? diag1 : 0.0f);
+    __bf16 h, l;
+    split_bf16(d, h, l);
+    Dh[e] = h;
+    Dl[e] = l;
+  }
+}
+
+// out = X + D X for lower-triangular D (FP32 N x N, zero above the diagonal)
+// and N > 128, on BF16 MFMA with both operands split into hi/lo pieces (four
+// products, FP32 accumulation); the identity is added in FP32, so the rounding
+// is relative to the correction D X.  That form loses accuracy when the factor
+// shrinks the rows strongly (D near -I: the sum cancels), as in the first pass
+// over an unnormalised block; when ginfo[1] (max |G - I| of the Gram the factor
+// came from) is 0.25 or more, the kernel multiplies by M = I + D itself (the
+// pieces from k_split_factor hold M then) and adds nothing.  Workgroup = (row block J of 128 output
+// orbitals, tile of 128 grid points); the row blocks of one point tile share
+// an XCD, heaviest first.  Eight waves in a 4 x 2 grid: wave (rw, cw) forms
+// (D X)^T for orbitals 32 rw .. 32 rw + 31 of the block and points 64 cw ..
+// 64 cw + 63 (2 x 4 tiles).  The K loop runs over 32-orbital chunks up to the
+// wave's diagonal; per chunk X is staged in LDS transposed ([point][orbital],
+// split into hi/lo pieces on the way) and the block's rows of the factor
+// pieces as [orbital][k], double-buffered with the next chunk's loads in
+// flight.  out must not alias X.
+template <bool VEC>
+__global__ __launch_bounds__(kAB) __attribute__((amdgpu_waves_per_eu(4)))
+void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
+                 const double *__restrict__ ginfo, const float *__restrict__ X,
+                 float *__restrict__ out, int N, i64 ng) {
+  __shared__ __attribute__((aligned(16))) __bf16 xh[2][kBB][kBP];
+  __shared__ __attribute__((aligned(16))) __bf16 xl[2][kBB][kBP];
+  __shared__ __attribute__((aligned(16))) __bf16 dh[2][kBB][kBP];
+  __shared__ __attribute__((aligned(16))) __bf16 dl[2][kBB][kBP];
+  const int nJ = (N + kBB - 1) / kBB;
+  int ptile, jj;
+  xcd_group(blockIdx.x, nJ, ptile, jj);
+  const int J = nJ - 1 - jj;
+  const i64 g0 = (i64)ptile * kBB;
+  if (g0 >= ng) return;  // padding workgroup: the whole group leaves before any barrier
+  const int nkc = min(4 * (J + 1), (N + 31) / 32);
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int rw = w >> 1, cw = w & 1;
+  const int wkc = min(nkc, 4 * J + rw + 1);  // chunks that reach this wave's orbitals
+  // loaders: X point xp, orbitals xo .. xo + 7 of the chunk; D row dr, columns dc .. dc + 7
+  const int xp = t & (kBB - 1), xo = 8 * (t >> 7);
+  const int dr = t >> 2, dc = 8 * (t & 3);
+  const i64 gx = g0 + xp;
+  const int jrow = J * kBB + dr;
+  const bool ident = ginfo == nullptr || !(ginfo[1] >= 0.25);
+  // X loads read clamped (always valid) addresses and zero what lies outside:
+  // no divergent branch, so every load of a chunk stays in flight; the factor
+  // pieces are padded, so their loads need no test at all
+  const float *xcol = X + min(gx, ng - 1);
+  const int NC = (N + 31) / 32 * 32;
+  const __bf16 *dhr = Dh + (i64)jrow * NC + dc;
+  const __bf16 *dlr = Dl + (i64)jrow * NC + dc;
+  float xv[8];
+  bf8 fh, fl;
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int i = 32 * kc + xo + e;
+      const float x = xcol[(i64)min(i, N - 1) * ng];
+      xv[e] = ((i < N) & (gx < ng)) ? x : 0.0f;  // & not &&: no branch around the load
+    }
+    fh = *(const bf8 *)(dhr + 32 * kc);
+    fl = *(const bf8 *)(dlr + 32 * kc);
+  };
+  auto stash = [&](int b) {
+    bf8 h1, l1;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 a, c;
+      split_bf16(xv[e], a, c);
+      h1[e] = a;
+      l1[e] = c;
+    }
+    *(bf8 *)&xh[b][xp][xo] = h1;
+    *(bf8 *)&xl[b][xp][xo] = l1;
+    *(bf8 *)&dh[b][dr][dc] = fh;
+    *(bf8 *)&dl[b][dr][dc] = fl;
+  };
+  f4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = f4{0, 0, 0, 0};
+  auto compute = [&](int b, int kc) {
+    if (kc >= wkc) return;
+    bf8 bh[2], bl[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      bh[a] = *(const bf8 *)&dh[b][32 * rw + 16 * a + r16][8 * q];
+      bl[a] = *(const bf8 *)&dl[b][32 * rw + 16 * a + r16][8 * q];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bf8 ah = *(const bf8 *)&xh[b][64 * cw + 16 * c + r16][8 * q];
+      const bf8 al = *(const bf8 *)&xl[b][64 * cw + 16 * c + r16][8 * q];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        f4 x = acc[a][c];
+        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl[a], x, 0, 0, 0);
+        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[a], x, 0, 0, 0);
+        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[a], x, 0, 0, 0);
+        x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[a], x, 0, 0, 0);
+        acc[a][c] = x;
+      }
+    }
+  };
+  // last chunk peeled: the next chunk's loads and stores stay unconditional
+  // in the loop, so they are not merged ahead of the products
+  load(0);
+  stash(0);
+  __syncthreads();
+  int kc = 0;
+  for (; kc + 1 < nkc; ++kc) {
+    load(kc + 1);
+    compute(kc & 1, kc);
+    __builtin_amdgcn_sched_barrier(0);
+    stash((kc & 1) ^ 1);
+    __syncthreads();
+  }
+  compute(kc & 1, kc);
+  // lane (r16, q) of tile (a, c) holds orbital 16 a + r16 at points 4 q .. 4 q + 3;
+  // per row tile, the identity loads are issued (clamped) before any store
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int j = J * kBB + 32 * rw + 16 * a + r16;
+    float4 xi[4];
+    const float *xr = X + (i64)min(j, N - 1) * ng;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const i64 g = g0 + 64 * cw + 16 * c + 4 * q;
+      if (VEC) {
+        xi[c] = *(const float4 *)(xr + min(g, ng - 4));
+      } else {
+        xi[c] = make_float4(xr[min(g, ng - 1)], xr[min(g + 1, ng - 1)], xr[min(g + 2, ng - 1)],
+                            xr[min(g + 3, ng - 1)]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const i64 g = g0 + 64 * cw + 16 * c + 4 * q;
+      const float w = ident ? 1.0f : 0.0f;
+      const float4 x = xi[c];
+      const float4 o = make_float4(w * x.x + acc[a][c][0], w * x.y + acc[a][c][1],
+                                   w * x.z + acc[a][c][2], w * x.w + acc[a][c][3]);
+      float *orow = out + (i64)j * ng + g;
+      if (j < N) {
+        if (VEC) {
+          if (g < ng) *(float4 *)orow = o;
+        } else {
+          if (g < ng) orow[0] = o.x;
+          if (g + 1 < ng) orow[1] = o.y;
+          if (g + 2 < ng) orow[2] = o.z;
+          if (g + 3 < ng) orow[3] = o.w;
+        }
+      }
+    }
+  }
+}
+
 // Workgroups of `kernel` (`block` threads, static LDS only) that are resident
 // on the current device at once: the grid of a kernel that walks its work in
 // a grid-stride loop.  Cached per kernel and device.
@@ -1701,7 +2120,30 @@ int resident_workgroups(const void *kernel, int block = kBlock) {
   }
 
 int gram_split(int N, bool fp32) {
-  if (N > 128) return 0;
+  if (N > 128) {
+    if (!fp32) {
+      const int nb = (N + kGB - 1) / kGB;
+      return std::max(1, 1024 / (nb * (nb + 1) / 2));
+    }
+    // k_gram_big: a multiple of 8 ranges (one XCD per range), the workgroup
+    // count as close to whole rounds of the resident ones as 2 .. 6 rounds allow
+    const int nb = (N + kBB - 1) / kBB;
+    const int npairs = nb * (nb + 1) / 2;
+    const int res = std::min(resident_workgroups((const void *)k_gram_big<true, true>, kAB),
+                             resident_workgroups((const void *)k_gram_big<false, true>, kAB));
+    int best = 8;
+    double best_eff = 0.0;
+    for (int rounds = 2; rounds <= 6; ++rounds) {
+      const int ns = std::max(8, (rounds * res / npairs) / 8 * 8);
+      const int wg = ns * npairs;
+      const double eff = (double)wg / (double)(((wg + res - 1) / res) * res);
+      if (eff > best_eff + 1e-9) {
+        best_eff = eff;
+        best = ns;
+      }
+    }
+    return best;
+  }
   const int NT = (N + 15) / 16;
   int g = 1 << 30;
   auto take = [&](const void *k) { g = std::min(g, resident_workgroups(k)); };
@@ -1721,12 +2163,17 @@ int gram_split(int N, bool fp32) {
   return std::max(256, std::min(g, 1024));
 }
 
+size_t split_factor_elems(int N) {
+  return (size_t)((N + kBB - 1) / kBB * kBB) * (size_t)((N + 31) / 32 * 32);
+}
+
 size_t chol_workspace_doubles(int N) { return N <= 128 ? 0 : (size_t)(528 + 32) * kTile; }
 
 size_t gram_partial_doubles(int N, int nsplit) {
   if (N <= 128) return (size_t)nsplit * 128 * 128;
-  const int nb = (N + kGB - 1) / kGB;
-  return (size_t)nsplit * (nb * (nb + 1) / 2) * kGB * kGB;
+  const int nb = (N + kGB - 1) / kGB, nbb = (N + kBB - 1) / kBB;
+  return (size_t)nsplit * std::max((size_t)(nb * (nb + 1) / 2) * kGB * kGB,
+                                   (size_t)(nbb * (nbb + 1) / 2) * kBB * kBB);
 }
 
 template <typename T>
@@ -1778,6 +2225,25 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const d
     return hipGetLastError();
   }
   if (trial) return hipErrorInvalidValue;  // the engine forms the trial separately for N > 128
+  if (sizeof(T) == 4) {
+    const int nbb = (N + kBB - 1) / kBB;
+    const int npairs = nbb * (nbb + 1) / 2;
+    kper = ((kper + 63) / 64) * 64;
+    const int grid = ((nsplit + 7) / 8) * 8 * npairs;
+    const bool vec = (ng & 3) == 0;
+#define POU_GBIG(SP, V)                                                                   \
+  hipLaunchKernelGGL((k_gram_big<SP, V>), dim3(grid), dim3(kAB), 0, s, (const float *)W, N, ng, \
+                     kper, nsplit, npairs, part)
+    if (bf16) {
+      if (vec) POU_GBIG(false, true);
+      else POU_GBIG(false, false);
+    } else {
+      if (vec) POU_GBIG(true, true);
+      else POU_GBIG(true, false);
+    }
+#undef POU_GBIG
+    return hipGetLastError();
+  }
   const int nb = (N + kGB - 1) / kGB;
   const int npairs = nb * (nb + 1) / 2;
   kper = ((kper + kKC - 1) / kKC) * kKC;
@@ -1789,11 +2255,19 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const d
   return hipGetLastError();
 }
 
-hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
-                              hipStream_t s) {
+hipError_t launch_gram_reduce(const double *part, int N, int nsplit, bool fp32, double dv,
+                              double *G, hipStream_t s) {
   if (N <= 128) {
     hipLaunchKernelGGL(k_gram_reduce_small, dim3(128 * 128 / 64), dim3(kBlock), 0, s, part, N,
                        nsplit, dv, G);
+    return hipGetLastError();
+  }
+  if (fp32) {
+    const int nbb = (N + kBB - 1) / kBB;
+    const int npairs = nbb * (nbb + 1) / 2;
+    const int blocks = npairs * kBB * kBB / kBlock;
+    hipLaunchKernelGGL(k_gram_reduce_big, dim3(blocks), dim3(kBlock), 0, s, part, N, nsplit,
+                       npairs, dv, G);
     return hipGetLastError();
   }
   const int nb = (N + kGB - 1) / kGB;
@@ -1819,6 +2293,8 @@ hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, G, Minv, N, info);
+  int blocks = (int)std::min<i64>(1024, ((i64)N * N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_minv_to_d, dim3(blocks), dim3(kBlock), 0, s, Minv, N, D64, D32);
   return hipGetLastError();
 }
 
@@ -1852,7 +2328,8 @@ hipError_t launch_combine_factors(const double *A, const double *B, double *M, d
 
 template <typename T>
 hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, int N, i64 ng,
-                              const double *occ, double *rho, hipStream_t s) {
+                              const double *occ, double *rho, hipStream_t s,
+                              const double *ginfo, void *split_ws) {
   if (N <= 128) {
     const int NT = (N + 15) / 16;
     constexpr int GC = sizeof(T) == 4 ? 32 : 16;
@@ -1875,9 +2352,27 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
 #undef POU_APPLY_SMALL
     return hipGetLastError();
   }
+  if (rho != nullptr) return hipErrorInvalidValue;  // density is fused for N <= 128 only
+  if (sizeof(T) == 4) {
+    const int nJ = (N + kBB - 1) / kBB;
+    const i64 npt = (ng + kBB - 1) / kBB;
+    const i64 grid = ((npt + 7) / 8) * 8 * nJ;
+    if (grid > 0x7fffffff || split_ws == nullptr) return hipErrorInvalidValue;
+    __bf16 *Dh = (__bf16 *)split_ws;
+    __bf16 *Dl = Dh + split_factor_elems(N);
+    const int sb = (int)std::min<i64>(1024, (split_factor_elems(N) + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_split_factor, dim3(sb), dim3(kBlock), 0, s, (const float *)D, ginfo, N,
+                       Dh, Dl);
+    if ((ng & 3) == 0)
+      hipLaunchKernelGGL(k_apply_big<true>, dim3((unsigned)grid), dim3(kAB), 0, s, Dh, Dl, ginfo,
+                         (const float *)X, (float *)out, N, ng);
+    else
+      hipLaunchKernelGGL(k_apply_big<false>, dim3((unsigned)grid), dim3(kAB), 0, s, Dh, Dl, ginfo,
+                         (const float *)X, (float *)out, N, ng);
+    return hipGetLastError();
+  }
   const int NT = (N + 15) / 16;
   const int groups = (NT + 7) / 8;
-  if (rho != nullptr && groups != 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)((ng + 63) / 64), groups);
   hipLaunchKernelGGL(k_apply_lower<T>, grid, dim3(kBlock), 0, s, M, X, out, N, ng, occ, rho);
   return hipGetLastError();
@@ -1895,10 +2390,10 @@ template hipError_t launch_gram_partial<float>(const float *, int, i64, int, dou
                                                hipStream_t);
 template hipError_t launch_apply_lower<double>(const double *, const double *, const double *,
                                                double *, int, i64, const double *, double *,
-                                               hipStream_t);
+                                               hipStream_t, const double *, void *);
 template hipError_t launch_apply_lower<float>(const double *, const float *, const float *,
                                               float *, int, i64, const double *, double *,
-                                              hipStream_t);
+                                              hipStream_t, const double *, void *);
 
 
 int cross_gram_split(int N) {

@@ -84,6 +84,7 @@ struct pou_ctx {
   double *d_G = nullptr, *d_Minv = nullptr, *d_Minv2 = nullptr, *d_Mcomb = nullptr;
   double *d_D64 = nullptr;
   float *d_D32 = nullptr;
+  void *d_fsplit = nullptr;  // BF16 pieces of the factor (FP32 orbitals, N > 128)
   double *d_cholws = nullptr;  // blocked Cholesky tiles when N > 128
   double *d_red = nullptr;     // small reduction outputs
   double *d_S = nullptr, *d_P = nullptr, *d_xpart = nullptr;  // subspace rotation / residual
@@ -175,6 +176,7 @@ void free_all(pou_ctx *c) {
   c->d_scal = nullptr;
   c->d_D64 = nullptr;
   c->d_D32 = nullptr;
+  c->d_fsplit = nullptr;
   c->d_cholws = nullptr;
   c->d_rep[0] = c->d_rep[1] = nullptr;
   c->d_HW = c->d_HWt = c->d_Wt = c->d_W1 = c->d_W2 = nullptr;
@@ -445,7 +447,8 @@ pou_status gram(pou_ctx *c, const T *X, bool bf16) {
                                             c->d_gpart, s));
   else
     KL(POU_K_GRAM, pou::launch_gram_partial<T>(X, c->N, c->ng, c->nsplit, c->d_gpart, s));
-  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->es == 4, c->dv,
+                                                c->d_G, s));
   return POU_OK;
 }
 
@@ -468,7 +471,8 @@ pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info,
     T *dst = last ? out : (T *)c->d_W1;
     if (cur == dst) return fail(c, POU_ERR_ARG, "internal: aliasing orth buffers");
     double *rho = (last && want_rho && fused_ok) ? c->d_rho : nullptr;
-    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), cur, dst, c->N, c->ng, c->d_occ, rho, s));
+    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), cur, dst, c->N, c->ng, c->d_occ,
+                                               rho, s, info + 2 * p, c->d_fsplit));
     if (rho) *rho_done = true;
     cur = dst;
   }
@@ -487,7 +491,8 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
   KL(POU_K_TRIAL, pou::launch_trial_gram<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, tscale,
                                            (T *)c->d_Wt, c->N, c->ng, c->nsplit,
                                            mixed && passes == 2, c->d_gpart, s));
-  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->es == 4, c->dv,
+                                                c->d_G, s));
   KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
                                                   info, c->d_cholws, s));
   if (passes == 2) {
@@ -502,7 +507,8 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
                                                0.0, nullptr, c->N, c->ng, c->nsplit, false,
                                                c->d_gpart, s));
     }
-    KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+    KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->es == 4, c->dv,
+                                                c->d_G, s));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv2, c->d_D32, c->d_D64, c->N,
                                                     info + 2, c->d_cholws, s));
     KL(POU_K_CHOLESKY, pou::launch_combine_factors(c->d_Minv2, c->d_Minv, c->d_Mcomb, c->d_D64,
@@ -934,7 +940,8 @@ pou_status orthonormalize_impl(pou_ctx *c, T *U, double *orth_err) {
     CHK(gram<T>(c, src, false));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
                                                        c->d_red, c->d_cholws, s));
-    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), src, dst, c->N, c->ng, nullptr, nullptr, s));
+    KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), src, dst, c->N, c->ng, nullptr,
+                                               nullptr, s, c->d_red, c->d_fsplit));
     CHK(sync_read(c, info, c->d_red, sizeof(info)));
     if (!std::isfinite(info[1])) return fail(c, POU_ERR_NONFINITE, "U is not finite");
     if (info[0] != 0.0)
@@ -1159,10 +1166,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   c->nblk_orb = (int)std::max<i64>(1, std::min<i64>(64, ng / 16384));
   const int nb64 = (norb + 63) / 64;
   c->npairs = nb64 * (nb64 + 1) / 2;
-  c->nsplit = (int)std::max<i64>(
-      1, std::min<i64>(norb <= 128 ? pou::gram_split(norb, c->es == 4)
-                                   : std::max(1, 1024 / c->npairs),
-                       (ng + 31) / 32));
+  c->nsplit = (int)std::max<i64>(1, std::min<i64>(pou::gram_split(norb, c->es == 4), (ng + 31) / 32));
 
   const size_t fbytes = sizeof(double) * (size_t)ng;
   const size_t bbytes = c->es * (size_t)ng * norb;
@@ -1189,6 +1193,8 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_gpart, sizeof(double) * pou::gram_partial_doubles(norb, c->nsplit)));
   CHK(dalloc(c, &c->d_D64, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_D32, sizeof(float) * (size_t)norb * norb));
+  if (c->es == 4 && norb > 128)
+    CHK(dalloc(c, &c->d_fsplit, 2 * sizeof(uint16_t) * pou::split_factor_elems(norb)));
   if (pou::chol_workspace_doubles(norb) > 0)
     CHK(dalloc(c, &c->d_cholws, sizeof(double) * pou::chol_workspace_doubles(norb)));
   CHK(dalloc(c, &c->d_G, sizeof(double) * (size_t)norb * norb));
