@@ -1677,6 +1677,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
 
 constexpr int kBB = 128;  // row block of the N > 128 Gram and apply kernels
 constexpr int kBP = 40;   // LDS pitch (BF16) of a 32-wide chunk: 80-byte, 16-byte aligned rows
+constexpr int kAT = 256;  // threads of the N > 128 apply
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
 // Work item of workgroup b when items come in groups of `per` that read the
@@ -1730,8 +1731,43 @@ void k_gram_big(const float *__restrict__ A, int N, i64 ng,
   // addresses and zero what lies outside, with non-short-circuit tests: no
   // branch, so they all stay in flight (a diagonal block loads its rows twice;
   // the second copy comes from the caches).
+  // VEC (ng % 4 == 0 and 128 rows of a block span < 4 GiB): 32-bit offsets
+  // inside the row block, fixed per lane (rows past N clamped to the last one:
+  // their Gram entries are never read), on a uniform base per block and chunk;
+  // the chunk start is clamped so that the last chunk ends at ng, and the points
+  // it repeats are zeroed (a uniform test, false but for that chunk).
   float4 v[NV];
+  unsigned voff[VEC ? NV : 1];
+  const int c4l = (t & 15) * 4;  // the point offset of every slot of this lane
+  if (VEC) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int row = (t + kAB * e) >> 4;
+      const int rb = row < kBB ? bi : bj, r = row & (kBB - 1);
+      voff[VEC ? e : 0] = (unsigned)((i64)min(r, N - 1 - rb * kBB) * ng + c4l);
+    }
+  }
+  const float *abase = A + (i64)bi * kBB * ng, *bbase = A + (i64)bj * kBB * ng;
   auto load = [&](i64 k0) {
+    if (VEC) {
+      const i64 k0c = min(k0, ng - KC);
+      const float *pa = abase + k0c, *pb = bbase + k0c;
+#pragma unroll
+      for (int e = 0; e < NV; ++e)
+        v[e] = *(const float4 *)((e < NV / 2 ? pa : pb) + voff[VEC ? e : 0]);
+      const int shift = (int)(k0 - k0c);
+      if (shift > 0) {
+        const bool ok = c4l >= shift;
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+          v[e].x = ok ? v[e].x : 0.f;
+          v[e].y = ok ? v[e].y : 0.f;
+          v[e].z = ok ? v[e].z : 0.f;
+          v[e].w = ok ? v[e].w : 0.f;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
       const int f = t + kAB * e;
@@ -1741,14 +1777,7 @@ void k_gram_big(const float *__restrict__ A, int N, i64 ng,
       const float *p = A + (i64)min(grow, N - 1) * ng;
       const i64 g = k0 + c4;
       float4 x;
-      if (VEC) {
-        x = *(const float4 *)(p + min(g, ng - 4));
-        const bool ok = rok & (g < k_end);
-        x.x = ok ? x.x : 0.f;
-        x.y = ok ? x.y : 0.f;
-        x.z = ok ? x.z : 0.f;
-        x.w = ok ? x.w : 0.f;
-      } else {
+      {
         x.x = p[min(g, ng - 1)];
         x.y = p[min(g + 1, ng - 1)];
         x.z = p[min(g + 2, ng - 1)];
@@ -1931,17 +1960,19 @@ __global__ __launch_bounds__(kBlock) void k_split_factor(const float *__restrict
 // shrinks the rows strongly (D near -I: the sum cancels), as in the first pass
 // over an unnormalised block; when ginfo[1] (max |G - I| of the Gram the factor
 // came from) is 0.25 or more, the kernel multiplies by M = I + D itself (the
-// pieces from k_split_factor hold M then) and adds nothing.  Workgroup = (row block J of 128 output
-// orbitals, tile of 128 grid points); the row blocks of one point tile share
-// an XCD, heaviest first.  Eight waves in a 4 x 2 grid: wave (rw, cw) forms
-// (D X)^T for orbitals 32 rw .. 32 rw + 31 of the block and points 64 cw ..
-// 64 cw + 63 (2 x 4 tiles).  The K loop runs over 32-orbital chunks up to the
-// wave's diagonal; per chunk X is staged in LDS transposed ([point][orbital],
-// split into hi/lo pieces on the way) and the block's rows of the factor
-// pieces as [orbital][k], double-buffered with the next chunk's loads in
-// flight.  out must not alias X.
+// pieces from k_split_factor hold M then) and adds nothing.
+//
+// Workgroup = (row block J of 128 output orbitals, tile of 128 grid points);
+// the row blocks of one point tile share an XCD, heaviest first.  Four waves
+// in a 2 x 2 grid: wave (rw, cw) forms (D X)^T for orbitals 64 rw .. 64 rw + 63
+// of the block and points 64 cw .. 64 cw + 63 (4 x 4 tiles), so each fragment
+// read from LDS feeds four products.  The K loop runs over 32-orbital chunks
+// up to the wave's diagonal; per chunk X is staged in LDS transposed
+// ([point][orbital], split into hi/lo pieces on the way) and the block's rows
+// of the factor pieces as [orbital][k], in two LDS stages, while two register
+// sets keep the loads of the next two chunks in flight.  out must not alias X.
 template <bool VEC>
-__global__ __launch_bounds__(kAB) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kAT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
                  const double *__restrict__ ginfo, const float *__restrict__ X,
                  float *__restrict__ out, int N, i64 ng) {
@@ -1959,65 +1990,77 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
   const int rw = w >> 1, cw = w & 1;
-  const int wkc = min(nkc, 4 * J + rw + 1);  // chunks that reach this wave's orbitals
-  // loaders: X point xp, orbitals xo .. xo + 7 of the chunk; D row dr, columns dc .. dc + 7
-  const int xp = t & (kBB - 1), xo = 8 * (t >> 7);
-  const int dr = t >> 2, dc = 8 * (t & 3);
-  const i64 gx = g0 + xp;
-  const int jrow = J * kBB + dr;
+  const int wkc = min(nkc, 4 * J + 2 * rw + 2);  // chunks that reach this wave's orbitals
   const bool ident = ginfo == nullptr || !(ginfo[1] >= 0.25);
-  // X loads read clamped (always valid) addresses and zero what lies outside:
-  // no divergent branch, so every load of a chunk stays in flight; the factor
-  // pieces are padded, so their loads need no test at all
-  const float *xcol = X + min(gx, ng - 1);
+  // loaders: X point xp, orbitals xo .. xo + 15 of the chunk; factor row dr,
+  // columns dc .. dc + 15
+  // The orbital of an X load is uniform over a wave (xo is), so its row base
+  // sits in scalar registers and each lane adds only its 32-bit point offset.
+  // Rows past N and points past ng are clamped to the last ones instead of
+  // tested: such rows meet zero factor columns (the pieces are padded), and a
+  // point's column of D X depends on that point's values only, so clamped
+  // points affect nothing that is stored.
+  const int xp = t & (kBB - 1);
+  const int xo = 16 * __builtin_amdgcn_readfirstlane(t >> 7);
+  const int dr = t >> 1, dc = 16 * (t & 1);
+  const unsigned gxc = (unsigned)min(g0 + xp, ng - 1);
   const int NC = (N + 31) / 32 * 32;
-  const __bf16 *dhr = Dh + (i64)jrow * NC + dc;
-  const __bf16 *dlr = Dl + (i64)jrow * NC + dc;
-  float xv[8];
-  bf8 fh, fl;
-  auto load = [&](int kc) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int i = 32 * kc + xo + e;
-      const float x = xcol[(i64)min(i, N - 1) * ng];
-      xv[e] = ((i < N) & (gx < ng)) ? x : 0.0f;  // & not &&: no branch around the load
-    }
-    fh = *(const bf8 *)(dhr + 32 * kc);
-    fl = *(const bf8 *)(dlr + 32 * kc);
+  const unsigned doff = (unsigned)(dr * NC + dc);
+  const __bf16 *dhb = Dh + (i64)J * kBB * NC, *dlb = Dl + (i64)J * kBB * NC;
+  struct Stage {
+    float x[16];
+    bf8 h0, h1, l0, l1;
   };
-  auto stash = [&](int b) {
-    bf8 h1, l1;
+  auto load = [&](Stage &st, int kc) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      __bf16 a, c;
-      split_bf16(xv[e], a, c);
-      h1[e] = a;
-      l1[e] = c;
+    for (int e = 0; e < 16; ++e) {
+      const int i = min(32 * kc + xo + e, N - 1);
+      st.x[e] = (X + (i64)i * ng)[gxc];
     }
-    *(bf8 *)&xh[b][xp][xo] = h1;
-    *(bf8 *)&xl[b][xp][xo] = l1;
-    *(bf8 *)&dh[b][dr][dc] = fh;
-    *(bf8 *)&dl[b][dr][dc] = fl;
+    const __bf16 *ph = dhb + 32 * kc, *pl = dlb + 32 * kc;
+    st.h0 = *(const bf8 *)(ph + doff);
+    st.h1 = *(const bf8 *)(ph + doff + 8);
+    st.l0 = *(const bf8 *)(pl + doff);
+    st.l1 = *(const bf8 *)(pl + doff + 8);
   };
-  f4 acc[2][4];
+  auto stash = [&](const Stage &st, int b) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int hlf = 0; hlf < 2; ++hlf) {
+      bf8 hv, lv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 a, c;
+        split_bf16(st.x[8 * hlf + e], a, c);
+        hv[e] = a;
+        lv[e] = c;
+      }
+      *(bf8 *)&xh[b][xp][xo + 8 * hlf] = hv;
+      *(bf8 *)&xl[b][xp][xo + 8 * hlf] = lv;
+    }
+    *(bf8 *)&dh[b][dr][dc] = st.h0;
+    *(bf8 *)&dh[b][dr][dc + 8] = st.h1;
+    *(bf8 *)&dl[b][dr][dc] = st.l0;
+    *(bf8 *)&dl[b][dr][dc + 8] = st.l1;
+  };
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = f4{0, 0, 0, 0};
   auto compute = [&](int b, int kc) {
     if (kc >= wkc) return;
-    bf8 bh[2], bl[2];
+    bf8 bh[4], bl[4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      bh[a] = *(const bf8 *)&dh[b][32 * rw + 16 * a + r16][8 * q];
-      bl[a] = *(const bf8 *)&dl[b][32 * rw + 16 * a + r16][8 * q];
+    for (int a = 0; a < 4; ++a) {
+      bh[a] = *(const bf8 *)&dh[b][64 * rw + 16 * a + r16][8 * q];
+      bl[a] = *(const bf8 *)&dl[b][64 * rw + 16 * a + r16][8 * q];
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const bf8 ah = *(const bf8 *)&xh[b][64 * cw + 16 * c + r16][8 * q];
       const bf8 al = *(const bf8 *)&xl[b][64 * cw + 16 * c + r16][8 * q];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < 4; ++a) {
         f4 x = acc[a][c];
         x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl[a], x, 0, 0, 0);
         x = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[a], x, 0, 0, 0);
@@ -2027,25 +2070,33 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
       }
     }
   };
-  // last chunk peeled: the next chunk's loads and stores stay unconditional
-  // in the loop, so they are not merged ahead of the products
-  load(0);
-  stash(0);
+  // Two chunks per trip, every load and store unconditional (chunk indices
+  // beyond the last are clamped to it: their stages are never multiplied), so
+  // the compiler cannot merge them ahead of the products.  Invariant at the
+  // top: LDS stage 0 holds chunk kc and register set sa has chunk kc + 1 in
+  // flight.
+  Stage sa, sb;
+  load(sa, 0);
+  stash(sa, 0);
   __syncthreads();
-  int kc = 0;
-  for (; kc + 1 < nkc; ++kc) {
-    load(kc + 1);
-    compute(kc & 1, kc);
+  load(sa, min(1, nkc - 1));
+  for (int kc = 0; kc < nkc; kc += 2) {
+    load(sb, min(kc + 2, nkc - 1));
+    compute(0, kc);
     __builtin_amdgcn_sched_barrier(0);
-    stash((kc & 1) ^ 1);
+    stash(sa, 1);
+    __syncthreads();
+    load(sa, min(kc + 3, nkc - 1));
+    compute(1, kc + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    stash(sb, 0);
     __syncthreads();
   }
-  compute(kc & 1, kc);
   // lane (r16, q) of tile (a, c) holds orbital 16 a + r16 at points 4 q .. 4 q + 3;
   // per row tile, the identity loads are issued (clamped) before any store
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int j = J * kBB + 32 * rw + 16 * a + r16;
+  for (int a = 0; a < 4; ++a) {
+    const int j = J * kBB + 64 * rw + 16 * a + r16;
     float4 xi[4];
     const float *xr = X + (i64)min(j, N - 1) * ng;
 #pragma unroll
@@ -2061,10 +2112,10 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const i64 g = g0 + 64 * cw + 16 * c + 4 * q;
-      const float w = ident ? 1.0f : 0.0f;
+      const float wgt = ident ? 1.0f : 0.0f;
       const float4 x = xi[c];
-      const float4 o = make_float4(w * x.x + acc[a][c][0], w * x.y + acc[a][c][1],
-                                   w * x.z + acc[a][c][2], w * x.w + acc[a][c][3]);
+      const float4 o = make_float4(wgt * x.x + acc[a][c][0], wgt * x.y + acc[a][c][1],
+                                   wgt * x.z + acc[a][c][2], wgt * x.w + acc[a][c][3]);
       float *orow = out + (i64)j * ng + g;
       if (j < N) {
         if (VEC) {
@@ -2230,7 +2281,7 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const d
     const int npairs = nbb * (nbb + 1) / 2;
     kper = ((kper + 63) / 64) * 64;
     const int grid = ((nsplit + 7) / 8) * 8 * npairs;
-    const bool vec = (ng & 3) == 0;
+    const bool vec = (ng & 3) == 0 && ng >= 64 && (i64)kBB * ng * 4 < (1LL << 32);
 #define POU_GBIG(SP, V)                                                                   \
   hipLaunchKernelGGL((k_gram_big<SP, V>), dim3(grid), dim3(kAB), 0, s, (const float *)W, N, ng, \
                      kper, nsplit, npairs, part)
@@ -2364,10 +2415,10 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
     hipLaunchKernelGGL(k_split_factor, dim3(sb), dim3(kBlock), 0, s, (const float *)D, ginfo, N,
                        Dh, Dl);
     if ((ng & 3) == 0)
-      hipLaunchKernelGGL(k_apply_big<true>, dim3((unsigned)grid), dim3(kAB), 0, s, Dh, Dl, ginfo,
+      hipLaunchKernelGGL(k_apply_big<true>, dim3((unsigned)grid), dim3(kAT), 0, s, Dh, Dl, ginfo,
                          (const float *)X, (float *)out, N, ng);
     else
-      hipLaunchKernelGGL(k_apply_big<false>, dim3((unsigned)grid), dim3(kAB), 0, s, Dh, Dl, ginfo,
+      hipLaunchKernelGGL(k_apply_big<false>, dim3((unsigned)grid), dim3(kAT), 0, s, Dh, Dl, ginfo,
                          (const float *)X, (float *)out, N, ng);
     return hipGetLastError();
   }
