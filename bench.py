@@ -75,17 +75,22 @@ def mfma_floor(group, N, ng, es):
     A triangular apply L^-1 X and a symmetric Gram X X^T each take N(N+1)
     flops per grid point.  The mixed first Gram runs on BF16 MFMA; the fused
     apply + second Gram does the apply in FP32 and the Gram as four BF16
-    products (hi/lo split), so its floor is the sum of the two parts."""
+    products (hi/lo split), so its floor is the sum of the two parts.  Above
+    128 FP32 orbitals the apply and the second Gram are four split-BF16
+    products each."""
     tri = float(N * (N + 1) * ng)
     wide = "f64" if es == 8 else "f32"
+    big = es == 4 and N > 128  # FP32 orbitals above 128: split-BF16 kernels
     if group == "apply":
-        return tri, tri / PEAK_FLOPS[wide]
+        return tri, (4 * tri / PEAK_FLOPS["bf16"]) if big else tri / PEAK_FLOPS[wide]
     if group == "apply_gram":
         return 2 * tri, tri / PEAK_FLOPS["f32"] + 4 * tri / PEAK_FLOPS["bf16"]
     if group == "trial":
         return tri, tri / PEAK_FLOPS["bf16" if es == 4 else "f64"]
     if group == "gram":
-        return tri, tri / PEAK_FLOPS[wide]
+        # above 128 FP32 orbitals the group alternates the BF16 first Gram and
+        # the split-BF16 (four products) second Gram: 2.5 products on average
+        return tri, (2.5 * tri / PEAK_FLOPS["bf16"]) if big else tri / PEAK_FLOPS[wide]
     return 0.0, 0.0
 
 
