@@ -18,9 +18,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int kGB = 64;   // Gram output block (rows and columns)
-constexpr int kKC = 32;   // grid points staged per chunk
-constexpr int kPitch = kKC + 1;
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -57,167 +54,6 @@ __device__ inline void decode_pair(int pair, int nb, int &bi, int &bj) {
   }
   bi = i;
   bj = i + p;
-}
-
-// Partial Gram over a contiguous range of grid points for one 64x64 output
-// block (bi <= bj).  MFMA 16x16x4: lane l supplies A[l%16][k = l/16] and
-// B[k = l/16][l%16]; output register r of lane l is row out_row(l/16, r),
-// column l%16.  FP32 accumulators are flushed into FP64 after every chunk.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gram(const T *__restrict__ A, int N, i64 ng,
-                                                 i64 kper, double *__restrict__ part) {
-  __shared__ T sA[kGB][kPitch];
-  __shared__ T sB[kGB][kPitch];
-  typedef typename AccOf<T>::type Acc;
-  const int split = blockIdx.x;
-  const int pair = blockIdx.y;
-  const int npairs = gridDim.y;
-  const int nb = (N + kGB - 1) / kGB;
-  int bi, bj;
-  decode_pair(pair, nb, bi, bj);
-  const i64 k_beg = (i64)split * kper;
-  const i64 k_end = min(ng, k_beg + kper);
-  const int t = threadIdx.x;
-  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
-  Acc acc[4];
-  double accd[4][4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    acc[c] = Acc{0, 0, 0, 0};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) accd[c][r] = 0.0;
-  }
-  const bool diag = (bi == bj);
-  for (i64 k0 = k_beg; k0 < k_end; k0 += kKC) {
-    const int col = t & 31;
-    const i64 g = k0 + col;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int row = (t >> 5) + 8 * e;
-      const int ra = bi * kGB + row;
-      sA[row][col] = (ra < N && g < k_end) ? A[(i64)ra * ng + g] : (T)0;
-      if (!diag) {
-        const int rb = bj * kGB + row;
-        sB[row][col] = (rb < N && g < k_end) ? A[(i64)rb * ng + g] : (T)0;
-      }
-    }
-    __syncthreads();
-    const T(*sb)[kPitch] = diag ? sA : sB;
-#pragma unroll
-    for (int ks = 0; ks < kKC / 4; ++ks) {
-      const T a = sA[16 * w + r16][4 * ks + q];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const T b = sb[16 * c + r16][4 * ks + q];
-        acc[c] = mfma(a, b, acc[c]);
-      }
-    }
-    __syncthreads();
-    if (sizeof(T) == 4) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) accd[c][r] += (double)acc[c][r];
-        acc[c] = Acc{0, 0, 0, 0};
-      }
-    }
-  }
-  double *out = part + ((i64)split * npairs + pair) * kGB * kGB;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * w + out_row<T>(q, r);
-      const int colo = 16 * c + r16;
-      out[row * kGB + colo] = (sizeof(T) == 4) ? accd[c][r] : (double)acc[c][r];
-    }
-  }
-}
-
-// Same contraction with the FP32 values rounded to BF16 and MFMA 16x16x32
-// (lane l supplies A[l%16][8(l/16) .. 8(l/16)+7]); FP32 accumulation per
-// 32-point chunk, flushed into FP64.
-constexpr int kPitchB = kKC + 4;
-__global__ __launch_bounds__(kBlock) void k_gram_bf16(const float *__restrict__ A, int N,
-                                                      i64 ng, i64 kper,
-                                                      double *__restrict__ part) {
-  __shared__ float sA[kGB][kPitchB];
-  __shared__ float sB[kGB][kPitchB];
-  const int split = blockIdx.x;
-  const int pair = blockIdx.y;
-  const int npairs = gridDim.y;
-  const int nb = (N + kGB - 1) / kGB;
-  int bi, bj;
-  decode_pair(pair, nb, bi, bj);
-  const i64 k_beg = (i64)split * kper;
-  const i64 k_end = min(ng, k_beg + kper);
-  const int t = threadIdx.x;
-  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
-  double accd[4][4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) accd[c][r] = 0.0;
-  const bool diag = (bi == bj);
-  for (i64 k0 = k_beg; k0 < k_end; k0 += kKC) {
-    const int col = t & 31;
-    const i64 g = k0 + col;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int row = (t >> 5) + 8 * e;
-      const int ra = bi * kGB + row;
-      sA[row][col] = (ra < N && g < k_end) ? A[(i64)ra * ng + g] : 0.0f;
-      if (!diag) {
-        const int rb = bj * kGB + row;
-        sB[row][col] = (rb < N && g < k_end) ? A[(i64)rb * ng + g] : 0.0f;
-      }
-    }
-    __syncthreads();
-    const float(*sb)[kPitchB] = diag ? sA : sB;
-    bf8 a;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) a[e] = (__bf16)sA[16 * w + r16][8 * q + e];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      bf8 b;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) b[e] = (__bf16)sb[16 * c + r16][8 * q + e];
-      f4 acc = f4{0, 0, 0, 0};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) accd[c][r] += (double)acc[r];
-    }
-    __syncthreads();
-  }
-  double *out = part + ((i64)split * npairs + pair) * kGB * kGB;
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      out[(16 * w + 4 * q + r) * kGB + 16 * c + r16] = accd[c][r];
-}
-
-// G[i][j] = dv * sum over splits of the block partials; both triangles.
-__global__ __launch_bounds__(kBlock) void k_gram_reduce(const double *__restrict__ part, int N,
-                                                        int nsplit, int npairs, double dv,
-                                                        double *__restrict__ G) {
-  const int nb = (N + kGB - 1) / kGB;
-  const i64 total = (i64)N * N;
-  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (i64)gridDim.x * blockDim.x) {
-    int i = (int)(e / N), j = (int)(e % N);
-    if (i > j) continue;  // fill both from the upper triangle
-    const int bi = i / kGB, bj = j / kGB;
-    // pair index for (bi, bj), bi <= bj
-    const int pair = bi * nb - (bi * (bi - 1)) / 2 + (bj - bi);
-    const int ri = i - bi * kGB, cj = j - bj * kGB;
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp)
-      s += part[(((i64)sp * npairs + pair) * kGB + ri) * kGB + cj];
-    s *= dv;
-    G[(i64)i * N + j] = s;
-    G[(i64)j * N + i] = s;
-  }
 }
 
 // Cholesky G = L L^T (lower, in place in G) and Minv = L^-1.  One workgroup.
@@ -348,100 +184,6 @@ __global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict
     }
   }
 }
-
-// C = A B for lower-triangular A, B (upper parts zero).
-__global__ __launch_bounds__(kBlock) void k_lower_matmul(const double *__restrict__ A,
-                                                         const double *__restrict__ B,
-                                                         double *__restrict__ C, int N) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
-    const int i = e / N, j = e % N;
-    double s = 0.0;
-    for (int k = j; k <= i; ++k) s += A[(i64)i * N + k] * B[(i64)k * N + j];
-    C[e] = (j <= i) ? s : 0.0;
-  }
-}
-
-// out[j][g] = X[j][g] + sum_i (M - I)[j][i] X[i][g] for lower-triangular M.
-// Written as identity plus correction so that the rounding of the result is
-// relative to the (small) correction.  Workgroup: 64 grid points x a group of
-// up to 8 row tiles of 16 orbitals; wave w takes row tiles w and w+4 of the
-// group.  X fragments are read straight from global memory in the MFMA
-// layout (16 consecutive grid points per k row).  Optional fused density
-// rho[g] = sum_j occ_j out[j][g]^2 when the group covers all orbitals.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_apply_lower(const double *__restrict__ M,
-                                                        const T *__restrict__ X,
-                                                        T *__restrict__ out, int N, i64 ng,
-                                                        const double *__restrict__ occ,
-                                                        double *__restrict__ rho) {
-  __shared__ double srho[4][64];
-  typedef typename AccOf<T>::type Acc;
-  const int t = threadIdx.x;
-  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
-  const i64 g0 = (i64)blockIdx.x * 64;
-  const int NT = (N + 15) / 16;
-  const int jt[2] = {(int)blockIdx.y * 8 + w, (int)blockIdx.y * 8 + w + 4};
-  const bool jv[2] = {jt[0] < NT, jt[1] < NT};
-  Acc acc[2][4];
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[u][c] = Acc{0, 0, 0, 0};
-  const int ks_end0 = jv[0] ? min(4 * (jt[0] + 1), (N + 3) / 4) : 0;
-  const int ks_end1 = jv[1] ? min(4 * (jt[1] + 1), (N + 3) / 4) : 0;
-  const int ks_end = max(ks_end0, ks_end1);
-  for (int ks = 0; ks < ks_end; ++ks) {
-    const int i = 4 * ks + q;
-    T b[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const i64 g = g0 + 16 * c + r16;
-      b[c] = (i < N && g < ng) ? X[(i64)i * ng + g] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      if (ks < (u == 0 ? ks_end0 : ks_end1)) {
-        const int j = 16 * jt[u] + r16;
-        const T a = (j < N && i < N) ? (T)(M[(i64)j * N + i] - (i == j ? 1.0 : 0.0)) : (T)0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[u][c] = mfma(a, b[c], acc[u][c]);
-      }
-    }
-  }
-  double rp[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    if (!jv[u]) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const i64 g = g0 + 16 * c + r16;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = 16 * jt[u] + out_row<T>(q, r);
-        if (j < N && g < ng) {
-          const T v = X[(i64)j * ng + g] + acc[u][c][r];
-          out[(i64)j * ng + g] = v;
-          rp[c] += occ ? occ[j] * (double)v * (double)v : 0.0;
-        }
-      }
-    }
-  }
-  if (rho != nullptr) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double v = rp[c];
-      v += __shfl_xor(v, 16, 64);
-      v += __shfl_xor(v, 32, 64);
-      if (q == 0) srho[w][16 * c + r16] = v;
-    }
-    __syncthreads();
-    if (t < 64) {
-      const i64 g = g0 + t;
-      if (g < ng) rho[g] = srho[0][t] + srho[1][t] + srho[2][t] + srho[3][t];
-    }
-  }
-}
-
 
 // ---------------------------------------------------------------- N <= 128
 
@@ -1930,6 +1672,243 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_big(const double *__rest
   G[(i64)j * N + i] = val;
 }
 
+// FP64 Gram for N > 128: the block pairs, ranges and XCD grouping of
+// k_gram_big, on FP64 MFMA 16x16x4 (lane l supplies row l%16 at point
+// k = l/16; FP64 accumulation, so no flushes).  Eight waves in a 4 x 2 grid:
+// wave (rw, cw) holds rows 32 rw .. 32 rw + 31 and columns 64 cw .. 64 cw + 63
+// of the block.  16-point chunks of both row blocks are staged in LDS
+// ([row][point], pitch 17 doubles: sixteen rows of one point column fall in
+// distinct bank pairs), double-buffered with the next chunk in flight in
+// registers.  VEC (ng even and 128 rows of a block span < 4 GiB): double2
+// loads at fixed per-lane 32-bit offsets on a uniform block base, the last
+// chunk clamped to the grid end and its repeated points zeroed.
+template <bool VEC>
+__global__ __launch_bounds__(kAB) __attribute__((amdgpu_waves_per_eu(4)))
+void k_gram_big64(const double *__restrict__ A, int N, i64 ng,
+                                                    i64 kper, int nsplit, int npairs,
+                                                    double *__restrict__ part) {
+  constexpr int KC = 16;
+  constexpr int PD = KC + 1;
+  constexpr int NV = 2 * kBB * KC / 2 / kAB;  // double2 loads per thread per chunk (4)
+  __shared__ double sd[2][2][kBB][PD];
+  int split, pair;
+  xcd_group(blockIdx.x, npairs, split, pair);
+  if (split >= nsplit) return;
+  const int nb = (N + kBB - 1) / kBB;
+  int bi, bj;
+  decode_pair(pair, nb, bi, bj);
+  const bool diag = bi == bj;
+  const i64 k_beg = (i64)split * kper;
+  const i64 k_end = min(ng, k_beg + kper);
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int rw = w >> 1, cw = w & 1;
+  const bool idle = diag && cw == 0 && rw >= 2;
+  // slot e: double2 f = t + 512 e, row f / 8 (block bi for e < NV / 2, bj after), points 2 (f % 8)
+  const int c2 = (t & 7) * 2;
+  double2 v[NV];
+  unsigned voff[VEC ? NV : 1];
+  if (VEC) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int row = (t + kAB * e) >> 3;
+      const int rb = row < kBB ? bi : bj, r = row & (kBB - 1);
+      voff[VEC ? e : 0] = (unsigned)((i64)min(r, N - 1 - rb * kBB) * ng + c2);
+    }
+  }
+  const double *abase = A + (i64)bi * kBB * ng, *bbase = A + (i64)bj * kBB * ng;
+  auto load = [&](i64 k0) {
+    if (VEC) {
+      const i64 k0c = min(k0, ng - KC);
+      const double *pa = abase + k0c, *pb = bbase + k0c;
+#pragma unroll
+      for (int e = 0; e < NV; ++e)
+        v[e] = *(const double2 *)((e < NV / 2 ? pa : pb) + voff[VEC ? e : 0]);
+      const int shift = (int)(k0 - k0c);
+      if (shift > 0) {
+        const bool ok = c2 >= shift;
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+          v[e].x = ok ? v[e].x : 0.0;
+          v[e].y = ok ? v[e].y : 0.0;
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int row = (t + kAB * e) >> 3;
+      const int grow = row < kBB ? bi * kBB + row : bj * kBB + row - kBB;
+      const double *p = A + (i64)min(grow, N - 1) * ng;
+      const i64 g = k0 + c2;
+      double2 x;
+      x.x = p[min(g, ng - 1)];
+      x.y = p[min(g + 1, ng - 1)];
+      x.x = (g < k_end) ? x.x : 0.0;
+      x.y = (g + 1 < k_end) ? x.y : 0.0;
+      v[e] = x;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int row = (t + kAB * e) >> 3;
+      const int blk = row >= kBB ? 1 : 0, r = row & (kBB - 1);
+      sd[b][blk][r][c2] = v[e].x;
+      sd[b][blk][r][c2 + 1] = v[e].y;
+    }
+  };
+  d4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = d4{0, 0, 0, 0};
+  auto compute = [&](int b) {
+    if (idle) return;
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      double av[2], bv[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = sd[b][0][32 * rw + 16 * a + r16][4 * ks + q];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = sd[b][1][64 * cw + 16 * c + r16][4 * ks + q];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = mfma(av[a], bv[c], acc[a][c]);
+    }
+  };
+  const i64 nchunk = k_end > k_beg ? (k_end - k_beg + KC - 1) / KC : 0;
+  if (nchunk > 0) {
+    load(k_beg);
+    stash(0);
+  }
+  __syncthreads();
+  int b = 0;
+  for (i64 ch = 0; ch + 1 < nchunk; ++ch, b ^= 1) {
+    load(k_beg + KC * (ch + 1));
+    compute(b);
+    __builtin_amdgcn_sched_barrier(0);
+    stash(b ^ 1);
+    __syncthreads();
+  }
+  if (nchunk > 0) compute(b);
+  if (idle) return;
+  double *out = part + ((i64)split * npairs + pair) * kBB * kBB;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(32 * rw + 16 * a + q + 4 * r) * kBB + 64 * cw + 16 * c + r16] = acc[a][c][r];
+}
+
+// out = X + D X for lower-triangular D = L^-1 - I (FP64 N x N) and FP64
+// orbitals, N > 128, on FP64 MFMA: the (row block J, 128-point tile)
+// workgroups of k_apply_big, eight waves in a 4 x 2 grid, wave (rw, cw)
+// forming rows 32 rw .. 32 rw + 31 of the block at points 64 cw .. 64 cw + 63
+// (2 x 4 tiles).  An FP64 MFMA needs one value per lane (lane l: row l%16 of
+// D at k = l/16; X at k = l/16, point l%16), so X is staged in LDS in its own
+// [orbital][point] layout and D as [row][k] (pitch 17 doubles), 16-orbital
+// chunks, double-buffered.  Loads read clamped addresses: rows of X past N
+// meet zero D columns, points past ng are never stored.  out must not alias X.
+__global__ __launch_bounds__(kAB) void k_apply_big64(const double *__restrict__ D,
+                                                     const double *__restrict__ X,
+                                                     double *__restrict__ out, int N, i64 ng) {
+  constexpr int KC = 16;
+  __shared__ double ds[2][kBB][KC + 1];
+  __shared__ double xs[2][KC][kBB];
+  const int nJ = (N + kBB - 1) / kBB;
+  int ptile, jj;
+  xcd_group(blockIdx.x, nJ, ptile, jj);
+  const int J = nJ - 1 - jj;
+  const i64 g0 = (i64)ptile * kBB;
+  if (g0 >= ng) return;
+  const int nkc = min(8 * (J + 1), (N + KC - 1) / KC);
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int rw = w >> 1, cw = w & 1;
+  const int wkc = min(nkc, 8 * J + 2 * rw + 2);  // 16-orbital chunks reaching this wave's rows
+  // loaders: D row dr, columns dc .. dc + 3 of the chunk; X orbital xo, points xq .. xq + 3
+  const int dr = t >> 2, dc = 4 * (t & 3);
+  const int jrow = J * kBB + dr;
+  const double *drow = D + (i64)min(jrow, N - 1) * N;
+  const int xo = t >> 5, xq = 4 * (t & 31);
+  double dv[4], xv[4];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = KC * kc + dc + e;
+      const double d = drow[min(i, N - 1)];
+      dv[e] = ((jrow < N) & (i < N)) ? d : 0.0;
+    }
+    const double *xr = X + (i64)min(KC * kc + xo, N - 1) * ng;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xv[e] = xr[min(g0 + xq + e, ng - 1)];
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ds[b][dr][dc + e] = dv[e];
+      xs[b][xo][xq + e] = xv[e];
+    }
+  };
+  d4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = d4{0, 0, 0, 0};
+  auto compute = [&](int b, int kc) {
+    if (kc >= wkc) return;
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      double av[2], bv[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = ds[b][32 * rw + 16 * a + r16][4 * ks + q];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = xs[b][4 * ks + q][64 * cw + 16 * c + r16];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = mfma(av[a], bv[c], acc[a][c]);
+    }
+  };
+  load(0);
+  stash(0);
+  __syncthreads();
+  int kc = 0;
+  for (; kc + 1 < nkc; ++kc) {
+    load(kc + 1);
+    compute(kc & 1, kc);
+    __builtin_amdgcn_sched_barrier(0);
+    stash((kc & 1) ^ 1);
+    __syncthreads();
+  }
+  compute(kc & 1, kc);
+  // lane (r16, q) of tile (a, c) holds rows q + 4 r of the tile at point r16
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    double xi[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = min(J * kBB + 32 * rw + 16 * a + q + 4 * r, N - 1);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        xi[r][c] = X[(i64)j * ng + min(g0 + 64 * cw + 16 * c + r16, ng - 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = J * kBB + 32 * rw + 16 * a + q + 4 * r;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const i64 g = g0 + 64 * cw + 16 * c + r16;
+        if (j < N && g < ng) out[(i64)j * ng + g] = xi[r][c] + acc[a][c][r];
+      }
+    }
+  }
+}
+
 // BF16 hi/lo pieces of the factor for k_apply_big, padded to whole 128-row
 // blocks and 32-column chunks (zeros outside N x N, so the apply loads them
 // without bounds tests): the correction D, or M = I + D (formed in FP32) when
@@ -2172,16 +2151,15 @@ int resident_workgroups(const void *kernel, int block = kBlock) {
 
 int gram_split(int N, bool fp32) {
   if (N > 128) {
-    if (!fp32) {
-      const int nb = (N + kGB - 1) / kGB;
-      return std::max(1, 1024 / (nb * (nb + 1) / 2));
-    }
-    // k_gram_big: a multiple of 8 ranges (one XCD per range), the workgroup
-    // count as close to whole rounds of the resident ones as 2 .. 6 rounds allow
+    // k_gram_big / k_gram_big64: a multiple of 8 ranges (one XCD per range),
+    // the workgroup count as close to whole rounds of the resident ones as
+    // 2 .. 6 rounds allow
     const int nb = (N + kBB - 1) / kBB;
     const int npairs = nb * (nb + 1) / 2;
-    const int res = std::min(resident_workgroups((const void *)k_gram_big<true, true>, kAB),
-                             resident_workgroups((const void *)k_gram_big<false, true>, kAB));
+    const int res =
+        fp32 ? std::min(resident_workgroups((const void *)k_gram_big<true, true>, kAB),
+                        resident_workgroups((const void *)k_gram_big<false, true>, kAB))
+             : resident_workgroups((const void *)k_gram_big64<true>, kAB);
     int best = 8;
     double best_eff = 0.0;
     for (int rounds = 2; rounds <= 6; ++rounds) {
@@ -2222,9 +2200,8 @@ size_t chol_workspace_doubles(int N) { return N <= 128 ? 0 : (size_t)(528 + 32) 
 
 size_t gram_partial_doubles(int N, int nsplit) {
   if (N <= 128) return (size_t)nsplit * 128 * 128;
-  const int nb = (N + kGB - 1) / kGB, nbb = (N + kBB - 1) / kBB;
-  return (size_t)nsplit * std::max((size_t)(nb * (nb + 1) / 2) * kGB * kGB,
-                                   (size_t)(nbb * (nbb + 1) / 2) * kBB * kBB);
+  const int nbb = (N + kBB - 1) / kBB;
+  return (size_t)nsplit * (size_t)(nbb * (nbb + 1) / 2) * kBB * kBB;
 }
 
 template <typename T>
@@ -2276,6 +2253,20 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const d
     return hipGetLastError();
   }
   if (trial) return hipErrorInvalidValue;  // the engine forms the trial separately for N > 128
+  if (sizeof(T) == 8) {
+    const int nbb = (N + kBB - 1) / kBB;
+    const int npairs = nbb * (nbb + 1) / 2;
+    kper = ((kper + 15) / 16) * 16;
+    const int grid = ((nsplit + 7) / 8) * 8 * npairs;
+    const bool vec = (ng & 1) == 0 && ng >= 16 && (i64)kBB * ng * 8 < (1LL << 32);
+    if (vec)
+      hipLaunchKernelGGL(k_gram_big64<true>, dim3(grid), dim3(kAB), 0, s, (const double *)W, N,
+                         ng, kper, nsplit, npairs, part);
+    else
+      hipLaunchKernelGGL(k_gram_big64<false>, dim3(grid), dim3(kAB), 0, s, (const double *)W, N,
+                         ng, kper, nsplit, npairs, part);
+    return hipGetLastError();
+  }
   if (sizeof(T) == 4) {
     const int nbb = (N + kBB - 1) / kBB;
     const int npairs = nbb * (nbb + 1) / 2;
@@ -2295,38 +2286,20 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const d
 #undef POU_GBIG
     return hipGetLastError();
   }
-  const int nb = (N + kGB - 1) / kGB;
-  const int npairs = nb * (nb + 1) / 2;
-  kper = ((kper + kKC - 1) / kKC) * kKC;
-  if (bf16 && sizeof(T) == 4)
-    hipLaunchKernelGGL(k_gram_bf16, dim3(nsplit, npairs), dim3(kBlock), 0, s, (const float *)W, N,
-                       ng, kper, part);
-  else
-    hipLaunchKernelGGL(k_gram<T>, dim3(nsplit, npairs), dim3(kBlock), 0, s, W, N, ng, kper, part);
-  return hipGetLastError();
+return hipErrorInvalidValue;
 }
 
-hipError_t launch_gram_reduce(const double *part, int N, int nsplit, bool fp32, double dv,
-                              double *G, hipStream_t s) {
+hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
+                              hipStream_t s) {
   if (N <= 128) {
     hipLaunchKernelGGL(k_gram_reduce_small, dim3(128 * 128 / 64), dim3(kBlock), 0, s, part, N,
                        nsplit, dv, G);
     return hipGetLastError();
   }
-  if (fp32) {
-    const int nbb = (N + kBB - 1) / kBB;
-    const int npairs = nbb * (nbb + 1) / 2;
-    const int blocks = npairs * kBB * kBB / kBlock;
-    hipLaunchKernelGGL(k_gram_reduce_big, dim3(blocks), dim3(kBlock), 0, s, part, N, nsplit,
-                       npairs, dv, G);
-    return hipGetLastError();
-  }
-  const int nb = (N + kGB - 1) / kGB;
-  const int npairs = nb * (nb + 1) / 2;
-  const i64 total = (i64)N * N;
-  int blocks = (int)((total + kBlock - 1) / kBlock);
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(kBlock), 0, s, part, N, nsplit, npairs,
+  const int nbb = (N + kBB - 1) / kBB;
+  const int npairs = nbb * (nbb + 1) / 2;
+  const int blocks = npairs * kBB * kBB / kBlock;
+  hipLaunchKernelGGL(k_gram_reduce_big, dim3(blocks), dim3(kBlock), 0, s, part, N, nsplit, npairs,
                      dv, G);
   return hipGetLastError();
 }
@@ -2346,14 +2319,6 @@ hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *
   hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, G, Minv, N, info);
   int blocks = (int)std::min<i64>(1024, ((i64)N * N + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_minv_to_d, dim3(blocks), dim3(kBlock), 0, s, Minv, N, D64, D32);
-  return hipGetLastError();
-}
-
-hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int N,
-                               hipStream_t s) {
-  int blocks = (N * N + kBlock - 1) / kBlock;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_lower_matmul, dim3(blocks), dim3(kBlock), 0, s, A, B, C, N);
   return hipGetLastError();
 }
 
@@ -2422,11 +2387,15 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
                          (const float *)X, (float *)out, N, ng);
     return hipGetLastError();
   }
-  const int NT = (N + 15) / 16;
-  const int groups = (NT + 7) / 8;
-  dim3 grid((unsigned)((ng + 63) / 64), groups);
-  hipLaunchKernelGGL(k_apply_lower<T>, grid, dim3(kBlock), 0, s, M, X, out, N, ng, occ, rho);
-  return hipGetLastError();
+  {
+    const int nJ = (N + kBB - 1) / kBB;
+    const i64 npt = (ng + kBB - 1) / kBB;
+    const i64 grid = ((npt + 7) / 8) * 8 * nJ;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_apply_big64, dim3((unsigned)grid), dim3(kAB), 0, s, (const double *)D,
+                       (const double *)X, (double *)out, N, ng);
+    return hipGetLastError();
+  }
 }
 
 template hipError_t launch_trial_gram<double>(const double *, const double *, const double *,

@@ -68,7 +68,6 @@ struct pou_ctx {
   int nblk_field = 0;   // blocks of field reductions
   int nblk_orb = 0;     // blocks per orbital for block reductions
   int nsplit = 0;       // Gram K splits
-  int npairs = 0;
 
   // device buffers
   double *d_occ = nullptr, *d_atoms = nullptr;
@@ -447,8 +446,7 @@ pou_status gram(pou_ctx *c, const T *X, bool bf16) {
                                             c->d_gpart, s));
   else
     KL(POU_K_GRAM, pou::launch_gram_partial<T>(X, c->N, c->ng, c->nsplit, c->d_gpart, s));
-  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->es == 4, c->dv,
-                                                c->d_G, s));
+  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
   return POU_OK;
 }
 
@@ -491,8 +489,7 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
   KL(POU_K_TRIAL, pou::launch_trial_gram<T>(W, (const T *)c->d_HW, c->d_rep[0], c->d_scal, tscale,
                                            (T *)c->d_Wt, c->N, c->ng, c->nsplit,
                                            mixed && passes == 2, c->d_gpart, s));
-  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->es == 4, c->dv,
-                                                c->d_G, s));
+  KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
   KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
                                                   info, c->d_cholws, s));
   if (passes == 2) {
@@ -507,8 +504,7 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
                                                0.0, nullptr, c->N, c->ng, c->nsplit, false,
                                                c->d_gpart, s));
     }
-    KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->es == 4, c->dv,
-                                                c->d_G, s));
+    KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv2, c->d_D32, c->d_D64, c->N,
                                                     info + 2, c->d_cholws, s));
     KL(POU_K_CHOLESKY, pou::launch_combine_factors(c->d_Minv2, c->d_Minv, c->d_Mcomb, c->d_D64,
@@ -1164,8 +1160,6 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   c->st.nzc = (c->n + c->st.zlen - 1) / c->st.zlen;
   c->nblk_field = (int)std::min<i64>(1024, (ng + 255) / 256);
   c->nblk_orb = (int)std::max<i64>(1, std::min<i64>(64, ng / 16384));
-  const int nb64 = (norb + 63) / 64;
-  c->npairs = nb64 * (nb64 + 1) / 2;
   c->nsplit = (int)std::max<i64>(1, std::min<i64>(pou::gram_split(norb, c->es == 4), (ng + 31) / 32));
 
   const size_t fbytes = sizeof(double) * (size_t)ng;

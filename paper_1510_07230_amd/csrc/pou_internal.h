@@ -207,10 +207,9 @@ hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, in
 // fused mixed-precision apply uses it)
 hipError_t launch_combine_factors(const double *A, const double *B, double *M, double *D64,
                                   float *D32, int N, bool split_b, hipStream_t s);
-// G = dv * sum of partials (full symmetric N x N); fp32 selects the partial
-// layout of the FP32 kernels for N > 128 (128 x 128 blocks instead of 64 x 64)
-hipError_t launch_gram_reduce(const double *part, int N, int nsplit, bool fp32, double dv,
-                              double *G, hipStream_t s);
+// G = dv * sum of partials (full symmetric N x N)
+hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
+                              hipStream_t s);
 // Cholesky G = L L^T and Minv = L^-1 (lower), plus D = Minv - I in FP64 and
 // FP32 (written for N <= 128).  info[0] = 1.0 if G is not numerically SPD
 // else 0.0; info[1] = max |G - I|.  Single workgroup.
@@ -231,16 +230,13 @@ hipError_t launch_cross_gram(const T *A, const T *B, int N, i64 ng, double dv, d
 template <typename T>
 hipError_t launch_rotate(const double *P, const T *X, T *out, int N, i64 ng, hipStream_t s);
 // Number of K splits of the Gram kernels.  N <= 128: as many as are resident
-// on the device at once, clamped to [256, 1024].  N > 128: FP32 orbitals, a
-// multiple of 8 ranges sized to whole rounds of resident workgroups; FP64,
-// 1024 / (pairs of 64-row blocks).
+// on the device at once, clamped to [256, 1024].  N > 128: a multiple of 8
+// ranges sized to whole rounds of resident workgroups.
 int gram_split(int N, bool fp32);
-// C = A * B for lower-triangular N x N matrices (FP64)
-hipError_t launch_lower_matmul(const double *A, const double *B, double *C, int N,
-                               hipStream_t s);
-// out[j][g] = sum_i M[j][i] X[i][g], M lower triangular N x N FP64 (for
-// N <= 128, and for FP32 orbitals at any N, the kernel reads D = M - I in the
-// element type instead; FP32 with N > 128 multiplies on split-BF16 MFMA).
+// out[j][g] = sum_i M[j][i] X[i][g] for M lower triangular N x N, formed as
+// X + D X from D = M - I in the element type (FP32 with N > 128 multiplies on
+// split-BF16 MFMA, FP64 on FP64 MFMA); M itself is read only for the
+// split-BF16 kernel's far-from-identity form below.
 // When rho is non-null (N <= 128 only) also rho[g] = sum_j occ_j out[j][g]^2.
 // ginfo (device, nullable): the Cholesky report of the Gram M came from; the
 // split-BF16 kernel multiplies by M itself instead of adding D X to X when

@@ -270,3 +270,33 @@ def test_more_than_128_orbitals(prec):
             assert np.isfinite(info["E"])
         G = g.gram(U)
         assert np.max(np.abs(G - np.eye(cfg.norb))) < 1e-5
+
+
+@pytest.mark.parametrize("norb,n", [(144, 20), (200, 19), (257, 24)])
+def test_fp64_more_than_128_orbitals_follow_oracle(norb, n):
+    """N > 128 in FP64 (128 x 128 block Gram and triangular apply on FP64
+    MFMA): row blocks ending inside a 16-orbital chunk and an odd point count
+    (scalar Gram loads) included.  Gram, orthonormalisation and three steps
+    against the oracle at FP64 tolerances."""
+    cfg = synth.custom(f"fp64_big_N{norb}", n, 0.6 * n, max(1, norb // 2), 2.0, 0.5, norb,
+                       min_sep=0.5, seed_id=500 + norb)
+    print(f"[fp64 big] N={norb} n={n}", flush=True)
+    so = oracle_system(cfg)
+    X = synth.orbitals(cfg)
+    p = algm.Params()
+    p.tau_init = 1.0 / algm.lambda_max_kinetic(so.h)
+    g = gpu_system(cfg, "fp64", tau_init=p.tau_init)
+    U = g.new_block(X)
+    assert rel(g.gram(U), oorth.gram(X, so.h)) < 1e-13
+    err = g.orthonormalize_(U)
+    W_o, _ = oorth.orth(X, so.h)
+    assert err < 1e-12
+    assert rel(to_np(U), W_o) < 1e-9
+    A = algm.AlgorithmM(W_o, so, p, orthonormalize_start=False)
+    U = g.new_block(W_o)
+    for k in range(3):
+        r = A.step()
+        info = g.step_(U)
+        assert info["s"] == r.s, (k, info["s"], r.s)
+        assert abs(info["E"] - r.E) < 1e-9 * max(1, abs(r.E)), (k, info["E"], r.E)
+    assert rel(to_np(U), A.W) < 1e-8
