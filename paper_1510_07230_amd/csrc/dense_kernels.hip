@@ -305,9 +305,10 @@ __device__ inline int tri_slot(int i, int j) { return i * (i + 1) / 2 + j; }
 // D (+)= sign * X * Y^op for 16 x 16 FP64 tiles in LDS.  X is read as the
 // MFMA A operand (X[l%16][4s + q]); Y is read as Y[4s + q][l%16] (ytrans = 0)
 // or as Y^T, i.e. Y[l%16][4s + q] (ytrans = 1).  C is read from / written to
-// the accumulator layout (row q + 4r, column l%16) of dst; cin = 0 starts from 0.
+// the accumulator layout (row q + 4r, column l%16) of dst (and of dst2 when
+// given); cin = 0 starts from 0.
 __device__ inline void tile_mma(const double *X, const double *Y, int ytrans, double sign,
-                                const double *C, double *dst, int l) {
+                                const double *C, double *dst, int l, double *dst2 = nullptr) {
   const int r16 = l & 15, q = l >> 4;
   d4 acc = d4{0, 0, 0, 0};
   if (C) {
@@ -322,6 +323,10 @@ __device__ inline void tile_mma(const double *X, const double *Y, int ytrans, do
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) dst[(q + 4 * r) * kTP + r16] = acc[r];
+  if (dst2) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst2[(q + 4 * r) * kTP + r16] = acc[r];
+  }
 }
 
 // Value of a (wave-uniform) lane of v, as two scalar reads.
@@ -380,7 +385,9 @@ __device__ inline void chol_diag_block(const double *App, double *Li, const doub
 // afterwards.  Padding rows beyond N carry an identity diagonal.
 //
 // LDS_TILES: tiles live in LDS (N <= 128, ~105 KB); otherwise in the global
-// workspace ws (L2-resident; N <= 512: 528 tile slots plus 32 panel tiles).
+// workspace ws (L2-resident; N <= 512: 528 tile slots), with the panel and the
+// current block row of L^-1 in LDS (~148 KB) and the trailing tasks batched
+// four per wave so that their workspace loads overlap.
 template <bool LDS_TILES, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict__ G, int N,
                                                        double *__restrict__ Minv,
@@ -389,13 +396,17 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
                                                        double *__restrict__ info,
                                                        double *__restrict__ ws) {
   __shared__ double slot_s[LDS_TILES ? 36 * kTile : 1];
-  __shared__ double P_s[LDS_TILES ? 8 * kTile : 1];
+  // panel tiles L_ip in LDS (8 for N <= 128, 32 for the workspace variant),
+  // and for the workspace variant the current block row B_pj of L^-1 too:
+  // the trailing tasks then read only their own tile from the workspace
+  __shared__ double P_s[(LDS_TILES ? 8 : 32) * kTile];
+  __shared__ double Brow_s[LDS_TILES ? 1 : 32 * kTile];
   __shared__ double Li2[2][kTile];
   __shared__ double sdg[512];
   __shared__ double sred[NTHR / 64];
   __shared__ int sbad;
   double *slot = LDS_TILES ? slot_s : ws;
-  double *P = LDS_TILES ? P_s : ws + 528 * kTile;
+  double *P = P_s;
   constexpr int NW = NTHR / 64;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int NT = (N + 15) / 16;
@@ -460,11 +471,17 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
         } else if (task < nb + nd) {
           const int j = task - nb;
           double *Bpj = slot + tri_slot(p, j) * kTile;
-          // in place: the MFMA chain reads the whole tile before the write
-          tile_mma(Li, Bpj, 0, 1.0, nullptr, Bpj, l);
+          // in place: the MFMA chain reads the whole tile before the write; the
+          // workspace variant also keeps the result in LDS (from registers)
+          tile_mma(Li, Bpj, 0, 1.0, nullptr, Bpj, l,
+                   LDS_TILES ? nullptr : Brow_s + (LDS_TILES ? 0 : j * kTile));
         } else {
           double *Bpp = slot + tri_slot(p, p) * kTile;
           for (int e = l; e < 256; e += 64) Bpp[(e >> 4) * kTP + (e & 15)] = Li[(e >> 4) * kTP + (e & 15)];
+          if (!LDS_TILES) {
+            double *Bl = Brow_s + (LDS_TILES ? 0 : p * kTile);
+            for (int e = l; e < 256; e += 64) Bl[(e >> 4) * kTP + (e & 15)] = Li[(e >> 4) * kTP + (e & 15)];
+          }
         }
       }
     }
@@ -485,7 +502,69 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
       }
       const int first = look ? 1 : 0;                // task 0 is wave 0's when looking ahead
       const int ww = look ? w - 1 : w, nww = look ? NW - 1 : NW;
-      if (ww >= 0) {
+      if (!LDS_TILES && ww >= 0) {
+        // workspace variant: four tasks per wave per round, their workspace
+        // tiles loaded before any product (the operands come from LDS)
+        constexpr int TB = 4;
+        const int r16 = l & 15, q = l >> 4;
+        for (int t0 = first + ww; t0 < nc + ne; t0 += TB * nww) {
+          double *cp[TB];
+          const double *xp[TB], *yp[TB];
+          bool yt[TB], cin[TB], ok[TB];
+          d4 acc[TB];
+#pragma unroll
+          for (int u = 0; u < TB; ++u) {
+            const int task = t0 + u * nww;
+            ok[u] = task < nc + ne;
+            cp[u] = slot;
+            xp[u] = yp[u] = P;
+            yt[u] = true;
+            cin[u] = false;
+            if (!ok[u]) continue;
+            if (task < nc) {
+              int a = task, ii = 0;
+              while (a > ii) { a -= ii + 1; ++ii; }
+              const int i = p + 1 + ii, j = p + 1 + a;
+              cp[u] = slot + tri_slot(i, j) * kTile;
+              xp[u] = P + i * kTile;
+              yp[u] = P + j * kTile;
+              cin[u] = true;
+            } else {
+              const int a = task - nc;
+              const int i = p + 1 + a / (p + 1), j = a % (p + 1);
+              cp[u] = slot + tri_slot(i, j) * kTile;
+              xp[u] = P + i * kTile;
+              yp[u] = Brow_s + (LDS_TILES ? 0 : j * kTile);
+              yt[u] = false;
+              cin[u] = j < p;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < TB; ++u) {
+            acc[u] = d4{0, 0, 0, 0};
+            if (ok[u] && cin[u]) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[u][r] = cp[u][(q + 4 * r) * kTP + r16];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < TB; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const double a = -xp[u][r16 * kTP + 4 * s4 + q];
+              const double b = yt[u] ? yp[u][r16 * kTP + 4 * s4 + q] : yp[u][(4 * s4 + q) * kTP + r16];
+              acc[u] = mfma(a, b, acc[u]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < TB; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cp[u][(q + 4 * r) * kTP + r16] = acc[u][r];
+          }
+        }
+      } else if (ww >= 0) {
         for (int task = first + ww; task < nc + ne; task += nww) {
           if (task < nc) {
             // decode (i, j) with p < j <= i
@@ -2196,7 +2275,7 @@ size_t split_factor_elems(int N) {
   return (size_t)((N + kBB - 1) / kBB * kBB) * (size_t)((N + 31) / 32 * 32);
 }
 
-size_t chol_workspace_doubles(int N) { return N <= 128 ? 0 : (size_t)(528 + 32) * kTile; }
+size_t chol_workspace_doubles(int N) { return N <= 128 ? 0 : (size_t)528 * kTile; }
 
 size_t gram_partial_doubles(int N, int nsplit) {
   if (N <= 128) return (size_t)nsplit * 128 * 128;
