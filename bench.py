@@ -94,6 +94,19 @@ def mfma_floor(group, N, ng, es):
     return 0.0, 0.0
 
 
+def groups_roofline(prof, N, ng, es):
+    """Roofline record of every kernel group with algorithmic bytes, from the
+    breakdown pass (average launch time of the group)."""
+    out = {}
+    for g, (ms, n) in prof.items():
+        if n <= 0 or algorithmic_bytes(g, N, ng, es) is None:
+            continue
+        r = roofline_of(g, N, ng, es, ms / n * 1e-3)
+        out[g] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+        out[g]["avg_launch_ms"] = round(ms / n, 5)
+    return out
+
+
 def roofline_of(group, N, ng, es, avg_s):
     """Roofline record of one kernel group from its average launch time."""
     abytes = algorithmic_bytes(group, N, ng, es)
@@ -244,7 +257,10 @@ def run(args):
                 "fp64_groups_ms_per_step": {k: round(v[0] / args.steps, 4)
                                             for k, v in prof64.items()},
                 "fp64_dominant": {"kernel": dom64, "avg_launch_ms": round(pd64[0] / pd64[1], 5)},
-                "note": "groups_ms_per_step come from a separate pass with every group timed"})
+                "groups_roofline": groups_roofline(prof32, N, ng, 4),
+                "fp64_groups_roofline": groups_roofline(prof64, N, ng, 8),
+                "note": "groups_ms_per_step and groups_roofline come from a separate pass "
+                        "with every group timed"})
 
     out = {
         "metric": METRIC,
