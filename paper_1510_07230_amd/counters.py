@@ -92,7 +92,7 @@ def markdown(res, cmds):
     c = res["calibration"]
     out = ["# HBM traffic per launch from FETCH_SIZE / WRITE_SIZE (mixed96, mixed precision)", "",
            "Two counter runs, one counter each, then scaled by the counts of a plain copy "
-           "kernel of known size:", ""]
+           "kernel of known size ($REPO: the repository root, $OUT: an output directory):", ""]
     out += ["    " + x for x in cmds]
     out += ["", f"Copy calibration (k_convert<float,float>, {c['block_bytes']:,} bytes read and "
                 f"written): FETCH_SIZE {c['copy_fetch_kib']:.0f} KiB -> scale {c['scale_fetch']:.4f}; "
@@ -122,9 +122,9 @@ def main():
     a = ap.parse_args()
     res = summarise(a.fetch, a.write, a.block, a.norb, a.n)
     cmds = [
-        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/full/fetch -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
-        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/full/write -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
-        f"python -m paper_1510_07230_amd.counters fetch/run_counter_collection.csv write/run_counter_collection.csv {int(a.block)} --json profiles/traffic_mixed96.json --md profiles/traffic_mixed96.md",
+        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/fetch -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
+        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/write -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
+        f"python -m paper_1510_07230_amd.counters $OUT/fetch/run_counter_collection.csv $OUT/write/run_counter_collection.csv {int(a.block)} --json profiles/traffic_mixed96.json --md profiles/traffic_mixed96.md",
     ]
     if a.json:
         rec = {"_commands": cmds, "calibration": res["calibration"], "groups": res["groups"]}
