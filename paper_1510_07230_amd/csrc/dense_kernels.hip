@@ -56,84 +56,6 @@ __device__ inline void decode_pair(int pair, int nb, int &bi, int &bj) {
   bj = i + p;
 }
 
-// Cholesky G = L L^T (lower, in place in G) and Minv = L^-1.  One workgroup.
-// info[0] = 1 when a pivot is not finite or not above 1e-13 times its original
-// diagonal entry (G not numerically SPD);
-// info[1] = max |G - I| measured before factorising.
-__global__ __launch_bounds__(1024) void k_cholesky_inverse(double *__restrict__ G,
-                                                           double *__restrict__ Minv, int N,
-                                                           double *__restrict__ info) {
-  __shared__ double sred[16];
-  __shared__ double sdiag[512];
-  __shared__ double spiv;
-  __shared__ int sbad;
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int i = t; i < N; i += nt) sdiag[i] = G[(i64)i * N + i];
-  double m = 0.0;
-  for (int e = t; e < N * N; e += nt) {
-    const int i = e / N, j = e % N;
-    const double v = G[e] - (i == j ? 1.0 : 0.0);
-    m = fmax(m, fabs(v));
-    if (!isfinite(v)) m = INFINITY;
-  }
-  m = wave_max(m);
-  if ((t & 63) == 0) sred[t >> 6] = m;
-  if (t == 0) sbad = 0;
-  __syncthreads();
-  if (t == 0) {
-    double mm = 0.0;
-    for (int w = 0; w < (nt >> 6); ++w) mm = fmax(mm, sred[w]);
-    info[1] = mm;
-  }
-  for (int k = 0; k < N; ++k) {
-    if (t == 0) {
-      double d = G[(i64)k * N + k];
-      // a pivot at rounding level of the original diagonal means the
-      // columns are numerically dependent
-      if (!(d > 1e-13 * sdiag[k]) || !isfinite(d)) {
-        sbad = 1;
-        d = 1.0;
-      }
-      spiv = sqrt(d);
-      G[(i64)k * N + k] = spiv;
-    }
-    __syncthreads();
-    const double piv = spiv;
-    for (int i = k + 1 + t; i < N; i += nt) G[(i64)i * N + k] /= piv;
-    __syncthreads();
-    const int mm = N - k - 1;
-    for (int e = t; e < mm * mm; e += nt) {
-      const int i = k + 1 + e / mm, j = k + 1 + e % mm;
-      if (j <= i) G[(i64)i * N + j] -= G[(i64)i * N + k] * G[(i64)j * N + k];
-    }
-    __syncthreads();
-  }
-  // triangular inverse, one column per thread
-  for (int c = t; c < N; c += nt) {
-    for (int i = 0; i < c; ++i) Minv[(i64)i * N + c] = 0.0;
-    Minv[(i64)c * N + c] = 1.0 / G[(i64)c * N + c];
-    for (int i = c + 1; i < N; ++i) {
-      double s = 0.0;
-      for (int k = c; k < i; ++k) s += G[(i64)i * N + k] * Minv[(i64)k * N + c];
-      Minv[(i64)i * N + c] = -s / G[(i64)i * N + i];
-    }
-  }
-  __syncthreads();
-  if (t == 0) info[0] = sbad ? 1.0 : 0.0;
-}
-
-// D64 = Minv - I and D32 its FP32 copy (after the single-workgroup Cholesky).
-__global__ __launch_bounds__(kBlock) void k_minv_to_d(const double *__restrict__ Minv, int N,
-                                                      double *__restrict__ D64,
-                                                      float *__restrict__ D32) {
-  const i64 total = (i64)N * N;
-  for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < total; e += (i64)gridDim.x * kBlock) {
-    const double d = Minv[e] - ((e / N) == (e % N) ? 1.0 : 0.0);
-    D64[e] = d;
-    D32[e] = (float)d;
-  }
-}
-
 // M = A B for lower-triangular A, B (N x N, zeros above the diagonal), with
 // D64 = M - I and D32 its FP32 copy: the combined factor of two Cholesky-QR
 // passes.  With split_b, B is replaced by the value the fused first apply
@@ -2390,14 +2312,10 @@ hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *
                        D64, info, ws);
     return hipGetLastError();
   }
-  if (N <= 512 && ws != nullptr) {
-    hipLaunchKernelGGL((k_chol_blocked<false, 1024>), dim3(1), dim3(1024), 0, s, G, N, Minv, D32,
-                       D64, info, ws);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, s, G, Minv, N, info);
-  int blocks = (int)std::min<i64>(1024, ((i64)N * N + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_minv_to_d, dim3(blocks), dim3(kBlock), 0, s, Minv, N, D64, D32);
+  // above 128 orbitals: the workspace variant (the library admits at most 512)
+  if (N > 512 || ws == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_chol_blocked<false, 1024>), dim3(1), dim3(1024), 0, s, G, N, Minv, D32,
+                     D64, info, ws);
   return hipGetLastError();
 }
 

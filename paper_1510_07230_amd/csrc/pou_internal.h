@@ -211,8 +211,9 @@ hipError_t launch_combine_factors(const double *A, const double *B, double *M, d
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s);
 // Cholesky G = L L^T and Minv = L^-1 (lower), plus D = Minv - I in FP64 and
-// FP32 (written for N <= 128).  info[0] = 1.0 if G is not numerically SPD
-// else 0.0; info[1] = max |G - I|.  Single workgroup.
+// FP32.  info[0] = 1.0 if G is not numerically SPD else 0.0; info[1] =
+// max |G - I|.  Single workgroup; N <= 512, and above 128 the global
+// workspace ws of chol_workspace_doubles(N) doubles is required.
 hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
                                    double *info, double *ws, hipStream_t s);
 // doubles of global workspace the blocked Cholesky needs for N > 128
