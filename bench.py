@@ -86,6 +86,8 @@ def mfma_floor(group, N, ng, es):
     if group == "apply_gram":
         return 2 * tri, tri / PEAK_FLOPS["f32"] + 4 * tri / PEAK_FLOPS["bf16"]
     if group == "trial":
+        if N > 128:  # the trial point alone; its Gram is the "gram" group
+            return 0.0, 0.0
         return tri, tri / PEAK_FLOPS["bf16" if es == 4 else "f64"]
     if group == "gram":
         # above 128 FP32 orbitals the group alternates the BF16 first Gram and
