@@ -510,10 +510,17 @@ __host__ inline Radices factorize(int n) {
   return f;
 }
 
-// One Stockham stage over all lines: a -> b.
+// One Stockham stage over all lines: a -> b.  Twiddles come from the table
+// tw[m] = exp(-2 pi i m / n) of the workgroup (conjugated for sign > 0): the
+// stage's factor exp(sign 2 pi i k / (Ns R)) is tw[k n / (Ns R)].
 __device__ inline void fft_stage(const double2 *a, double2 *b, int n, int lb, int R, int Ns,
-                                 double sign) {
+                                 double sign, const double2 *tw) {
   const int nbf = n / R;  // butterflies per line
+  const int step = n / (Ns * R);
+  auto twid = [&](int idx) {
+    const double2 w = tw[idx];
+    return sign > 0.0 ? make_double2(w.x, -w.y) : w;
+  };
   for (int t = threadIdx.x; t < lb * nbf; t += blockDim.x) {
     const int line = t / nbf;
     const int j = t - line * nbf;
@@ -521,18 +528,13 @@ __device__ inline void fft_stage(const double2 *a, double2 *b, int n, int lb, in
     double2 *dst = b + line * n;
     const int k = j % Ns;
     const int base = (j / Ns) * Ns * R + k;
-    const double ang = sign * 2.0 * (double)k / (double)(Ns * R);  // in units of pi
+    const int m = k * step;  // < n / R
     if (R == 4) {
       double2 x0 = src[j], x1 = src[j + nbf], x2 = src[j + 2 * nbf], x3 = src[j + 3 * nbf];
       if (k) {
-        double sv, cv;
-        sincospi(ang, &sv, &cv);
-        const double2 w1 = make_double2(cv, sv);
-        const double2 w2 = cmul(w1, w1);
-        const double2 w3 = cmul(w2, w1);
-        x1 = cmul(x1, w1);
-        x2 = cmul(x2, w2);
-        x3 = cmul(x3, w3);
+        x1 = cmul(x1, twid(m));
+        x2 = cmul(x2, twid(2 * m));
+        x3 = cmul(x3, twid(3 * m));
       }
       const double2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
       const double2 s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3), sign);
@@ -542,40 +544,30 @@ __device__ inline void fft_stage(const double2 *a, double2 *b, int n, int lb, in
       dst[base + 3 * Ns] = csub(d02, d13);
     } else if (R == 2) {
       double2 x0 = src[j], x1 = src[j + nbf];
-      if (k) {
-        double sv, cv;
-        sincospi(ang, &sv, &cv);
-        x1 = cmul(x1, make_double2(cv, sv));
-      }
+      if (k) x1 = cmul(x1, twid(m));
       dst[base] = cadd(x0, x1);
       dst[base + Ns] = csub(x0, x1);
     } else if (R == 3) {
       double2 x0 = src[j], x1 = src[j + nbf], x2 = src[j + 2 * nbf];
       if (k) {
-        double sv, cv;
-        sincospi(ang, &sv, &cv);
-        const double2 w1 = make_double2(cv, sv);
-        x1 = cmul(x1, w1);
-        x2 = cmul(x2, cmul(w1, w1));
+        x1 = cmul(x1, twid(m));
+        x2 = cmul(x2, twid(2 * m));
       }
       const double2 t1 = cadd(x1, x2);
       const double2 t2 = cmuli(csub(x1, x2), sign * 0.86602540378443864676);
-      const double2 m = make_double2(x0.x - 0.5 * t1.x, x0.y - 0.5 * t1.y);
+      const double2 mm = make_double2(x0.x - 0.5 * t1.x, x0.y - 0.5 * t1.y);
       dst[base] = cadd(x0, t1);
-      dst[base + Ns] = cadd(m, t2);
-      dst[base + 2 * Ns] = csub(m, t2);
+      dst[base + Ns] = cadd(mm, t2);
+      dst[base + 2 * Ns] = csub(mm, t2);
     } else {
-      // generic radix: twiddle, then a direct DFT of length R
+      // generic radix: twiddle, then a direct DFT of length R; the total
+      // phase tt k / (Ns R) + (s tt mod R) / R turns is the table entry
+      // tt m + (s tt mod R) n / R (mod n)
       for (int s = 0; s < R; ++s) {
         double2 acc = make_double2(0.0, 0.0);
         for (int tt = 0; tt < R; ++tt) {
-          double2 x = src[j + tt * nbf];
-          // total phase: twiddle tt*k/(Ns R) plus DFT s*tt/R, both times 2 sign
-          const double ph = sign * 2.0 * ((double)tt * k / (double)(Ns * R) +
-                                          (double)((s * tt) % R) / (double)R);
-          double sv, cv;
-          sincospi(ph, &sv, &cv);
-          acc = cadd(acc, cmul(x, make_double2(cv, sv)));
+          const double2 x = src[j + tt * nbf];
+          acc = cadd(acc, cmul(x, twid((tt * m + ((s * tt) % R) * (n / R)) % n)));
         }
         dst[base + s * Ns] = acc;
       }
@@ -585,10 +577,10 @@ __device__ inline void fft_stage(const double2 *a, double2 *b, int n, int lb, in
 
 // Transform lb lines in LDS buffers a/b; returns the buffer holding the result.
 __device__ inline double2 *fft_lines(double2 *a, double2 *b, int n, int lb, Radices f,
-                                     double sign) {
+                                     double sign, const double2 *tw) {
   int Ns = 1;
   for (int st = 0; st < f.nr; ++st) {
-    fft_stage(a, b, n, lb, f.r[st], Ns, sign);
+    fft_stage(a, b, n, lb, f.r[st], Ns, sign, tw);
     __syncthreads();
     double2 *t = a;
     a = b;
@@ -609,6 +601,12 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
   extern __shared__ double2 lds[];
   double2 *a = lds;
   double2 *b = lds + lb * n;
+  double2 *tw = lds + 2 * lb * n;  // tw[m] = exp(-2 pi i m / n)
+  for (int m = threadIdx.x; m < n; m += blockDim.x) {
+    double sv, cv;
+    sincospi(-2.0 * (double)m / (double)n, &sv, &cv);
+    tw[m] = make_double2(cv, sv);
+  }
   const i64 n2 = (i64)n * n;
   // batch decoding: for x lines the batch is lb consecutive y rows of one z;
   // for y and z lines the batch is lb consecutive x of one (z) or (y).
@@ -645,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
     a[line * n + e] = v;
   }
   __syncthreads();
-  double2 *res = fft_lines(a, b, n, lb, f, sign);
+  double2 *res = fft_lines(a, b, n, lb, f, sign, tw);
   if (mode == 3) {
     // z lines: element e is kz; the line is (kx = first + line, ky = outer)
     for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
@@ -660,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
     }
     __syncthreads();
     double2 *other = (res == a) ? b : a;
-    res = fft_lines(res, other, n, lb, f, 1.0);
+    res = fft_lines(res, other, n, lb, f, 1.0, tw);
   }
   for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
     int line, e;
@@ -1059,10 +1057,10 @@ hipError_t launch_remove_mean(double *x, const double *dsum, i64 ng, hipStream_t
 hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, double2 *w1,
                                    const double *lam1, int n, double scale, hipStream_t s) {
   const Radices f = factorize(n);
-  int lb = 1024 / n;  // two LDS buffers of lb*n complex doubles: at most 32 KiB
+  int lb = 1024 / n;  // two LDS buffers of lb*n complex doubles (at most 32 KiB) + twiddles
   if (lb < 1) lb = 1;
   if (lb > 16) lb = 16;
-  const size_t lds = (size_t)2 * lb * n * sizeof(double2);
+  const size_t lds = (size_t)(2 * lb + 1) * n * sizeof(double2);  // two line buffers + twiddles
   const int groups = (n + lb - 1) / lb;
   const dim3 grid(groups * n), block(kBlock);
   const double invn3 = scale / ((double)n * n * n);
