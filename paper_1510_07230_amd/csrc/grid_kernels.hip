@@ -17,6 +17,12 @@ __host__ __device__ inline int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Periodic index for -n <= i < 2n (a stencil offset from a point of the grid):
+// one compare and add instead of an integer division.
+__host__ __device__ inline int wrap_near(int i, int n) {
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
 // ----------------------------------------------------------------- stencil
 
 // H u = -1/2 Lap_h u + V_eff u on the periodic grid (section 2.1 H(rho), with
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   T nhx[kPD], nhy[kPD], nq[kPD][kNB], nvf[kPD][kNB];
   auto issue = [&](int slot, int zz) {
     const T *pz = u + (i64)zz * nn;
-    const T *pq = u + (i64)wrap(zz + kRad, n) * nn;
+    const T *pq = u + (i64)wrap_near(zz + kRad, n) * nn;
     const T *pv = veff + (i64)zz * nn;
     const T hx = pz[off_hx];
     const T hy = pz[off_hy];
@@ -317,12 +323,17 @@ __global__ __launch_bounds__(kBlock) void k_segment_sum(const double *__restrict
 // -Lap p at point g = (z*n + y)*n + x of a periodic FP64 field; c0 = p[g].
 // Indices are 32-bit (n <= 1024 keeps n^3 below 2^31).
 __device__ inline double neg_lap_at(const double *__restrict__ p, unsigned g, int n,
-                                    double inv_h2, double &c0) {
+                                    double inv_n, double inv_h2, double &c0) {
   const unsigned un = (unsigned)n;
-  const unsigned yz = g / un;
-  const int x = (int)(g - yz * un);
-  const int z = (int)(yz / un);
-  const int y = (int)(yz - (unsigned)z * un);
+  // g = (z n + y) n + x by floating-point quotients (exact after the +-1
+  // correction for g < 2^31), not integer divisions
+  unsigned yz = (unsigned)((double)g * inv_n);
+  int x = (int)(g - yz * un);
+  if (x < 0) { --yz; x += n; } else if (x >= n) { ++yz; x -= n; }
+  unsigned zq = (unsigned)((double)yz * inv_n);
+  int y = (int)(yz - zq * un);
+  if (y < 0) { --zq; y += n; } else if (y >= n) { ++zq; y -= n; }
+  const int z = (int)zq;
   const unsigned row = g - (unsigned)x;            // (z*n + y)*n
   const unsigned plane = (unsigned)z * un * un;    // z*n*n
   const unsigned nn = un * un;
@@ -331,11 +342,11 @@ __device__ inline double neg_lap_at(const double *__restrict__ p, unsigned g, in
   double lap = 0.0;
 #pragma unroll
   for (int m = 1; m <= kRad; ++m) {
-    const double dx = (p[row + wrap(x + m, n)] - c0) + (p[row + wrap(x - m, n)] - c0);
-    const double dy = (p[plane + (unsigned)wrap(y + m, n) * un + x] - c0) +
-                      (p[plane + (unsigned)wrap(y - m, n) * un + x] - c0);
-    const double dz = (p[(unsigned)wrap(z + m, n) * nn + (g - plane)] - c0) +
-                      (p[(unsigned)wrap(z - m, n) * nn + (g - plane)] - c0);
+    const double dx = (p[row + wrap_near(x + m, n)] - c0) + (p[row + wrap_near(x - m, n)] - c0);
+    const double dy = (p[plane + (unsigned)wrap_near(y + m, n) * un + x] - c0) +
+                      (p[plane + (unsigned)wrap_near(y - m, n) * un + x] - c0);
+    const double dz = (p[(unsigned)wrap_near(z + m, n) * nn + (g - plane)] - c0) +
+                      (p[(unsigned)wrap_near(z - m, n) * nn + (g - plane)] - c0);
     lap += c[m] * ((dx + dy) + dz);
   }
   return -lap * inv_h2;
@@ -347,10 +358,11 @@ __global__ __launch_bounds__(kBlock) void k_neg_lap(const double *__restrict__ p
                                                     double inv_h2) {
   __shared__ double red[4];
   const unsigned ng = (unsigned)n * n * n;
+  const double inv_n = 1.0 / (double)n;
   double acc = 0.0;
   for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
     double c0;
-    const double v = neg_lap_at(p, g, n, inv_h2, c0);
+    const double v = neg_lap_at(p, g, n, inv_n, inv_h2, c0);
     q[g] = v;
     acc += c0 * v;
   }
@@ -370,13 +382,14 @@ __global__ __launch_bounds__(kBlock) void k_poisson_residual(const double *__res
                                                              double inv_h2) {
   __shared__ double red[4 * 2];
   const unsigned ng = (unsigned)n * n * n;
+  const double inv_n = 1.0 / (double)n;
   const double mean = dsum[0] / (double)ng;
   const double fourpi = 12.566370614359172954;
   double a0 = 0.0, a1 = 0.0;
   for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x) {
     double c0;
     const double b = fourpi * (rho[g] - mean);
-    const double rr = b - neg_lap_at(x, g, n, inv_h2, c0);
+    const double rr = b - neg_lap_at(x, g, n, inv_n, inv_h2, c0);
     a0 += rr * rr;
     a1 += b * b;
   }
