@@ -23,6 +23,34 @@ __host__ __device__ inline int wrap_near(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+// Plane access through a buffer descriptor: a uniform plane base in scalar
+// registers, a 32-bit unsigned byte offset per lane, and the plane size as
+// the record count (an access beyond the plane reads zero and writes nothing).
+typedef unsigned pou_v2u __attribute__((ext_vector_type(2)));
+
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+template <typename T>
+__device__ inline T plane_load(__amdgpu_buffer_rsrc_t r, unsigned boff);
+template <>
+__device__ inline float plane_load<float>(__amdgpu_buffer_rsrc_t r, unsigned boff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+}
+template <>
+__device__ inline double plane_load<double>(__amdgpu_buffer_rsrc_t r, unsigned boff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+
+__device__ inline void plane_store(__amdgpu_buffer_rsrc_t r, unsigned boff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, boff, 0, 0);
+}
+__device__ inline void plane_store(__amdgpu_buffer_rsrc_t r, unsigned boff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(pou_v2u, v), r, boff, 0, 0);
+}
+
 // ----------------------------------------------------------------- stencil
 
 // H u = -1/2 Lap_h u + V_eff u on the periodic grid (section 2.1 H(rho), with
@@ -67,103 +95,122 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   const int gx = x0 + tx;
   const bool vx = gx < n;
   const int gxw = wrap(gx, n);
-  // in-plane offsets (32-bit: n <= 1024) of this thread's rows and halo cells
+  // in-plane byte offsets (32-bit: n <= 1024) of this thread's rows and halo
+  // cells; every plane access is a buffer access at one of these offsets
   const int nn = n * n;
-  int offr[kNB];
-  bool valid[kNB];
+  const unsigned pbytes = (unsigned)(n * n) * (unsigned)sizeof(T);
+  unsigned offr[kNB], offw[kNB];
+  T vmask[kNB];
 #pragma unroll
   for (int r = 0; r < kNB; ++r) {
     const int gy = y0 + 4 * trow + r;
-    offr[r] = wrap(gy, n) * n + gxw;
-    valid[r] = vx && gy < n;
+    const bool valid = vx && gy < n;
+    offr[r] = (unsigned)(wrap(gy, n) * n + gxw) * (unsigned)sizeof(T);
+    offw[r] = valid ? offr[r] : 0x80000000u;  // beyond the plane: not written
+    vmask[r] = valid ? (T)1 : (T)0;
   }
   // halo assignments (independent of z)
   const int hx_row = threadIdx.x >> 3;  // 0..31
   const int hx_c = threadIdx.x & 7;     // 0..7
   const int hx_lc = hx_c < 4 ? hx_c - 4 : kTX + hx_c - 4;
-  const int off_hx = wrap(y0 + hx_row, n) * n + wrap(x0 + hx_lc, n);
+  const unsigned off_hx =
+      (unsigned)(wrap(y0 + hx_row, n) * n + wrap(x0 + hx_lc, n)) * (unsigned)sizeof(T);
   const int hy_col = threadIdx.x & 31;
   const int hy_r = threadIdx.x >> 5;  // 0..7
   const int hy_lr = hy_r < 4 ? hy_r - 4 : kTY + hy_r - 4;
-  const int off_hy = wrap(y0 + hy_lr, n) * n + wrap(x0 + hy_col, n);
+  const unsigned off_hy =
+      (unsigned)(wrap(y0 + hy_lr, n) * n + wrap(x0 + hy_col, n)) * (unsigned)sizeof(T);
+  auto at = [&](const T *base, unsigned boff) -> T {
+    return plane_load<T>(plane_rsrc(base, pbytes), boff);
+  };
 
   const int z0 = zc * a.zlen;
   const int z1 = min(n, z0 + a.zlen);
 
-  // z neighbours: a circular register queue, plane p in slot (p - z0) mod 9;
-  // the z loop is unrolled by 9 so every slot index is a compile-time constant
-  constexpr int kQ = 2 * kRad + 1;
+  // z neighbours: a circular register queue of kQ planes, plane p in slot
+  // (p - z0 + kRad) mod kQ.  The queue holds the nine planes of the stencil
+  // plus the kPD planes whose loads are in flight, so a load goes straight
+  // into the slot it is read from; the z loop is unrolled by kQ so every slot
+  // index is a compile-time constant.
+  constexpr int kPD = 3;
+  constexpr int kQ = 2 * kRad + 1 + kPD;
   T q[kNB][kQ];
 #pragma unroll
   for (int m = 0; m < 2 * kRad; ++m) {
     const T *pz = u + (i64)wrap(z0 - kRad + m, n) * nn;
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) q[r][(m - kRad + kQ) % kQ] = pz[offr[r]];
+    for (int r = 0; r < kNB; ++r) q[r][m] = at(pz, offr[r]);
   }
   const T c1 = (T)FD8::c1, c2 = (T)FD8::c2, c3 = (T)FD8::c3, c4 = (T)FD8::c4;
   const T cm[5] = {(T)0, c1, c2, c3, c4};
   const T mh = (T)(-0.5 * a.inv_h2);
   double acc_sig = 0.0, acc_kin = 0.0;
 
-  // Loads for plane zz are issued kPD planes ahead of their use into a ring
-  // of register sets (the halo of plane zz, the queue head zz + 4 and V_eff
-  // on plane zz), so kPD planes of loads are in flight per workgroup; kPD
-  // divides the unroll factor, so ring slots are compile-time constants too.
-  constexpr int kPD = 3;
-  static_assert(kQ % kPD == 0, "prefetch ring must divide the z unroll");
-  T nhx[kPD], nhy[kPD], nq[kPD][kNB], nvf[kPD][kNB];
-  auto issue = [&](int slot, int zz) {
+  // Loads for plane zz are issued kPD planes ahead of their use: the halo of
+  // plane zz and V_eff on plane zz into a ring of kR = kPD + 1 register sets
+  // (plane zz in set (zz - z0) mod kR, so a load never lands in the set being
+  // read), the queue head zz + kRad into its queue slot.
+  constexpr int kR = kPD + 1;
+  static_assert(kQ % kR == 0, "prefetch ring must divide the z unroll");
+  T nhx[kR], nhy[kR], nvf[kR][kNB];
+  auto issue = [&](int slot, int qs, int zz) {
     const T *pz = u + (i64)zz * nn;
     const T *pq = u + (i64)wrap_near(zz + kRad, n) * nn;
     const T *pv = veff + (i64)zz * nn;
-    const T hx = pz[off_hx];
-    const T hy = pz[off_hy];
+    const T hx = at(pz, off_hx);
+    const T hy = at(pz, off_hy);
     T qq[kNB], vv[kNB];
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) qq[r] = pq[offr[r]];
+    for (int r = 0; r < kNB; ++r) qq[r] = at(pq, offr[r]);
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) vv[r] = pv[offr[r]];
+    for (int r = 0; r < kNB; ++r) vv[r] = at(pv, offr[r]);
 #pragma unroll
-    for (int k = 0; k < kPD; ++k) {
+    for (int k = 0; k < kR; ++k) {
       if (k == slot) {
         nhx[k] = hx;
         nhy[k] = hy;
 #pragma unroll
-        for (int r = 0; r < kNB; ++r) {
-          nq[k][r] = qq[r];
-          nvf[k][r] = vv[r];
-        }
+        for (int r = 0; r < kNB; ++r) nvf[k][r] = vv[r];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+      if (k == qs) {
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) q[r][k] = qq[r];
       }
     }
   };
 #pragma unroll
   for (int k = 0; k < kPD; ++k)
-    if (z0 + k < z1) issue(k, z0 + k);
+    if (z0 + k < z1) issue(k, (k + 2 * kRad) % kQ, z0 + k);
 
   for (int zb = z0; zb < z1; zb += kQ) {
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
       const int z = zb + k;
       if (z < z1) {
-        T *hz = hu + (i64)z * nn;
-        const int ps = k % kPD;
-        T vf[kNB];
+        const __amdgpu_buffer_rsrc_t hz = plane_rsrc(hu + (i64)z * nn, pbytes);
+        const int ps = k % kR;
+        const int qc = (k + kRad) % kQ;  // slot of plane z
 #pragma unroll
-        for (int r = 0; r < kNB; ++r) {
-          q[r][(k + kRad) % kQ] = nq[ps][r];
-          vf[r] = nvf[ps][r];
-        }
-#pragma unroll
-        for (int r = 0; r < kNB; ++r) s[4 * trow + r + kRad][tx + kRad] = q[r][k % kQ];
+        for (int r = 0; r < kNB; ++r) s[4 * trow + r + kRad][tx + kRad] = q[r][qc];
         s[hx_row + kRad][hx_lc + kRad] = nhx[ps];
         s[hy_lr + kRad][hy_col + kRad] = nhy[ps];
-        if (z + kPD < z1) issue(ps, z + kPD);
+        const T *vf = nvf[ps];
+        // plane z + kPD: its queue head z + kPD + kRad goes to the slot of
+        // plane z - kRad - 1, which no later plane reads
+        if (z + kPD < z1) issue((k + kPD) % kR, (k + kRad + kPD + kRad) % kQ, z + kPD);
         __syncthreads();
         // y column of this thread: rows 4 trow - 4 .. 4 trow + 7 (local + kRad offset)
         T col[kNB + 2 * kRad];
 #pragma unroll
         for (int kk = 0; kk < kNB + 2 * kRad; ++kk) col[kk] = s[4 * trow + kk][tx + kRad];
-        // sigma and kinetic partials of this plane's four points in T, then FP64
+        // sigma and kinetic partials of this plane's four points in T, then
+        // FP64; every point is computed (its loads are in bounds by the
+        // periodic wrap) and a point outside the grid is stored at an offset
+        // beyond the plane, which the buffer range check drops, so no branch
+        // splits the work of the four points
         T psig = (T)0, pkin = (T)0;
 #pragma unroll
         for (int r = 0; r < kNB; ++r) {
@@ -175,16 +222,15 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
           for (int m = 1; m <= kRad; ++m) {
             const T dxm = (s[ly][lx + m] - c0) + (s[ly][lx - m] - c0);
             const T dym = (col[r + kRad + m] - c0) + (col[r + kRad - m] - c0);
-            const T dzm = (q[r][(k + m) % kQ] - c0) + (q[r][(k - m + kQ) % kQ] - c0);
+            const T dzm = (q[r][(qc + m) % kQ] - c0) + (q[r][(qc - m + kQ) % kQ] - c0);
             lap += cm[m] * ((dxm + dym) + dzm);
           }
           const T ku = mh * lap;
-          if (valid[r]) {
-            const T h = ku + vf[r] * c0;
-            hz[offr[r]] = h;
-            psig += c0 * h;
-            pkin += c0 * ku;
-          }
+          const T h = ku + vf[r] * c0;
+          plane_store(hz, offw[r], h);
+          const T cv = c0 * vmask[r];
+          psig += cv * h;
+          pkin += cv * ku;
         }
         acc_sig += (double)psig;
         acc_kin += (double)pkin;
