@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 namespace pou {
@@ -790,62 +791,46 @@ __device__ inline void apply_load_a(const T *__restrict__ D, int N, T (&a0)[4 * 
   }
 }
 
-template <typename T, int NT, int W, int GC, int PITCH, typename Acc>
-__device__ inline void apply_compute(const T (*xs)[PITCH], const T (&a0)[4 * NT],
-                                     const T (&a1)[4 * NT], Acc (&acc0)[GC / 16],
-                                     Acc (&acc1)[GC / 16], int r16, int q) {
+// out[j][g] = X[j][g] + sum_{i<=j} D[j][i] X[i][g] with D = L^-1 - I (lower
+// triangular, N <= 128).  Wave W owns the row tiles W and 7 - W; the whole
+// block loop is instantiated per wave so the wave keeps in registers only
+// the D fragments of its triangle (4(W+1) + 4(8-W) = 36 k-steps for NT = 8)
+// for the whole launch.  The workgroup walks over blocks of GC grid points,
+// staging each X block in LDS while the next one is loaded into registers.
+// Blocks with every row and point inside the problem take a path with no
+// per-element tests; the tail block tests each element.  Optional fused
+// density rho[g] = sum_j occ_j out[j][g]^2 (FP64 accumulation): each wave
+// leaves its partial of a block in LDS and the partials are summed after the
+// next block's first barrier, so the density adds no barrier of its own.
+template <typename T, int NT, int GC, int W>
+__device__ __attribute__((always_inline)) inline void apply_small_body(const T *__restrict__ D, const T *__restrict__ X,
+                                        T *__restrict__ out, int N, i64 ng,
+                                        const double *__restrict__ occ, double *__restrict__ rho,
+                                        T (*xs)[GC + 1], double (*srho)[4][GC]) {
+  constexpr int ROWS = 16 * NT;
+  constexpr int RSTEP = kBlock / GC;
+  constexpr int PER = ROWS / RSTEP;  // ROWS is a multiple of 16 and RSTEP divides 16
+  static_assert(PER * RSTEP == ROWS, "loader rows must tile the block");
+  constexpr int NC = GC / 16;
   constexpr int jt0 = W, jt1 = 7 - W;
   constexpr int ke0 = jt0 < NT ? 4 * (jt0 + 1) : 0;
   constexpr int ke1 = jt1 < NT ? 4 * (jt1 + 1) : 0;
   constexpr int ke = ke0 > ke1 ? ke0 : ke1;
-#pragma unroll
-  for (int ks = 0; ks < ke; ++ks) {
-    T b[GC / 16];
-#pragma unroll
-    for (int cc = 0; cc < GC / 16; ++cc) b[cc] = xs[4 * ks + q][16 * cc + r16];
-    if (ks < ke0) {
-#pragma unroll
-      for (int cc = 0; cc < GC / 16; ++cc) acc0[cc] = mfma(a0[ks], b[cc], acc0[cc]);
-    }
-    if (ks < ke1) {
-#pragma unroll
-      for (int cc = 0; cc < GC / 16; ++cc) acc1[cc] = mfma(a1[ks], b[cc], acc1[cc]);
-    }
-  }
-}
-
-// out[j][g] = X[j][g] + sum_{i<=j} D[j][i] X[i][g] with D = L^-1 - I (lower
-// triangular, N <= 128).  The D fragments of a wave's two row tiles stay in
-// registers for the whole launch; the workgroup walks over blocks of GC grid
-// points, staging each X block in LDS while the next one is loaded into
-// registers.  Optional fused density rho[g] = sum_j occ_j out[j][g]^2 (FP64
-// accumulation): each wave leaves its partial of a block in LDS and the
-// partials are summed after the next block's first barrier, so the density
-// adds no barrier of its own.
-template <typename T, int NT, int GC>
-__global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
-                                                        const T *__restrict__ X,
-                                                        T *__restrict__ out, int N, i64 ng,
-                                                        const double *__restrict__ occ,
-                                                        double *__restrict__ rho) {
-  constexpr int ROWS = 16 * NT;
-  constexpr int PITCH = GC + 1;
-  constexpr int RSTEP = kBlock / GC;
-  constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
-  constexpr int NC = GC / 16;
-  __shared__ T xs[ROWS][PITCH];
-  __shared__ double srho[2][4][GC];
   typedef typename AccOf<T>::type Acc;
   const int t = threadIdx.x;
-  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
-  T a0[4 * NT], a1[4 * NT];
-  switch (w) {
-    case 0: apply_load_a<T, NT, 0>(D, N, a0, a1, r16, q); break;
-    case 1: apply_load_a<T, NT, 1>(D, N, a0, a1, r16, q); break;
-    case 2: apply_load_a<T, NT, 2>(D, N, a0, a1, r16, q); break;
-    default: apply_load_a<T, NT, 3>(D, N, a0, a1, r16, q); break;
+  const int l = t & 63, r16 = l & 15, q = l >> 4;
+  // D fragments: a0[ks] = D[16 jt0 + r16][4 ks + q], only k-steps of the triangle
+  T a0[ke0 > 0 ? ke0 : 1], a1[ke1 > 0 ? ke1 : 1];
+#pragma unroll
+  for (int ks = 0; ks < ke0; ++ks) {
+    const int i = 4 * ks + q, j = 16 * jt0 + r16;
+    a0[ks] = (j < N && i < N) ? D[(i64)j * N + i] : (T)0;
   }
-  const int jt0 = w, jt1 = 7 - w;
+#pragma unroll
+  for (int ks = 0; ks < ke1; ++ks) {
+    const int i = 4 * ks + q, j = 16 * jt1 + r16;
+    a1[ks] = (j < N && i < N) ? D[(i64)j * N + i] : (T)0;
+  }
   // occupations of the rows this lane writes
   double occv[2][4];
 #pragma unroll
@@ -857,19 +842,25 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
       occv[u][r] = (rho != nullptr && jt < NT && j < N) ? occ[j] : 0.0;
     }
   }
+  const bool all_rows = N == ROWS;
   const i64 nblk = (ng + GC - 1) / GC;
   const int col = t % GC, row0 = t / GC;
   T nxt[PER];
-  auto load = [&](i64 blk) {
+  auto load = [&](i64 blk) __attribute__((always_inline)) {
     const i64 g = blk * GC + col;
+    if (all_rows && blk * GC + GC <= ng) {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int row = row0 + RSTEP * e;
-      nxt[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : (T)0;
+      for (int e = 0; e < PER; ++e) nxt[e] = X[(i64)(row0 + RSTEP * e) * ng + g];
+    } else {
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int row = row0 + RSTEP * e;
+        nxt[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : (T)0;
+      }
     }
   };
   // density of the previous block still to be summed from srho[buf ^ 1]
-  auto flush_rho = [&](i64 pblk, int pbuf) {
+  auto flush_rho = [&](i64 pblk, int pbuf) __attribute__((always_inline)) {
     if (t < GC) {
       const i64 g = pblk * GC + t;
       if (g < ng)
@@ -884,10 +875,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
     __syncthreads();
     if (rho != nullptr && pending >= 0) flush_rho(pending, buf ^ 1);
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int row = row0 + RSTEP * e;
-      if (row < ROWS) xs[row][col] = nxt[e];
-    }
+    for (int e = 0; e < PER; ++e) xs[row0 + RSTEP * e][col] = nxt[e];
     __syncthreads();
     if (blk + gridDim.x < nblk) load(blk + gridDim.x);
     Acc acc0[NC], acc1[NC];
@@ -896,41 +884,55 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
       acc0[cc] = Acc{0, 0, 0, 0};
       acc1[cc] = Acc{0, 0, 0, 0};
     }
-    switch (w) {
-      case 0: apply_compute<T, NT, 0, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      case 1: apply_compute<T, NT, 1, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      case 2: apply_compute<T, NT, 2, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
-      default: apply_compute<T, NT, 3, GC, PITCH>(xs, a0, a1, acc0, acc1, r16, q); break;
+#pragma unroll
+    for (int ks = 0; ks < ke; ++ks) {
+      T b[NC];
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) b[cc] = xs[4 * ks + q][16 * cc + r16];
+      if (ks < ke0) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) acc0[cc] = mfma(a0[ks], b[cc], acc0[cc]);
+      }
+      if (ks < ke1) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) acc1[cc] = mfma(a1[ks], b[cc], acc1[cc]);
+      }
     }
     const i64 g0 = blk * GC;
     double rp[NC];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) rp[cc] = 0.0;
+    auto epilogue = [&](auto tested) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int jt = u == 0 ? jt0 : jt1;
-      if (jt >= NT) continue;
+      for (int u = 0; u < 2; ++u) {
+        const int jt = u == 0 ? jt0 : jt1;
+        if (jt >= NT) continue;
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const i64 g = g0 + 16 * cc + r16;
+        for (int cc = 0; cc < NC; ++cc) {
+          const i64 g = g0 + 16 * cc + r16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int j = 16 * jt + out_row<T>(q, r);
-          if (j < N && g < ng) {
+          for (int r = 0; r < 4; ++r) {
+            const int j = 16 * jt + out_row<T>(q, r);
             const T v = xs[j][16 * cc + r16] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
-            out[(i64)j * ng + g] = v;
-            rp[cc] += occv[u][r] * ((double)v * (double)v);
+            if (!decltype(tested)::value || (j < N && g < ng)) {
+              out[(i64)j * ng + g] = v;
+              rp[cc] += occv[u][r] * ((double)v * (double)v);
+            }
           }
         }
       }
-    }
+    };
+    if (all_rows && g0 + GC <= ng)
+      epilogue(std::false_type());
+    else
+      epilogue(std::true_type());
     if (rho != nullptr) {
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         double v = rp[cc];
         v += __shfl_xor(v, 16, 64);
         v += __shfl_xor(v, 32, 64);
-        if (q == 0) srho[buf][w][16 * cc + r16] = v;
+        if (q == 0) srho[buf][W][16 * cc + r16] = v;
       }
       pending = blk;
       buf ^= 1;
@@ -939,6 +941,23 @@ __global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
   if (rho != nullptr && pending >= 0) {
     __syncthreads();
     flush_rho(pending, buf ^ 1);
+  }
+}
+
+template <typename T, int NT, int GC>
+__global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
+                                                        const T *__restrict__ X,
+                                                        T *__restrict__ out, int N, i64 ng,
+                                                        const double *__restrict__ occ,
+                                                        double *__restrict__ rho) {
+  __shared__ T xs[16 * NT][GC + 1];
+  __shared__ double srho[2][4][GC];
+  // every wave runs the same block loop with the same barriers
+  switch (threadIdx.x >> 6) {
+    case 0: apply_small_body<T, NT, GC, 0>(D, X, out, N, ng, occ, rho, xs, srho); break;
+    case 1: apply_small_body<T, NT, GC, 1>(D, X, out, N, ng, occ, rho, xs, srho); break;
+    case 2: apply_small_body<T, NT, GC, 2>(D, X, out, N, ng, occ, rho, xs, srho); break;
+    default: apply_small_body<T, NT, GC, 3>(D, X, out, N, ng, occ, rho, xs, srho); break;
   }
 }
 
@@ -1183,12 +1202,21 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   const bool loader = 8 * rg < ROWS;
   const i64 G = gridDim.x;
   float na[8], nb[8];
-  auto load = [&](float (&dst)[8], i64 blk) {
+  // blocks with every row and point inside the problem load with no
+  // per-element tests (the tests would put each load in a branch of its own)
+  const bool all_rows = N == ROWS;
+  auto load = [&](float (&dst)[8], i64 blk) __attribute__((always_inline)) {
     const i64 g = blk * GC + col;
+    if (!loader) return;  // rows 8 rg .. 8 rg + 7 lie beyond the problem
+    if (all_rows && blk * GC + GC <= ng) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int row = 8 * rg + e;
-      dst[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : 0.0f;
+      for (int e = 0; e < 8; ++e) dst[e] = X[(i64)(8 * rg + e) * ng + g];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int row = 8 * rg + e;
+        dst[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : 0.0f;
+      }
     }
   };
   i64 blk = blockIdx.x;
