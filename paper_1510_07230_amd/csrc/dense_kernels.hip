@@ -548,19 +548,16 @@ __device__ inline void gram_chunk(const T (*s)[PITCH], Acc (&acc)[9], int r16, i
   }
 }
 
-template <int NT, int W, int KC, int PITCH>
-__device__ inline void gram_chunk_bf16(const float (*s)[PITCH], double (&accd)[9][4], int r16,
+template <int NT, int W, int KC, int PB>
+__device__ inline void gram_chunk_bf16(const __bf16 (*s)[PB], double (&accd)[9][4], int r16,
                                        int q) {
 #pragma unroll
   for (int kk = 0; kk < KC / 32; ++kk) {
     bf8 f[8];
 #pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        f[ct][e] = (ct < NT && ct >= W) ? (__bf16)s[16 * ct + r16][32 * kk + 8 * q + e]
-                                        : (__bf16)0.0f;
-    }
+    for (int ct = 0; ct < 8; ++ct)
+      f[ct] = (ct < NT && ct >= W) ? *(const bf8 *)&s[16 * ct + r16][32 * kk + 8 * q]
+                                   : bf8{0, 0, 0, 0, 0, 0, 0, 0};
 #define POU_GTB(U)                                                                        \
   if (GramTile<W, U>::rt < NT && GramTile<W, U>::ct < NT) {                               \
     f4 c = f4{0, 0, 0, 0};                                                                \
@@ -703,11 +700,11 @@ __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restr
                                                                double tscale,
                                                                float *__restrict__ Wt) {
   constexpr int ROWS = 16 * NT;
-  constexpr int PITCH = KC + 4;
+  constexpr int PB = KC + 8;  // BF16 rows of 16-byte multiples: fragments are single reads
   constexpr int TPR = KC;
   constexpr int RSTEP = kBlock / TPR;
   constexpr int PER = (ROWS + RSTEP - 1) / RSTEP;
-  __shared__ float s[ROWS][PITCH];
+  __shared__ __attribute__((aligned(16))) __bf16 s[ROWS][PB];
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
   const i64 k_beg = (i64)blockIdx.x * kper;
@@ -729,37 +726,72 @@ __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restr
       ca[e] = (row < N) ? (float)(1.0 + tau * sig[row]) : 0.0f;
     }
   }
-  auto load = [&](i64 k0) {
+  // chunks with every row and point inside the range load and store with no
+  // per-element tests (the tests would put each access in a branch of its own)
+  const bool all_rows = N == ROWS;
+  // Whole chunks address row row0 + RSTEP e as a per-lane pointer plus a
+  // uniform row step.  The lane offset passes through an empty asm each
+  // time, so the compiler cannot hoist one 64-bit pointer per row out of the
+  // chunk loop (which would hold 2 PER registers per array for the launch).
+  const i64 lane_off = (i64)row0 * ng + col;
+  const i64 rstep = (i64)RSTEP * ng;
+  auto lane_base = [&](i64 k0) __attribute__((always_inline)) -> i64 {
+    i64 o = lane_off;
+    asm volatile("" : "+v"(o));
+    return o + k0;
+  };
+  auto load = [&](i64 k0) __attribute__((always_inline)) {
+    const i64 g = k0 + col;
+    if (all_rows && k0 + KC <= k_end) {
+      const i64 o = lane_base(k0);
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int row = row0 + RSTEP * e;
-      const i64 g = k0 + col;
-      const bool ok = row < N && g < k_end;
-      nxt[e] = ok ? A[(i64)row * ng + g] : 0.0f;
-      if (TRIAL) nxh[e] = ok ? HW[(i64)row * ng + g] : 0.0f;
+      for (int e = 0; e < PER; ++e) {
+        nxt[e] = A[o + e * rstep];
+        if (TRIAL) nxh[e] = HW[o + e * rstep];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int row = row0 + RSTEP * e;
+        const bool ok = row < N && g < k_end;
+        nxt[e] = ok ? A[(i64)row * ng + g] : 0.0f;
+        if (TRIAL) nxh[e] = ok ? HW[(i64)row * ng + g] : 0.0f;
+      }
     }
   };
   if (k_beg < k_end) load(k_beg);
   const float tt = (float)tau;
   for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
+    const bool full = all_rows && k0 + KC <= k_end;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
       float v = nxt[e];
-      if (TRIAL) {
-        v = ca[e] * v - tt * nxh[e];
-        const i64 g = k0 + col;
-        if (row < N && g < k_end) Wt[(i64)row * ng + g] = v;
+      if (TRIAL) v = ca[e] * v - tt * nxh[e];
+      if (row < ROWS) s[row][col] = (__bf16)v;
+      nxt[e] = v;
+    }
+    if (TRIAL) {
+      const i64 g = k0 + col;
+      if (full) {
+        const i64 o = lane_base(k0);
+#pragma unroll
+        for (int e = 0; e < PER; ++e) Wt[o + e * rstep] = nxt[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int row = row0 + RSTEP * e;
+          if (row < N && g < k_end) Wt[(i64)row * ng + g] = nxt[e];
+        }
       }
-      if (row < ROWS) s[row][col] = v;
     }
     __syncthreads();
     if (k0 + KC < k_end) load(k0 + KC);
     switch (w) {
-      case 0: gram_chunk_bf16<NT, 0, KC, PITCH>(s, accd, r16, q); break;
-      case 1: gram_chunk_bf16<NT, 1, KC, PITCH>(s, accd, r16, q); break;
-      case 2: gram_chunk_bf16<NT, 2, KC, PITCH>(s, accd, r16, q); break;
-      default: gram_chunk_bf16<NT, 3, KC, PITCH>(s, accd, r16, q); break;
+      case 0: gram_chunk_bf16<NT, 0, KC, PB>(s, accd, r16, q); break;
+      case 1: gram_chunk_bf16<NT, 1, KC, PB>(s, accd, r16, q); break;
+      case 2: gram_chunk_bf16<NT, 2, KC, PB>(s, accd, r16, q); break;
+      default: gram_chunk_bf16<NT, 3, KC, PB>(s, accd, r16, q); break;
     }
     __syncthreads();
   }
