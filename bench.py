@@ -74,17 +74,17 @@ def mfma_floor(group, N, ng, es):
 
     A triangular apply L^-1 X and a symmetric Gram X X^T each take N(N+1)
     flops per grid point.  The mixed first Gram runs on BF16 MFMA; the fused
-    apply + second Gram does the apply in FP32 and the Gram as four BF16
-    products (hi/lo split), so its floor is the sum of the two parts.  Above
-    128 FP32 orbitals the apply and the second Gram are four split-BF16
-    products each."""
+    apply + second Gram does both contractions as four BF16 products each
+    (hi/lo split), so its floor is eight BF16 products.  Above 128 FP32
+    orbitals the apply and the second Gram are four split-BF16 products
+    each."""
     tri = float(N * (N + 1) * ng)
     wide = "f64" if es == 8 else "f32"
     big = es == 4 and N > 128  # FP32 orbitals above 128: split-BF16 kernels
     if group == "apply":
         return tri, (4 * tri / PEAK_FLOPS["bf16"]) if big else tri / PEAK_FLOPS[wide]
     if group == "apply_gram":
-        return 2 * tri, tri / PEAK_FLOPS["f32"] + 4 * tri / PEAK_FLOPS["bf16"]
+        return 2 * tri, 8 * tri / PEAK_FLOPS["bf16"]
     if group == "trial":
         if N > 128:  # the trial point alone; its Gram is the "gram" group
             return 0.0, 0.0
