@@ -108,116 +108,6 @@ __global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict
   }
 }
 
-// ---------------------------------------------------------------- N <= 128
-
-// One elimination step k = K of the augmented sweep below (all indices into
-// the register array are compile-time).
-template <int K>
-__device__ __forceinline__ void chol_step(double (&a)[32], int c, int r0, int N, int ncol,
-                                          double *rowk, double *colk, const double *sdg,
-                                          int *sbad) {
-  if (K >= N) return;  // uniform over the workgroup
-  constexpr int MM = K >> 2, R0K = K & 3;
-  if (r0 == R0K && c < ncol) rowk[c] = a[MM];
-  if (c == K) {
-#pragma unroll
-    for (int mm = 0; mm < 32; ++mm) {
-      const int r = r0 + 4 * mm;
-      if (r < N) colk[r] = a[mm];
-    }
-  }
-  __syncthreads();
-  double p = rowk[K];
-  // a pivot at rounding level of the original diagonal means the columns
-  // are numerically dependent
-  if (!((p > 1e-13 * sdg[K]) && isfinite(p))) {
-    if (threadIdx.x == 0) *sbad = 1;
-    p = 1.0;
-  }
-  const double ip = 1.0 / p;
-  const double rc = (c < ncol) ? rowk[c] : 0.0;
-  const double rcp = rc * ip;
-  if (r0 == R0K) a[MM] = rc / sqrt(p);
-  else if (r0 > R0K && r0 + 4 * MM < N) a[MM] -= colk[r0 + 4 * MM] * rcp;
-#pragma unroll
-  for (int mm = MM + 1; mm < 32; ++mm) {
-    const int r = r0 + 4 * mm;
-    if (r < N) a[mm] -= colk[r] * rcp;
-  }
-  __syncthreads();
-}
-
-template <int... Ks>
-__device__ __forceinline__ void chol_sweep(std::integer_sequence<int, Ks...>, double (&a)[32],
-                                           int c, int r0, int N, int ncol, double *rowk,
-                                           double *colk, const double *sdg, int *sbad) {
-  (chol_step<Ks>(a, c, r0, N, ncol, rowk, colk, sdg, sbad), ...);
-}
-
-// Cholesky factor and inverse in one sweep: Gaussian elimination without
-// pivoting on the augmented matrix [G | I].  Step k divides row k by the square
-// root of its pivot and removes column k from the rows below; at the end the
-// left half holds L^T and the right half L^-1 (the row operations are L^-1
-// itself).  1024 threads: column c = t % 256 of [G | I], rows (t / 256) + 4m
-// held in registers.
-__global__ __launch_bounds__(1024) void k_chol_inv_small(const double *__restrict__ G,
-                                                         double *__restrict__ Minv,
-                                                         float *__restrict__ D32,
-                                                         double *__restrict__ D64, int N,
-                                                         double *__restrict__ info) {
-  __shared__ double rowk[256];
-  __shared__ double colk[128];
-  __shared__ double sdg[128];
-  __shared__ double sred[16];
-  __shared__ int sbad;
-  const int t = threadIdx.x;
-  const int c = t & 255, r0 = t >> 8;
-  const int ncol = 2 * N;
-  if (t < N) sdg[t] = G[(i64)t * N + t];
-  double a[32];
-  double m = 0.0;
-#pragma unroll
-  for (int mm = 0; mm < 32; ++mm) {
-    const int r = r0 + 4 * mm;
-    double v = 0.0;
-    if (r < N && c < ncol) {
-      if (c < N) {
-        v = G[(i64)r * N + c];
-        const double d = v - (r == c ? 1.0 : 0.0);
-        m = isfinite(d) ? fmax(m, fabs(d)) : INFINITY;
-      } else {
-        v = (c - N == r) ? 1.0 : 0.0;
-      }
-    }
-    a[mm] = v;
-  }
-  m = wave_max(m);
-  if ((t & 63) == 0) sred[t >> 6] = m;
-  if (t == 0) sbad = 0;
-  __syncthreads();
-  if (t == 0) {
-    double mx = 0.0;
-    for (int w = 0; w < 16; ++w) mx = fmax(mx, sred[w]);
-    info[1] = mx;
-  }
-  chol_sweep(std::make_integer_sequence<int, 128>{}, a, c, r0, N, ncol, rowk, colk, sdg, &sbad);
-  if (c >= N && c < ncol) {
-    const int j = c - N;
-#pragma unroll
-    for (int mm = 0; mm < 32; ++mm) {
-      const int r = r0 + 4 * mm;
-      if (r < N) {
-        const double v = a[mm];
-        Minv[(i64)r * N + j] = v;
-        const double d = v - (r == j ? 1.0 : 0.0);
-        D64[(i64)r * N + j] = d;
-        D32[(i64)r * N + j] = (float)d;
-      }
-    }
-  }
-  if (t == 0) info[0] = sbad ? 1.0 : 0.0;
-}
-
 // ---------------------------------------------------------------- blocked Cholesky
 
 constexpr int kTP = 17;                 // padded pitch of a 16 x 16 FP64 tile in LDS
@@ -260,6 +150,19 @@ __device__ inline double readlane_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton steps y <- y (3 - x y^2) / 2 (each roughly doubles the correct bits;
+// the result is within a few units in the last place).  It replaces an
+// IEEE square root and division on the serial chain of pivots, where their
+// long expansions dominated the diagonal-block factorisation.
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 // One wave: [A_pp | I] -> [L_pp^T | L_pp^-1] for a 16 x 16 diagonal block
 // (Gaussian elimination without pivoting).  Lane c < 32 holds column c of the
 // 16 x 32 augmented block in registers (all 16 rows), so row k of step k is
@@ -284,7 +187,7 @@ __device__ inline void chol_diag_block(const double *App, double *Li, const doub
       if (l == 0) *sbad = 1;
       piv = 1.0;
     }
-    const double isp = 1.0 / sqrt(piv);
+    const double isp = rsqrt_nr(piv);
     const double rk = v[k];
     const double rki = rk * (isp * isp);
     v[k] = rk * isp;
@@ -338,7 +241,7 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
   // the lower triangle of G into the tile slots: wave w takes rows w, w + NW,
   // ..., lanes take columns, ROWB rows per batch of independent loads
   constexpr int CPR = LDS_TILES ? 2 : 8;       // 64-column chunks per row (NP <= 64 CPR)
-  constexpr int ROWB = LDS_TILES ? 8 : 2;
+  constexpr int ROWB = LDS_TILES ? 16 : 2;      // N <= 128: all of a wave's rows in one batch
   for (int r0 = w; r0 < NP; r0 += NW * ROWB) {
     double v[ROWB][CPR];
 #pragma unroll
