@@ -1358,16 +1358,23 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
   const int e = blockIdx.x * 64 + lane;  // element of the 128 x 128 partial
   // the partials hold the upper triangle only: skip ranges entirely below it
   if (((blockIdx.x * 64) & 127) + 63 < (int)((blockIdx.x * 64) >> 7)) return;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  // 16 independent loads in flight per lane (the sum is latency-bound: few
+  // workgroups, each reading one 64-element column of every partial)
+  constexpr int U = 16;
+  double acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[u] = 0.0;
   int sp = w;
-  for (; sp + 12 < nsplit; sp += 16) {
-    acc0 += part[(i64)sp * 128 * 128 + e];
-    acc1 += part[(i64)(sp + 4) * 128 * 128 + e];
-    acc2 += part[(i64)(sp + 8) * 128 * 128 + e];
-    acc3 += part[(i64)(sp + 12) * 128 * 128 + e];
+  for (; sp + 4 * (U - 1) < nsplit; sp += 4 * U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] += part[(i64)(sp + 4 * u) * 128 * 128 + e];
   }
-  for (; sp < nsplit; sp += 4) acc0 += part[(i64)sp * 128 * 128 + e];
-  sacc[w][lane] = (acc0 + acc1) + (acc2 + acc3);
+  for (; sp < nsplit; sp += 4) acc[0] += part[(i64)sp * 128 * 128 + e];
+#pragma unroll
+  for (int h = U / 2; h >= 1; h /= 2)
+#pragma unroll
+    for (int u = 0; u < h; ++u) acc[u] += acc[u + h];
+  sacc[w][lane] = acc[0];
   __syncthreads();
   if (w == 0) {
     const double v = (sacc[0][lane] + sacc[1][lane] + sacc[2][lane] + sacc[3][lane]) * dv;

@@ -72,7 +72,9 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
                                                         T *__restrict__ HU,
                                                         double *__restrict__ part,
                                                         StencilArgs a, int N) {
-  __shared__ T s[kTY + 2 * kRad][kTX + 2 * kRad + 1];
+  // the plane with its halo, double-buffered: plane z uses buffer z mod 2, so
+  // one barrier per plane separates the stores from the reads
+  __shared__ T s2[2][kTY + 2 * kRad][kTX + 2 * kRad + 1];
   __shared__ double red[4 * 2];
   const int n = a.n;
   const i64 ng = (i64)n * n * n;
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
   // read), the queue head zz + kRad into its queue slot.
   constexpr int kR = kPD + 1;
   static_assert(kQ % kR == 0, "prefetch ring must divide the z unroll");
+  static_assert(kQ % 2 == 0, "the plane buffers alternate within the z unroll");
   T nhx[kR], nhy[kR], nvf[kR][kNB];
   auto issue = [&](int slot, int qs, int zz) {
     const T *pz = u + (i64)zz * nn;
@@ -193,6 +196,9 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
         const __amdgpu_buffer_rsrc_t hz = plane_rsrc(hu + (i64)z * nn, pbytes);
         const int ps = k % kR;
         const int qc = (k + kRad) % kQ;  // slot of plane z
+        // buffer k mod 2 was last read for plane z - 2, and every wave passed
+        // plane z - 1's barrier after those reads
+        T(*s)[kTX + 2 * kRad + 1] = s2[k & 1];
 #pragma unroll
         for (int r = 0; r < kNB; ++r) s[4 * trow + r + kRad][tx + kRad] = q[r][qc];
         s[hx_row + kRad][hx_lc + kRad] = nhx[ps];
@@ -234,7 +240,6 @@ __global__ __launch_bounds__(kBlock) void k_hamiltonian(const T *__restrict__ U,
         }
         acc_sig += (double)psig;
         acc_kin += (double)pkin;
-        __syncthreads();
       }
     }
   }
