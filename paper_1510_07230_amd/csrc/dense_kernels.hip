@@ -1040,46 +1040,48 @@ __global__ __launch_bounds__(kAB) void k_apply8(const T *__restrict__ D, const T
 // lo = bf16(W1 - hi)).  Each tile sums the four products lo lo^T, hi lo^T,
 // lo hi^T, hi hi^T in FP32 on BF16 MFMA (exact products, FP32 accumulation),
 // which leaves only the rounding of lo (2^-18 relative) and the FP32 sums; it
-// is flushed into FP64 per chunk.
+// is flushed into FP64 per chunk.  All fragments are read first and the
+// products are issued product by product across the tiles, so the tiles'
+// accumulation chains are in flight together.
 template <int NT, int W, int U0, int U1, int PB>
 __device__ inline void gram_tiles_split(const __bf16 (*hs)[PB], const __bf16 (*ls)[PB],
                                         double (&gd)[U1 - U0][4], int r16, int q) {
+  constexpr int NU = U1 - U0;
+  constexpr int nfirst = 8 - W;
+  bf8 rh[NU], rl[NU], ch[NU], cl[NU];
+  bool ok[NU];
 #pragma unroll
-  for (int u = U0; u < U1; ++u) {
-    constexpr int nfirst = 8 - W;
-    const int rt = u < nfirst ? W : 7 - W;
-    const int ct = u < nfirst ? W + u : (7 - W) + (u - nfirst);
-    if (rt >= NT || ct >= NT) continue;
-    const bf8 rh = *(const bf8 *)&hs[16 * rt + r16][8 * q];
-    const bf8 rl = *(const bf8 *)&ls[16 * rt + r16][8 * q];
-    const bf8 ch = *(const bf8 *)&hs[16 * ct + r16][8 * q];
-    const bf8 cl = *(const bf8 *)&ls[16 * ct + r16][8 * q];
-    f4 c = f4{0, 0, 0, 0};
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl, cl, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh, cl, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl, ch, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh, ch, c, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) gd[u - U0][r] += (double)c[r];
+  for (int u = 0; u < NU; ++u) {
+    const int rt = U0 + u < nfirst ? W : 7 - W;
+    const int ct = U0 + u < nfirst ? W + U0 + u : (7 - W) + (U0 + u - nfirst);
+    ok[u] = rt < NT && ct < NT;
+    const int ri = ok[u] ? rt : 0, ci = ok[u] ? ct : 0;  // unused tiles read tile 0
+    rh[u] = *(const bf8 *)&hs[16 * ri + r16][8 * q];
+    rl[u] = *(const bf8 *)&ls[16 * ri + r16][8 * q];
+    ch[u] = *(const bf8 *)&hs[16 * ci + r16][8 * q];
+    cl[u] = *(const bf8 *)&ls[16 * ci + r16][8 * q];
   }
+  f4 c[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) c[u] = f4{0, 0, 0, 0};
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl[u], cl[u], c[u], 0, 0, 0);
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh[u], cl[u], c[u], 0, 0, 0);
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl[u], ch[u], c[u], 0, 0, 0);
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh[u], ch[u], c[u], 0, 0, 0);
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gd[u][r] += (double)c[u][r];
 }
 
-// First Cholesky-QR pass fused with the second Gram (FP32 orbitals, N <= 128):
-// W1 never leaves the chip.  The first factor enters as its split value
-// I + (Dh + Dl), Dh/Dl the BF16 pieces of D = L1^-1 - I (the combined factor
-// of the two passes is formed from that same split value, so the second pass
-// measures exactly the transform that is applied; the first factor comes from
-// a BF16 Gram and is approximate anyway).  Per 32-point block:
-//  * each thread loads 8 consecutive orbitals at one point (two blocks in
-//    flight in registers), stores them in LDS in FP32 and, transposed, as
-//    BF16 hi/lo pieces (one 16-byte write each);
-//  * wave (pair p, half h) forms (D X)^T for row tiles p, 7 - p and the 16
-//    points 16h .. 16h + 15 as the four BF16 MFMA products Dh Xh, Dh Xl,
-//    Dl Xh, Dl Xl with FP32 accumulation, adds X in FP32 and stores W1 as
-//    BF16 hi/lo pieces;
-//  * after a barrier, the wave accumulates Gram tiles u in [0, 5) (h = 0) or
-//    [5, 9) (h = 1) of pair p with the split products (gram_tiles_split),
-//    flushed into FP64 every block.
 template <int NT>
 __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D,
                                                      const float *__restrict__ X, int N, i64 ng,
