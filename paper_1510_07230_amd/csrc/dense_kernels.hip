@@ -592,7 +592,9 @@ __global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, 
 }
 
 // The same contraction with the FP32 values rounded to BF16 (MFMA 16x16x32,
-// FP32 accumulation per 32 points, flushed into FP64).
+// FP32 accumulation per 32 points, flushed into FP64).  Each chunk is staged
+// in LDS already rounded, so an MFMA fragment is one 16-byte read; with TRIAL
+// the kernel also forms and stores the FP32 trial point W - tau Z it rounds.
 template <int NT, int KC, bool TRIAL>
 __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restrict__ A, int N,
                                                                i64 ng, i64 kper,
