@@ -325,15 +325,13 @@ pou_status poisson(pou_ctx *c, const double *f, double *x, double rtol, int maxi
 // r.r and b.b land in rrbb[0..1] for the caller's check.
 pou_status poisson_async(pou_ctx *c, const double *f, double *x, double *rrbb) {
   hipStream_t s = c->stream;
-  const i64 ng = c->ng;
   const int nb = c->nblk_field;
   const double ih2 = 1.0 / (c->h * c->h);
   double *sc = c->d_sc;  // [5] sum f
   const double fourpi = 12.566370614359172954;
+  // sum f (for the residual's right-hand side) comes out of the forward FFT
   KL(POU_K_POISSON, pou::launch_spectral_inverse(f, x, c->d_fft0, c->d_fft1, c->d_lam1, c->n,
-                                                 fourpi, s));
-  KL(POU_K_POISSON, pou::launch_dot2(f, nullptr, c->d_part, ng, nb, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, sc + 5, 1, nb, 1, 1.0, s));
+                                                 fourpi, s, sc + 5));
   KL(POU_K_POISSON, pou::launch_poisson_residual(x, f, sc + 5, c->d_part, c->n, ih2, nb, s));
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rrbb, 1, nb, 2, 1.0, s));
   return POU_OK;

@@ -662,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
                                                 void *__restrict__ out, int n, int axis,
                                                 int lb, int mode, Radices f,
                                                 const double *__restrict__ lam1,
-                                                double scale) {
+                                                double scale, double *__restrict__ dc) {
   extern __shared__ double2 lds[];
   double2 *a = lds;
   double2 *b = lds + lb * n;
@@ -715,8 +715,12 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
       const int line = t / n, e = t % n;
       double2 v = res[t];
       if (line < nl) {
+        const bool mean_mode = first + line == 0 && outer == 0 && e == 0;
+        // the (0,0,0) coefficient of the unnormalised forward transform is
+        // the sum of the input over the grid
+        if (mean_mode && dc != nullptr) dc[0] = v.x;
         const double lam = lam1[first + line] + lam1[outer] + lam1[e];
-        const double w = (first + line == 0 && outer == 0 && e == 0) ? 0.0 : scale / lam;
+        const double w = mean_mode ? 0.0 : scale / lam;
         v = make_double2(v.x * w, v.y * w);
       }
       res[t] = v;
@@ -1142,7 +1146,8 @@ hipError_t launch_remove_mean(double *x, const double *dsum, i64 ng, hipStream_t
 }
 
 hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, double2 *w1,
-                                   const double *lam1, int n, double scale, hipStream_t s) {
+                                   const double *lam1, int n, double scale, hipStream_t s,
+                                   double *sum_r) {
   const Radices f = factorize(n);
   // lines per workgroup: 8, or the largest divisor of n in 4..7, so that no
   // workgroup holds a ragged batch (measured at 96^3: 8 lines per workgroup
@@ -1161,15 +1166,15 @@ hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, do
   const double invn3 = scale / ((double)n * n * n);
   // x forward (real in) -> y forward -> z forward, divide, z inverse -> y inverse -> x inverse
   hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)r, (void *)w0, n, 0, lb, 1, f,
-                     lam1, 1.0);
+                     lam1, 1.0, (double *)nullptr);
   hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 0, f,
-                     lam1, 1.0);
+                     lam1, 1.0, (double *)nullptr);
   hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w1, (void *)w0, n, 2, lb, 3, f,
-                     lam1, invn3);
+                     lam1, invn3, sum_r);
   hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 4, f,
-                     lam1, 1.0);
+                     lam1, 1.0, (double *)nullptr);
   hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w1, (void *)out, n, 0, lb, 2, f,
-                     lam1, 1.0);
+                     lam1, 1.0, (double *)nullptr);
   return hipGetLastError();
 }
 

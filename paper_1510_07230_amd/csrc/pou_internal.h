@@ -125,10 +125,12 @@ hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const doub
 hipError_t launch_scale(double *x, double a, i64 ng, hipStream_t s);
 // dst = src - mean(src) with mean from dmean (used to fix the gauge)
 hipError_t launch_remove_mean(double *x, const double *dmean, i64 ng, hipStream_t s);
-// Spectral inverse of -Lap: out = (-Lap)^+ r (zero mean), via 3-D FFT.
-// out = scale * (-Lap)^+ r by FFT (zero mean), exact for the FD8 operator.
+// Spectral inverse of -Lap: out = scale * (-Lap)^+ r (zero mean) by 3-D FFT,
+// exact for the FD8 operator; sum_r (nullable) receives sum_g r_g, the mean
+// mode of the forward transform.
 hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, double2 *w1,
-                                   const double *lam1, int n, double scale, hipStream_t s);
+                                   const double *lam1, int n, double scale, hipStream_t s,
+                                   double *sum_r = nullptr);
 hipError_t launch_poisson_residual(const double *x, const double *rho, const double *dsum,
                                    double *part, int n, double inv_h2, int nblk, hipStream_t s);
 
