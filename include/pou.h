@@ -58,8 +58,10 @@ typedef enum {
 typedef enum {
   POU_FP64 = 0,  /* orbitals, H*U, stencil, Gram and apply in FP64 */
   POU_MIXED = 1  /* orbitals and stencil in FP32; Gram pass 1 in BF16 on MFMA with
-                    FP32 accumulation, pass 2 and the apply FP32; Cholesky, energy
-                    and all reductions FP64 (section 3.2 Cholesky QR, applied twice) */
+                    FP32 accumulation; pass 2 and the applies FP32-accurate (BF16
+                    hi/lo products on MFMA, or FP32 MFMA for the final apply of up
+                    to 128 orbitals); Cholesky, energy and all reductions FP64
+                    (section 3.2 Cholesky QR, applied twice) */
 } pou_precision;
 
 /* Energy-term mask for tests: the full model is POU_TERM_ALL. */
