@@ -65,7 +65,11 @@ Parity: trajectory values have no published reference (the paper prints none
 for a reproducible system): "parity unpinned" for the tau / s / E sequences
 themselves.  The converged results are pinned by closed forms and dense
 diagonalisation, and every step is checked against the invariants of
-eq. "ene-de" (tests/test_oracle_algm.py).
+eq. "ene-de" (tests/test_oracle_algm.py).  The parts that make up a step are
+pinned on their own: the two Barzilai-Borwein values by blocks with
+hand-known traces, their alternation and the S, Y bookkeeping along a run,
+the fallback to tau_init, and the C/Q recursion by its unrolled closed form
+(C^(l) is the eta-weighted mean of E^(0..l)).
 """
 from __future__ import annotations
 

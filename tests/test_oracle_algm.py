@@ -226,3 +226,148 @@ def test_residual_is_orthogonal_to_the_block_and_matches_the_trace_identity():
     # ||R||^2 = ||H W||^2 - ||Sigma||_F^2 for orthonormal W
     hw2 = A.h ** 3 * np.sum(A.HW * A.HW)
     assert abs(A.residual() ** 2 - (hw2 - np.sum(S * S))) < 1e-9 * hw2
+
+
+# ---- Barzilai-Borwein values, their alternation, and the C/Q recursion
+# (section 3.2), pinned by hand-known traces and closed forms
+
+def _plane_wave_pair(n=8, L=5.0):
+    """Two functions orthonormal in the grid inner product h^3 sum a b:
+    normalised cos and sin of the lowest x mode (exactly orthogonal on the grid)."""
+    h = L / n
+    x = h * np.arange(n)
+    c = np.broadcast_to(np.cos(2 * np.pi * x / L)[None, None, :], (n, n, n)).copy()
+    s = np.broadcast_to(np.sin(2 * np.pi * x / L)[None, None, :], (n, n, n)).copy()
+    e1 = c / np.sqrt(h ** 3 * np.sum(c * c))
+    e2 = s / np.sqrt(h ** 3 * np.sum(s * s))
+    return e1, e2, h
+
+
+def _free_runner(n=8, L=5.0, N=2, **params):
+    cfg = synth.custom("t", n, L, 0, 1.0, 0.5, N, seed_id=61)
+    sys_ = ks.System(n, L, np.zeros((0, 3)), np.zeros(0), np.zeros(0),
+                     synth.occupations(cfg), ks.TERM_KIN)
+    return algm.AlgorithmM(synth.orbitals(cfg), sys_, algm.Params(**params))
+
+
+# S = [a1 e1, a2 e2], Y = [b1 e1 + c1 e2, b2 e2]:
+#   tr<S^T S> = a1^2 + a2^2, tr<S^T Y> = a1 b1 + a2 b2, tr<Y^T Y> = b1^2 + c1^2 + b2^2
+BB_CASES = [
+    # (a1, a2, b1, c1, b2)
+    (2.0, 1.0, 0.5, 1.0, 0.25),
+    (0.3, -1.5, -2.0, 0.7, 0.4),     # tr<S^T Y> < 0: its absolute value is used
+    (1e-3, 2e-3, 5e-2, -3e-2, 1e-2),
+]
+
+
+def _bb_blocks(a1, a2, b1, c1, b2):
+    e1, e2, h = _plane_wave_pair()
+    S = np.stack([a1 * e1, a2 * e2])
+    Y = np.stack([b1 * e1 + c1 * e2, b2 * e2])
+    ss = a1 * a1 + a2 * a2
+    sy = a1 * b1 + a2 * b2
+    yy = b1 * b1 + c1 * c1 + b2 * b2
+    return S, Y, ss, sy, yy
+
+
+@pytest.mark.parametrize("case", BB_CASES)
+def test_bb_values_from_hand_known_traces(case):
+    """tau1 = tr<S^T S>/|tr<S^T Y>| and tau2 = |tr<S^T Y>|/tr<Y^T Y> (section 3.2)
+    on blocks whose traces are known by construction; fixed modes 1 and 2, and
+    the alternating mode 0 (tau1 on odd l, tau2 on even l)."""
+    S, Y, ss, sy, yy = _bb_blocks(*case)
+    tau1 = ss / abs(sy)
+    tau2 = abs(sy) / yy
+    assert abs(tau1 - tau2) > 1e-3 * tau1      # the cases tell the two values apart
+    A1 = _free_runner(bb_mode=1)
+    A2 = _free_runner(bb_mode=2)
+    A0 = _free_runner(bb_mode=0)
+    for l in (1, 2, 3, 4, 7):
+        assert abs(A1._bb_value(S, Y, l) - tau1) < 1e-13 * tau1
+        assert abs(A2._bb_value(S, Y, l) - tau2) < 1e-13 * tau2
+        want = tau1 if l % 2 == 1 else tau2
+        assert abs(A0._bb_value(S, Y, l) - want) < 1e-13 * want, l
+
+
+def test_bb_step_uses_the_last_two_iterates_and_directions():
+    """bb_step forms S = W^(l) - W^(l-1) and Y = Z^(l) - Z^(l-1) from the stored
+    history: plant a history whose differences are the hand-known blocks."""
+    S, Y, ss, sy, yy = _bb_blocks(*BB_CASES[0])
+    A = _free_runner(bb_mode=0)
+    rng = np.random.default_rng(7)
+    Z = rng.standard_normal(A.W.shape)
+    A.Wp = A.W - S
+    A.Zp = Z - Y
+    A.l = 1
+    assert abs(A.bb_step(Z) - ss / abs(sy)) < 1e-12 * ss / abs(sy)
+    A.l = 2
+    assert abs(A.bb_step(Z) - abs(sy) / yy) < 1e-12 * abs(sy) / yy
+    # l = 0 (no history) takes tau_init whatever is stored
+    A.l = 0
+    assert A.bb_step(Z) == A.tau_init
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_bb_fallback_on_zero_or_nonfinite_values(mode):
+    """No usable BB value (S = 0 or Y = 0 make a ratio 0/0, x/0 or 0) falls back
+    to tau_init (the reading for a missing safeguard)."""
+    S, Y, _, _, _ = _bb_blocks(*BB_CASES[0])
+    A = _free_runner(bb_mode=mode, tau_init=0.0123)
+    zero = np.zeros_like(S)
+    for l in (1, 2):
+        assert A._bb_value(zero, Y, l) == 0.0123
+        assert A._bb_value(S, zero, l) == 0.0123
+        assert A._bb_value(zero, zero, l) == 0.0123
+    # S and Y in different orbitals: tr<S^T Y> = 0 exactly, so tau1 = x/0 and tau2 = 0
+    e1, e2, _ = _plane_wave_pair()
+    So = np.stack([e1, np.zeros_like(e1)])
+    Yo = np.stack([np.zeros_like(e2), e2])
+    for l in (1, 2):
+        assert A._bb_value(So, Yo, l) == 0.0123
+
+
+def test_bb_alternation_along_a_trajectory():
+    """Along a run with mode 0, each step's tau_BB is the value the paper's
+    formula gives for the recorded W^(l), W^(l-1), Z^(l), Z^(l-1): tau1 on odd l,
+    tau2 on even l, tau_init at l = 0 (traces summed here with plain numpy)."""
+    sys_, cfg = _small16()
+    A = algm.AlgorithmM(synth.orbitals(cfg), sys_, algm.Params(bb_mode=0))
+    h3 = sys_.h ** 3
+    Ws, Zs = [], []
+    for l in range(16):
+        Ws.append(A.W.copy())
+        Zs.append(A.direction())
+        rec = A.step()
+        if l == 0:
+            assert rec.tau_bb == A.tau_init
+            continue
+        S = Ws[l] - Ws[l - 1]
+        Y = Zs[l] - Zs[l - 1]
+        ss = h3 * float(np.sum(S * S))
+        sy = abs(h3 * float(np.sum(S * Y)))
+        yy = h3 * float(np.sum(Y * Y))
+        want = ss / sy if l % 2 == 1 else sy / yy
+        assert abs(rec.tau_bb - want) < 1e-9 * want, (l, rec.tau_bb, want)
+
+
+@pytest.mark.parametrize("eta", [0.0, 0.85, 1.0])
+def test_nonmonotone_reference_matches_closed_form(eta):
+    """Q^(0) = 1, Q^(l+1) = eta Q^(l) + 1 and C^(l+1) = (eta Q^(l) C^(l) + E^(l+1)) / Q^(l+1)
+    (section 3.2) unroll to Q^(l) = sum_{j<=l} eta^j and
+    C^(l) = sum_{j<=l} eta^(l-j) E^(j) / Q^(l): a weighted mean of the energies.
+    eta = 0 gives C = E, eta = 1 the running mean."""
+    sys_, cfg = _small16()
+    A = algm.AlgorithmM(synth.orbitals(cfg), sys_, algm.Params(eta=eta))
+    E = [A.E]
+    for l in range(1, 51):
+        rec = A.step()
+        E.append(rec.E)
+        w = np.array([eta ** (l - j) for j in range(l + 1)])
+        Q = float(np.sum(w))
+        C = float(np.sum(w * np.array(E))) / Q
+        assert abs(rec.Q - Q) < 1e-12 * Q, (l, rec.Q, Q)
+        assert abs(rec.C - C) < 1e-12 * abs(C), (l, rec.C, C)
+        if eta == 0.0:
+            assert rec.C == rec.E
+        if eta == 1.0:
+            assert abs(rec.C - np.mean(E)) < 1e-12 * abs(rec.C)

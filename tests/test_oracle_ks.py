@@ -217,7 +217,7 @@ def test_correlation_high_density_limit_and_branch_continuity():
     rs = np.array([1.0 - 1e-12, 1.0 + 1e-12])
     rho = 3.0 / (4.0 * np.pi * rs ** 3)
     eps, v = ks.correlation_density(rho)
-    assert abs(eps[0] - eps[1]) < 1e-4 and abs(v[0] - v[1]) < 1e-3
+    assert abs(eps[0] - eps[1]) < 1e-4 and abs(v[0] - v[1]) < 1e-4
     # zero density: no energy, no potential; low density: eps_c -> G / (B2 r_s)
     e0, v0 = ks.correlation_density(np.array([0.0]))
     assert e0[0] == 0.0 and v0[0] == 0.0
@@ -238,3 +238,26 @@ def test_energy_gradient_with_correlation_matches_central_differences():
         fd = (ks.energy(U + eps * D, sys_).E - ks.energy(U - eps * D, sys_).E) / (2 * eps)
         an = float(np.sum(G * D))
         assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (fd, an)
+
+
+def _eps_c_of_rs(rs):
+    rs = np.asarray(rs, dtype=np.float64)
+    return ks.correlation_density(3.0 / (4.0 * np.pi * rs ** 3))[0]
+
+
+def test_correlation_fit_has_a_continuous_slope_at_rs_one():
+    """The Perdew-Zunger fit joins its two branches at r_s = 1 with equal value
+    and equal slope d eps_c / d r_s (that is how the coefficients of the
+    high-density branch were fixed).  Slopes are taken by central differences
+    of the oracle's eps_c on each side of r_s = 1, so a mistyped coefficient of
+    either branch (C = 0.0002 or 0.0038 gives a slope jump of 1.8e-3, a wrong
+    D a value jump of 1e-3 and more) fails here; the published fit itself
+    meets to 1.3e-5 in slope and 3.2e-5 in value (its printed digits)."""
+    d = 5e-7
+    left = (_eps_c_of_rs(1.0 - 1e-6 + d) - _eps_c_of_rs(1.0 - 1e-6 - d)) / (2 * d)
+    right = (_eps_c_of_rs(1.0 + 1e-6 + d) - _eps_c_of_rs(1.0 + 1e-6 - d)) / (2 * d)
+    assert abs(left - right) < 2e-5, (left, right)
+    # both slopes are positive: eps_c rises towards zero as the density falls
+    assert left > 0.0 and right > 0.0
+    e = _eps_c_of_rs(np.array([1.0 - 1e-12, 1.0 + 1e-12]))
+    assert abs(e[0] - e[1]) < 5e-5
