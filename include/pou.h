@@ -155,8 +155,11 @@ pou_status pou_set_system(pou_ctx *ctx, const pou_grid *grid, int natoms,
 pou_status pou_energy(pou_ctx *ctx, const void *U, pou_energy_terms *out);
 
 /* Orth(U) of Algorithm B step 5, in place: U <- U R^-1 with R upper
-   triangular, diag R > 0, <U^T U> = I (Cholesky QR through the Gram matrix,
-   repeated until the Gram is within 1e-13 (FP64) of I, at most 3 passes).
+   triangular, diag R > 0, <U^T U> = I (Cholesky QR through the Gram matrix
+   with FP32-accurate or FP64 products, at most 3 passes: passes continue
+   until the Gram measured by a pass is within 1e-8 (FP64) / 1e-4 (FP32
+   orbitals) of I after at least two passes, or within 1e-12 / 1e-8 already
+   after the first).
    orth_err (host, nullable) receives max |<U^T U> - I| after the call.
    POU_ERR_NOT_SPD if U is numerically rank deficient (U unchanged).
    Resets the BB history (U changed). */
@@ -169,7 +172,10 @@ pou_status pou_orthonormalize(pou_ctx *ctx, void *U, double *orth_err);
    modify U between consecutive calls. */
 pou_status pou_orbital_update_step(pou_ctx *ctx, void *U, pou_step_info *out);
 
-/* Gradient of gE * E(U) at fixed ions, and of E with respect to the ions:
+/* Gradient of gE * E(U) at fixed ions, and of E with respect to the ions.
+   The orbital part is the derivative E_{u_i} of section 2.1 for this E,
+   including the occupation factor (the discrete energy of eq. "energy" with
+   rho = sum f_i u_i^2 gives dE/du_i = 2 f_i h^3 H(rho) u_i):
      dU     (device, nullable, precision of U): gE * 2 f_i h^3 (H u_i)
      dR     (device double [natoms][3], nullable): gE * dE/dR_I
      dsigma (device double [natoms], nullable):   gE * dE/dsigma_I
@@ -195,8 +201,26 @@ pou_status pou_hamiltonian_apply(pou_ctx *ctx, const void *U, void *HU, double *
 pou_status pou_get_fields(pou_ctx *ctx, double *rho, double *vh, double *veff,
                           double *vext);
 
-/* Symmetric Gram matrix <U^T U> = h^3 U U^T into G (host double [norb][norb]). */
-pou_status pou_gram(pou_ctx *ctx, const void *U, double *G);
+/* Gram matrix of section 3.2 (Cholesky QR), <U^T U> = h^3 U U^T, into G
+   (host double [norb][norb], full symmetric), formed by the kernels of the
+   orthonormalisation.  mode POU_GRAM_ACCURATE: FP64 MFMA for FP64 orbitals;
+   FP32-accurate for FP32 orbitals (FP32 MFMA up to 128 orbitals, BF16 hi/lo
+   products above).  mode POU_GRAM_BF16 (FP32 orbitals only, else
+   POU_ERR_ARG): the first-pass Gram of the mixed form, products of
+   BF16-rounded values summed in FP32 on MFMA and flushed to FP64.  U is not
+   modified. */
+enum { POU_GRAM_ACCURATE = 0, POU_GRAM_BF16 = 1 };
+pou_status pou_gram(pou_ctx *ctx, const void *U, int mode, double *G);
+
+/* Trial point of a step (section 3.2 and Algorithm M): for the device block
+   U, H = H(rho(U)) is formed (as by pou_energy) and W~ = U - tau Z with
+   z_i = H u_i - sigma_ii u_i, sigma_ii = <H u_i, u_i>, is written to Wt
+   (device, nullable, precision and layout of U) and its Gram <W~^T W~> to G
+   (host double [norb][norb], nullable), by the kernels a step's first
+   Cholesky-QR pass uses (with POU_MIXED and two passes the Gram is the BF16
+   first-pass Gram).  tau must be finite.  U is not modified; the iteration
+   state is kept. */
+pou_status pou_trial_point(pou_ctx *ctx, const void *U, double tau, void *Wt, double *G);
 
 /* Element-type conversion of a block of count elements between FP32 and
    FP64 device buffers (src_prec, dst_prec in {POU_FP64, POU_MIXED}). */

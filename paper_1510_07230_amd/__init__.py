@@ -25,6 +25,7 @@ STATUS = {0: "POU_OK", -1: "POU_ERR_ARG", -2: "POU_ERR_STATE", -3: "POU_ERR_HIP"
 FP64, MIXED = 0, 1
 TERM_KIN, TERM_EXT, TERM_HARTREE, TERM_XC, TERM_ALL = 1, 2, 4, 8, 15
 TERM_CORR = 16  # LDA correlation, opt in
+GRAM_ACCURATE, GRAM_BF16 = 0, 1
 
 
 class PouError(RuntimeError):
@@ -77,7 +78,8 @@ _SIGNATURES = {
     "pou_energy_backward": (_i, [_vp, _vp, _d, _vp, _vp, _vp]),
     "pou_hamiltonian_apply": (_i, [_vp, _vp, _vp, _dp]),
     "pou_get_fields": (_i, [_vp, _vp, _vp, _vp, _vp]),
-    "pou_gram": (_i, [_vp, _vp, _dp]),
+    "pou_gram": (_i, [_vp, _vp, _i, _dp]),
+    "pou_trial_point": (_i, [_vp, _vp, _d, _vp, _dp]),
     "pou_convert": (_i, [_vp, _vp, _i, _vp, _i, ctypes.c_longlong]),
     "pou_reset_history": (_i, [_vp]),
     "pou_profile_enable": (_i, [_vp, ctypes.c_uint]),
@@ -211,14 +213,28 @@ class System:
         return {"E": t.E, "E_kin": t.E_kin, "E_ext": t.E_ext, "E_H": t.E_H, "E_x": t.E_x,
                 "E_c": t.E_c, "cg_iters": t.cg_iters}
 
+    @staticmethod
+    def _written(t):
+        """Tell autograd that the library wrote t in place (ctypes bypasses
+        torch's version counter), so a graph that saved t refuses to use it."""
+        from torch.autograd.graph import increment_version
+        increment_version(t)
+
     def orthonormalize_(self, U):
         err = ctypes.c_double(0.0)
-        self._check(lib().pou_orthonormalize(self._h, self._block(U), ctypes.byref(err)))
+        try:
+            self._check(lib().pou_orthonormalize(self._h, self._block(U), ctypes.byref(err)))
+        finally:
+            self._written(U)
         return err.value
 
     def step_(self, U):
         info = StepInfo()
-        self._check(lib().pou_orbital_update_step(self._h, self._block(U), ctypes.byref(info)))
+        try:
+            self._check(lib().pou_orbital_update_step(self._h, self._block(U),
+                                                      ctypes.byref(info)))
+        finally:
+            self._written(U)
         return {k: getattr(info, k) for k, _ in StepInfo._fields_}
 
     def residual(self, U):
@@ -243,10 +259,22 @@ class System:
                                                     for k in ("rho", "vh", "veff", "vext")]))
         return out
 
-    def gram(self, U):
+    def gram(self, U, bf16=False):
+        """<U^T U> (FP64 host array); bf16=True: the mixed form's first-pass
+        BF16 Gram (FP32 blocks only)."""
         G = np.zeros((self.N, self.N))
-        self._check(lib().pou_gram(self._h, self._block(U), _dptr(G)))
+        mode = GRAM_BF16 if bf16 else GRAM_ACCURATE
+        self._check(lib().pou_gram(self._h, self._block(U), mode, _dptr(G)))
         return G
+
+    def trial_point(self, U, tau):
+        """(W~ = U - tau Z as a device block, its Gram as the step's first pass
+        forms it) for Z = H(rho(U)) U - U diag(sigma)."""
+        Wt = self.torch.empty_like(U)
+        G = np.zeros((self.N, self.N))
+        self._check(lib().pou_trial_point(self._h, self._block(U), float(tau),
+                                          ctypes.c_void_p(Wt.data_ptr()), _dptr(G)))
+        return Wt, G
 
     def backward(self, U, gE=1.0, want_dU=True, want_forces=True):
         torch = self.torch
@@ -262,8 +290,11 @@ class System:
         pr = lambda t: FP64 if t.dtype == self.torch.float64 else MIXED
         if src.numel() != dst.numel():
             raise ValueError("size mismatch")
-        self._check(lib().pou_convert(self._h, ctypes.c_void_p(src.data_ptr()), pr(src),
-                                      ctypes.c_void_p(dst.data_ptr()), pr(dst), src.numel()))
+        try:
+            self._check(lib().pou_convert(self._h, ctypes.c_void_p(src.data_ptr()), pr(src),
+                                          ctypes.c_void_p(dst.data_ptr()), pr(dst), src.numel()))
+        finally:
+            self._written(dst)
         return dst
 
     def reset_history(self):
@@ -302,12 +333,15 @@ def _energy_fn():
 
         @staticmethod
         def forward(ctx, U, R, sigma, system):
-            Rn = R.detach().cpu().numpy()
-            sn = sigma.detach().cpu().numpy()
+            Rn = np.array(R.detach().cpu().numpy(), dtype=np.float64).reshape(-1, 3)
+            sn = np.array(sigma.detach().cpu().numpy(), dtype=np.float64)
             if not (np.array_equal(Rn, system.R) and np.array_equal(sn, system.sigma)):
                 system.set_system(Rn, system.Z, sn, system.occ)
             e = system.energy(U.detach())
             ctx.system = system
+            # the ions of this evaluation: another forward may move the shared
+            # context's ions before this graph's backward runs
+            ctx.R, ctx.sigma = Rn, sn
             ctx.rdev = (R.device, R.dtype, sigma.device, sigma.dtype)
             ctx.save_for_backward(U)
             return torch.tensor(e["E"], dtype=torch.float64, device=U.device)
@@ -315,10 +349,16 @@ def _energy_fn():
         @staticmethod
         def backward(ctx, g):
             (U,) = ctx.saved_tensors
-            dU, dR, ds = ctx.system.backward(U.detach(), float(g.item()),
-                                             want_dU=ctx.needs_input_grad[0],
-                                             want_forces=(ctx.needs_input_grad[1]
-                                                          or ctx.needs_input_grad[2]))
+            system = ctx.system
+            if not (np.array_equal(ctx.R, system.R) and np.array_equal(ctx.sigma, system.sigma)):
+                system.set_system(ctx.R, system.Z, ctx.sigma, system.occ)
+            # evaluate U afresh at these ions: the context's cached evaluation may
+            # belong to another block or to other ions
+            system.energy(U.detach())
+            dU, dR, ds = system.backward(U.detach(), float(g.item()),
+                                         want_dU=ctx.needs_input_grad[0],
+                                         want_forces=(ctx.needs_input_grad[1]
+                                                      or ctx.needs_input_grad[2]))
             if dR is not None:
                 dR = dR.to(ctx.rdev[0], ctx.rdev[1])
                 ds = ds.to(ctx.rdev[2], ctx.rdev[3])

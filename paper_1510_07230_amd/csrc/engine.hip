@@ -35,6 +35,17 @@ struct Report {
   static int rr(int N) { return 2 * N + 4 + 2 * kMaxPass; }
 };
 
+// Every admitted grid (9 <= n <= 1024) gets at least one FFT line per
+// workgroup within the LDS cap of the Hartree solve.
+constexpr bool fft_fits_all_grids() {
+  for (int n = 9; n <= 1024; ++n)
+    if (pou::fft_lines_per_group(n) < 1 || pou::fft_lds_bytes(n, pou::fft_lines_per_group(n)) >
+                                                pou::kFftLdsMax)
+      return false;
+  return true;
+}
+static_assert(fft_fits_all_grids(), "FFT line batch does not fit the LDS cap for some n");
+
 double lambda1(int n, double h, int k) {
   // eigenvalue of -D2 (periodic 8th-order) on Fourier mode k: -(c0 + 2 sum c_m cos m theta)/h^2
   const double c[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
@@ -88,6 +99,7 @@ struct pou_ctx {
   double *d_red = nullptr;     // small reduction outputs
   double *d_S = nullptr, *d_P = nullptr, *d_xpart = nullptr;  // subspace rotation / residual
   double *d_scal = nullptr;    // (tau_BB, zz, ss, sy, yy) of the current step
+  double *d_diag = nullptr;    // step size of a pou_trial_point call
   double *d_rep[2] = {nullptr, nullptr};  // evaluation reports (current, trial)
   void *d_HW = nullptr, *d_HWt = nullptr, *d_Wt = nullptr, *d_W1 = nullptr, *d_W2 = nullptr;
   std::vector<void *> allocs;
@@ -460,7 +472,9 @@ pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info,
   const bool fused_ok = ((c->N + 15) / 16 + 7) / 8 == 1;
   *rho_done = false;
   for (int p = 0; p < passes; ++p) {
-    CHK(gram<T>(c, cur, mixed && p == 0));
+    // BF16 Gram only for the first of two passes: a single pass must be
+    // FP32-accurate, since nothing after it corrects its factor
+    CHK(gram<T>(c, cur, mixed && p == 0 && passes == 2));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
                                                        info + 2 * p, c->d_cholws, s));
     const bool last = (p == passes - 1);
@@ -1023,9 +1037,40 @@ pou_status hamiltonian_impl(pou_ctx *c, const T *U, T *HU, double *sigma) {
 }
 
 template <typename T>
-pou_status gram_impl(pou_ctx *c, const T *U, double *G) {
-  CHK(gram<T>(c, U, false));
+pou_status gram_impl(pou_ctx *c, const T *U, int mode, double *G) {
+  CHK(gram<T>(c, U, mode == POU_GRAM_BF16));
   CHK(sync_read(c, G, c->d_G, sizeof(double) * c->N * c->N));
+  return POU_OK;
+}
+
+// The trial point W - tau Z of U (Z from H(rho(U)), evaluated afresh) and its
+// Gram, through the kernels a step's first orthonormalisation pass uses.
+template <typename T>
+pou_status trial_point_impl(pou_ctx *c, const T *U, double tau, T *Wt, double *G) {
+  hipStream_t s = c->stream;
+  CHK(energy_impl<T>(c, U, nullptr));
+  const double *rep = (c->eval_HU == c->d_HW) ? c->d_rep[0] : c->d_rep[1];
+  c->h_step[0] = tau;  // pinned: the copy reads it after the synchronisation above
+  HIPCHK(c, hipMemcpyAsync(c->d_diag, c->h_step, sizeof(double), hipMemcpyHostToDevice, s));
+  const bool bf16 = sizeof(T) == 4 && c->p.orth_passes == 2;
+  if (c->N <= 128) {
+    KL(POU_K_TRIAL, pou::launch_trial_gram<T>(U, (const T *)c->eval_HU, rep, c->d_diag, 1.0,
+                                              (T *)c->d_Wt, c->N, c->ng, c->nsplit, bf16,
+                                              c->d_gpart, s));
+    KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+  } else {
+    KL(POU_K_TRIAL, pou::launch_trial<T>(U, (const T *)c->eval_HU, rep, c->d_diag, 1.0,
+                                         (T *)c->d_Wt, c->N, c->ng, s));
+    CHK(gram<T>(c, (const T *)c->d_Wt, bf16));
+  }
+  if (Wt)
+    HIPCHK(c, hipMemcpyAsync(Wt, c->d_Wt, sizeof(T) * (size_t)c->N * c->ng,
+                             hipMemcpyDeviceToDevice, s));
+  if (G) CHK(sync_read(c, G, c->d_G, sizeof(double) * c->N * c->N));
+  else {
+    HIPCHK(c, hipStreamSynchronize(s));
+    prof_drain(c);
+  }
   return POU_OK;
 }
 
@@ -1199,6 +1244,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_Mcomb, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_red, sizeof(double) * (size_t)std::max(4 * norb, 4 * std::max(1, natoms)) + 64));
   CHK(dalloc(c, &c->d_scal, sizeof(double) * 8));
+  CHK(dalloc(c, &c->d_diag, sizeof(double) * 8));
   // each report is followed by 8 doubles: step scalars and the accept flags
   CHK(dalloc(c, &c->d_rep[0], sizeof(double) * (Report::size(norb) + 8)));
   CHK(dalloc(c, &c->d_rep[1], sizeof(double) * (Report::size(norb) + 8)));
@@ -1311,11 +1357,24 @@ pou_status pou_get_fields(pou_ctx *c, double *rho, double *vh, double *veff, dou
   return POU_OK;
 }
 
-pou_status pou_gram(pou_ctx *c, const void *U, double *G) {
+pou_status pou_gram(pou_ctx *c, const void *U, int mode, double *G) {
   NEED_SYSTEM(c);
   if (!U || !G) return fail(c, POU_ERR_ARG, "null U or G");
-  if (c->prec == POU_FP64) return gram_impl<double>(c, (const double *)U, G);
-  return gram_impl<float>(c, (const float *)U, G);
+  if (mode != POU_GRAM_ACCURATE && mode != POU_GRAM_BF16)
+    return fail(c, POU_ERR_ARG, "bad Gram mode");
+  if (mode == POU_GRAM_BF16 && c->prec == POU_FP64)
+    return fail(c, POU_ERR_ARG, "the BF16 Gram needs FP32 orbitals (POU_MIXED)");
+  if (c->prec == POU_FP64) return gram_impl<double>(c, (const double *)U, mode, G);
+  return gram_impl<float>(c, (const float *)U, mode, G);
+}
+
+pou_status pou_trial_point(pou_ctx *c, const void *U, double tau, void *Wt, double *G) {
+  NEED_SYSTEM(c);
+  if (!U) return fail(c, POU_ERR_ARG, "null U");
+  if (!std::isfinite(tau)) return fail(c, POU_ERR_ARG, "tau must be finite");
+  if (c->prec == POU_FP64)
+    return trial_point_impl<double>(c, (const double *)U, tau, (double *)Wt, G);
+  return trial_point_impl<float>(c, (const float *)U, tau, (float *)Wt, G);
 }
 
 pou_status pou_convert(pou_ctx *c, const void *src, int src_prec, void *dst, int dst_prec,

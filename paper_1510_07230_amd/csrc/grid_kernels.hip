@@ -1149,18 +1149,9 @@ hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, do
                                    const double *lam1, int n, double scale, hipStream_t s,
                                    double *sum_r) {
   const Radices f = factorize(n);
-  // lines per workgroup: 8, or the largest divisor of n in 4..7, so that no
-  // workgroup holds a ragged batch (measured at 96^3: 8 lines per workgroup
-  // 5% faster than 10 with a ragged last batch, 16 and 20 slower: fewer
-  // workgroups); two LDS buffers of lb*n complex doubles + twiddles
-  int lb = 8;
-  for (int d = 8; d >= 4; --d)
-    if (n % d == 0) {
-      lb = d;
-      break;
-    }
-  if (lb > n) lb = n;
-  const size_t lds = (size_t)(2 * lb + 1) * n * sizeof(double2);  // two line buffers + twiddles
+  const int lb = fft_lines_per_group(n);
+  if (lb < 1) return hipErrorInvalidValue;
+  const size_t lds = fft_lds_bytes(n, lb);
   const int groups = (n + lb - 1) / lb;
   const dim3 grid(groups * n), block(kBlock);
   const double invn3 = scale / ((double)n * n * n);

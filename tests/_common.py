@@ -27,3 +27,95 @@ def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b))))
+
+
+# ---- tolerances derived from the arithmetic of the mixed form
+#
+# Rounding errors are modelled as independent with zero mean (the probabilistic
+# rounding-error analysis of Higham and Mary, SIAM J. Sci. Comput. 2019): a sum
+# of terms t_g, each carrying an error bounded by e_g, is off by at most
+# LAM * sqrt(sum e_g^2), except with probability below 2 exp(-LAM^2 / 2).
+LAM = 8.0
+U32 = 2.0 ** -24   # unit roundoff of FP32
+UBF = 2.0 ** -9    # unit roundoff of BF16 (8 significant bits)
+FD8_ABS = (205.0 / 72.0, 8.0 / 5.0, 1.0 / 5.0, 8.0 / 315.0, 1.0 / 560.0)
+
+
+def _abs_symbol(n, h):
+    """Fourier symbol of the magnitude operator A below on one axis."""
+    th = 2.0 * np.pi * np.arange(n) / n
+    return 0.5 / (h * h) * sum(FD8_ABS[m] * (2.0 * np.cos(m * th) + 2.0) for m in range(1, 5))
+
+
+def _kin_symbol(n, h):
+    th = 2.0 * np.pi * np.arange(n) / n
+    c = (-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0)
+    return -0.5 / (h * h) * (c[0] + sum(2.0 * c[m] * np.cos(m * th) for m in range(1, 5)))
+
+
+def _apply_symbol(U, s1):
+    import scipy.fft as sf
+    n = U.shape[-1]
+    sz = s1[:, None, None] + s1[None, :, None] + s1[None, None, : n // 2 + 1]
+    F = sf.rfftn(U, axes=(-3, -2, -1), workers=-1)
+    F *= sz
+    return sf.irfftn(F, s=(n, n, n), axes=(-3, -2, -1), workers=-1)
+
+
+def stencil_magnitude(U, h):
+    """A_g = 1/2 h^-2 sum_m |c_m| sum_axes (|u_{g+m}| + |u_{g-m}| + 2|u_g|): the
+    magnitude of the intermediate sums of the difference-form FP32 stencil
+    (sums of (u_{+m} - u_0) + (u_{-m} - u_0)); its rounding error per point is
+    a small multiple of U32 * A_g.  Applied through its Fourier symbol."""
+    a = np.abs(np.asarray(U, dtype=np.float64))
+    n = a.shape[-1]
+    return np.maximum(_apply_symbol(a, _abs_symbol(n, h)), 0.0)
+
+
+def kinetic_energy_tolerance(U, occ, h, ops=12):
+    """Bound on |E_kin(FP32 stencil) - E_kin(exact)| for the FP32 block U: per
+    point the kinetic value carries at most ops * U32 * A_g (the depth of the
+    stencil's sum tree with its subtractions) and its product with u_g, the
+    FP32 sum of a thread's four points and the product rounding add 3 U32
+    |u_g K u_g|; each term enters E_kin with weight f_i h^3."""
+    h3 = h ** 3
+    n = U.shape[-1]
+    tot = 0.0
+    for i0 in range(0, U.shape[0], 16):
+        u = np.asarray(U[i0:i0 + 16], dtype=np.float64)
+        A = stencil_magnitude(u, h)
+        ku = np.abs(_apply_symbol(u, _kin_symbol(n, h)))
+        f = np.asarray(occ[i0:i0 + 16], dtype=np.float64)[:, None, None, None]
+        e = f * h3 * np.abs(u) * (ops * A + 3.0 * ku) * U32
+        tot += float(np.sum(e * e))
+    return LAM * np.sqrt(tot)
+
+
+def gram_tolerance(X, h, chunk, u=UBF):
+    """Elementwise bound on |G - <X^T X>| for a Gram whose products use values
+    rounded to relative precision u (BF16: UBF; the hi + lo split of an FP32
+    value into two BF16 pieces: 2^-17; exact FP32 products: 0), summed in FP32
+    over runs of at most `chunk` points and in FP64 beyond:
+      * each value x(1 + d), |d| <= u, d uniform: the error x_i x_j (d_i + d_j)
+        has variance 2/3 u^2 (x_i x_j)^2 (4/3 on the diagonal);
+      * the second-order term x_i x_j d_i d_j is at most u^2 |x_i x_j|;
+      * an FP32 run of K terms is off by at most LAM sqrt(K) U32 times the sum
+        of its |terms|; the runs are added up linearly (no cancellation
+        credited between them)."""
+    N = X.shape[0]
+    A = np.asarray(X, dtype=np.float64).reshape(N, -1)
+    h3 = h ** 3
+    sq = (A * A) @ (A * A).T
+    ab = np.abs(A) @ np.abs(A).T
+    var = (2.0 / 3.0) * u ** 2 * sq
+    var[np.diag_indices(N)] *= 2.0
+    return h3 * (LAM * np.sqrt(var) + (u ** 2 + LAM * np.sqrt(chunk) * U32) * ab)
+
+
+def hamiltonian_error_bound(U, veff, h, ops=12):
+    """Per-element bound on |(H u)_FP32 - (H u)_exact| for the FP32 stencil with
+    an FP32 copy of V_eff: ops U32 A_g for the difference-form sum, and
+    3 U32 |V_eff u| for the rounding of V_eff to FP32, its product and the
+    final sum."""
+    A = stencil_magnitude(U, h)
+    return U32 * (ops * A + 3.0 * np.abs(veff)[None] * np.abs(U))

@@ -59,3 +59,14 @@ def test_fullsize_first_step_matches_oracle(setup):
     Wn = to_np(U)
     for i in (0, 64, 127):
         assert rel(Wn[i], A.W[i]) < 1e-9
+
+
+def test_fullsize_mixed_steps_match_oracle():
+    """Two mixed steps at 96^3 x 128 (the benchmark's configuration and launch
+    shapes) against the oracle from the same state: s equal, tau_BB within the
+    FP32-direction bound, the new block element-wise and the reported energy
+    against the oracle's energy of that block (bounds in tests/_common.py)."""
+    from _stepcheck import step_parity
+    cfg = synth.CONFIGS["mixed96"]
+    print("[full] mixed steps", flush=True)
+    step_parity(cfg, 2, "full mixed96")

@@ -300,3 +300,105 @@ def test_fp64_more_than_128_orbitals_follow_oracle(norb, n):
         assert info["s"] == r.s, (k, info["s"], r.s)
         assert abs(info["E"] - r.E) < 1e-9 * max(1, abs(r.E)), (k, info["E"], r.E)
     assert rel(to_np(U), A.W) < 1e-8
+
+
+def test_plain_cg_matches_oracle():
+    """cg_precond = 0: the Hartree potential by plain warm-started conjugate
+    gradients (the solve as first stated for the method) matches the oracle's
+    exact FFT solve, and three steps follow the oracle."""
+    cfg = synth.CONFIGS["fp64_48"]
+    print("[plain CG] fp64_48", flush=True)
+    so = oracle_system(cfg)
+    W = _start(cfg, so)
+    p = algm.Params()
+    p.tau_init = 1.0 / algm.lambda_max_kinetic(so.h)
+    g = gpu_system(cfg, cg_precond=0, tau_init=p.tau_init)
+    U = g.new_block(W)
+    e = g.energy(U)
+    assert e["cg_iters"] > 1
+    rho, VH, vx, veff, ex, vext, _ = ks.potentials(W, so)
+    f = g.fields()
+    assert rel(to_np(f["vext"]), vext) < 1e-11
+    assert rel(to_np(f["vh"]), VH) < 1e-11
+    assert abs(e["E"] - ks.energy(W, so, vext).E) < 1e-9 * abs(e["E"])
+    A = algm.AlgorithmM(W, so, p, orthonormalize_start=False)
+    for k in range(3):
+        r = A.step()
+        info = g.step_(U)
+        print(f"[plain CG] step {k}: s {info['s']}/{r.s} cg {info['cg_iters']} "
+              f"E {info['E']:.12f}/{r.E:.12f}", flush=True)
+        assert info["s"] == r.s
+        assert abs(info["E"] - r.E) < 1e-9 * abs(r.E)
+    assert rel(to_np(U), A.W) < 1e-8
+
+
+def test_energyfn_forces_at_the_forward_positions():
+    """Two forwards at displaced ions before the first backward: each backward
+    returns the gradient at its own forward's positions (section 2.1 energy;
+    forces at fixed orbitals), not at the positions the shared context holds
+    last."""
+    import torch
+    import paper_1510_07230_amd as pk
+    cfg = synth.CONFIGS["small16"]
+    so = oracle_system(cfg)
+    W = _start(cfg, so)
+    g = gpu_system(cfg)
+    R0, Z, s0 = synth.atoms(cfg)
+    Rp = R0.copy(); Rp[0, 1] += 0.05
+    Rm = R0.copy(); Rm[0, 1] -= 0.05
+    Up = g.new_block(W).requires_grad_(True)
+    Um = g.new_block(W).requires_grad_(True)
+    Rpt = torch.tensor(Rp, requires_grad=True)
+    Rmt = torch.tensor(Rm, requires_grad=True)
+    sp = torch.tensor(s0, requires_grad=True)
+    sm = torch.tensor(s0, requires_grad=True)
+    Ep = pk.EnergyFn.apply(Up, Rpt, sp, g)
+    Em = pk.EnergyFn.apply(Um, Rmt, sm, g)
+    Ep.backward()
+    Em.backward()
+    for Rx, Ux, Rt, st in ((Rp, Up, Rpt, sp), (Rm, Um, Rmt, sm)):
+        sx = ks.System(cfg.n, cfg.L, Rx, Z, s0, synth.occupations(cfg))
+        dR_o, ds_o = ks.forces(W, sx)
+        assert rel(Rt.grad.numpy(), dR_o) < 1e-9
+        assert rel(st.grad.numpy(), ds_o) < 1e-9
+        assert rel(to_np(Ux.grad), ks.energy_gradient(W, sx)) < 1e-10
+    assert abs(Ep.item() - ks.energy(W, ks.System(cfg.n, cfg.L, Rp, Z, s0,
+                                                  synth.occupations(cfg))).E) < 1e-9
+
+
+def test_energyfn_refuses_a_block_stepped_in_place():
+    """A step through the library writes U in place; autograd must refuse a
+    graph that saved the old U instead of differentiating at the new one."""
+    import torch
+    import paper_1510_07230_amd as pk
+    cfg = synth.CONFIGS["small16"]
+    so = oracle_system(cfg)
+    g = gpu_system(cfg)
+    U = g.new_block(_start(cfg, so))
+    R0, Z, s0 = synth.atoms(cfg)
+    Ul = U.detach().requires_grad_(True)
+    E = pk.EnergyFn.apply(Ul, torch.tensor(R0), torch.tensor(s0), g)
+    g.step_(Ul.detach())
+    with pytest.raises(RuntimeError, match="modified by an inplace operation"):
+        E.backward()
+
+
+@pytest.mark.parametrize("prec,cfgname", [("fp64", "fp64_48"), ("mixed", "n40N17")])
+def test_runs_are_bitwise_reproducible(prec, cfgname):
+    """Every reduction sums in a fixed order, so two runs from the same start
+    in fresh contexts give bit-identical blocks and step reports."""
+    cfg = synth.CONFIGS.get(cfgname) or next(c for c in CASES if c.name == cfgname)
+    so = oracle_system(cfg)
+    W = _start(cfg, so)
+    outs = []
+    for rep in range(2):
+        g = gpu_system(cfg, prec)
+        U = g.new_block(W)
+        infos = [g.step_(U) for _ in range(10)]
+        outs.append((to_np(U).copy(), infos))
+        g.close()
+    (U1, i1), (U2, i2) = outs
+    assert np.array_equal(U1, U2)
+    for a, b in zip(i1, i2):
+        for k in a:
+            assert (a[k] == b[k]) or (np.isnan(a[k]) and np.isnan(b[k])), (k, a[k], b[k])
