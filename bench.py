@@ -60,9 +60,18 @@ def algorithmic_bytes(group, N, ng, es):
         "apply_gram": B,                    # read X once (L^-1 X stays on chip)
         "gram": B,                          # read the block once
         "trial": 3 * B,                     # read W, H W; write W - tau Z (+ its Gram)
-        "commit": 5 * B,                    # read W, H W, W_new, H W_new; write U
+        # the Barzilai-Borwein traces read W, H W, W_new, H W_new; the kernel's
+        # write of W_new into the caller's block is counted apart (abi_bytes)
+        "commit": 4 * B,
         "density": B + ng * 8,
     }.get(group)
+
+
+def abi_bytes(group, N, ng, es):
+    """Bytes a launch moves for the interface rather than the method: the
+    accept kernel writes the new iterate into the caller's block U (one block),
+    which the method itself keeps in place."""
+    return N * ng * es if group == "commit" else 0
 
 
 # MFMA peaks of MI355X (dense), FLOP/s
@@ -121,21 +130,34 @@ def roofline_of(group, N, ng, es, avg_s):
                 "unit": "TFLOP/s", "frac": round(t_mfma / avg_s, 4),
                 "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": abytes}
     achieved = abytes / avg_s / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": abytes,
-            "algorithmic_flops_per_launch": flops}
+    rec = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": abytes,
+           "algorithmic_flops_per_launch": flops}
+    extra = abi_bytes(group, N, ng, es)
+    if extra:
+        rec["abi_copy_bytes_per_launch"] = extra
+        rec["frac_with_abi_copy"] = round((abytes + extra) / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    return rec
 
 
-def cpu_baseline(cfg, budget_s=30.0):
-    """Time the oracle's Algorithm-M step on this workload (bounded sample)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, single_thread=True):
+    """Time the oracle's Algorithm-M step on this workload (bounded sample:
+    one step with the host's BLAS/LAPACK threads, one with a single thread)."""
     import numpy as np
     import synth
     from oracle import ks, algm
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     R, Z, s = synth.atoms(cfg)
     so = ks.System(cfg.n, cfg.L, R, Z, s, synth.occupations(cfg))
     X = synth.orbitals(cfg)
@@ -143,10 +165,20 @@ def cpu_baseline(cfg, budget_s=30.0):
     t0 = time.perf_counter()
     A.step()
     t = time.perf_counter() - t0
-    return {"value": 1.0 / t, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one oracle Algorithm-M step (trial orth + energy + H W) on the full "
-                      f"{cfg.n}^3 / N={cfg.norb} workload, {t:.1f} s; the oracle's initial "
-                      f"orthonormalisation and energy are not timed"}
+    out = {"value": 1.0 / t, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
+           "cpu": cpu_model(), "host_cpus": len(os.sched_getaffinity(0)),
+           "sample": f"one oracle Algorithm-M step (trial orth + energy + H W) on the full "
+                     f"{cfg.n}^3 / N={cfg.norb} workload, {t:.1f} s, BLAS/LAPACK on {threads} "
+                     f"threads (NumPy's elementwise work and FFTs run on one); the oracle's "
+                     f"initial orthonormalisation and energy are not timed"}
+    if single_thread:
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            A.step()
+            t1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": 1.0 / t1, "unit": "iters/s", "cores": 1,
+                                "sample": f"the next oracle step with one thread, {t1:.1f} s"}
+    return out
 
 
 def run(args):
@@ -312,7 +344,7 @@ def run(args):
         out["copy_calibration_bytes"] = {"read": U32.numel() * 4, "write": U32.numel() * 4}
         del tmp
     if not args.no_converge:
-        out["delta_E"] = converge(args, cfg, R, Z, s, occ, g64, U64, g32, U32, progress)
+        out["delta_E"] = converge(args, cfg, R, Z, s, occ, g64, g32, W0, progress)
     if not args.no_cpu_baseline:
         progress("oracle CPU baseline")
         del g64, g32, U64, U32, W0
@@ -321,48 +353,108 @@ def run(args):
     print(json.dumps(out), flush=True)
 
 
-def converge(args, cfg, R, Z, s, occ, g64, U64, g32, U32, progress):
-    """Untimed: converge FP64 and mixed (+ FP64 refinement) and compare energies."""
+def mixed_switch(df, info):
+    """Rule that ends the mixed phase: the first step whose backtracking
+    exhausted s_max (no trial met eq. "ene-de").  Near the minimum the energy
+    decrease the test asks for, rho1 tau ||Z||^2, falls below the resolution of
+    an energy evaluated from FP32 orbitals and FP32 stencil sums, and the test
+    starts failing on rounding noise: at 96^3 x 128 the first such step comes
+    about 1e-3 Ha above the minimum, after which mixed steps average 3 to 7
+    trials and stall near 1e-4 Ha, while FP64 steps keep converging at about
+    1.2 trials.  A 3-step mean of df below 1e-10 also ends the phase."""
+    if info is not None and info.get("accepted", 1) == 0:
+        return True
+    return len(df) >= 3 and float(sum(df[-3:])) / 3.0 < 1e-10
+
+
+def converge(args, cfg, R, Z, s, occ, g64, g32, W0, progress):
+    """Time to |dE| <= 1e-6 Ha from the same orthonormal start by two routes:
+    FP64 steps alone, and mixed steps switched (mixed_switch) to FP64
+    refinement steps.  Both converge by the 3-step mean of df < 1e-13
+    (section 4.2).  The reference is the FP64 route's converged energy; the
+    oracle's energy of the final FP64 iterate is reported beside it.  The
+    wall time includes the host's step loop (each step synchronises)."""
     import numpy as np
     import torch
     import paper_1510_07230_amd as pk
 
-    def until(g, U, tol, cap_s, cap_steps):
-        df = []
+    def run(g, U, done, cap_s, cap_steps):
+        E, t, df = [], [], []
         t0 = time.perf_counter()
         info = None
-        k = 0
-        while time.perf_counter() - t0 < cap_s and k < cap_steps:
+        while len(E) < cap_steps and time.perf_counter() - t0 < cap_s:
             info = g.step_(U)
+            E.append(info["E"])
             df.append(info["df"])
-            k += 1
-            if len(df) >= 3 and np.mean(df[-3:]) < tol:
-                return info, k, True
-        return info, k, False
+            t.append(time.perf_counter() - t0)
+            if done(df, info):
+                return E, t, info, True
+        return E, t, info, False
 
-    i64, k64, c64 = until(g64, U64, 1e-13, args.converge_seconds, 100000)
-    progress(f"fp64 converged={c64} after {k64} more steps, E={i64['E']:.12f}")
-    i32, k32, c32 = until(g32, U32, 1e-10, args.converge_seconds / 2, 100000)
-    progress(f"mixed phase: {k32} more steps, E={i32['E']:.12f}")
+    def df_rule(df, info):
+        return len(df) >= 3 and float(np.mean(df[-3:])) < 1e-13
+
+    def time_to(E, t, E_ref, tol=1e-6):
+        """Time of the first step after which every energy stays within tol."""
+        k = len(E)
+        while k > 0 and abs(E[k - 1] - E_ref) <= tol:
+            k -= 1
+        return t[k] if k < len(E) else None
+
+    cap = args.converge_seconds
+    # route A: FP64 alone
+    U64 = W0.clone()
+    g64.reset_history()
+    EA, tA, iA, cA = run(g64, U64, df_rule, cap, 200000)
+    E_ref = iA["E"]
+    progress(f"fp64 route: {len(EA)} steps, {tA[-1]:.2f} s, converged={cA}, E={E_ref:.12f}")
+    # route B: mixed, then FP64 refinement
+    U32 = W0.to(torch.float32).contiguous()
+    g32.reset_history()
+    t0 = time.perf_counter()
+    EB1, tB1, iB1, cB1 = run(g32, U32, mixed_switch, cap, 200000)
     gr = pk.System(cfg.n, cfg.L, R, Z, s, occ, precision="fp64")
+    t1 = time.perf_counter()
     Ur = gr.new_block()
     gr.convert(U32, Ur)
     gr.orthonormalize_(Ur)
-    ir, kr, cr = until(gr, Ur, 1e-13, args.converge_seconds, 100000)
-    orth = gr.orthonormalize_(Ur.clone())
+    t_switch = time.perf_counter() - t1
+    EB2, tB2, iB2, cB2 = run(gr, Ur, df_rule, cap, 200000)
+    off = tB1[-1] + t_switch
+    EB = EB1 + EB2
+    tB = tB1 + [off + x for x in tB2]
+    progress(f"mixed route: {len(EB1)} mixed steps ({tB1[-1]:.2f} s), {len(EB2)} FP64 steps "
+             f"({tB2[-1]:.2f} s), E={iB2['E']:.12f}")
     G = gr.gram(Ur)
     orth_err = float(np.max(np.abs(G - np.eye(G.shape[0]))))
-    dE = abs(ir["E"] - i64["E"])
+    ttA = time_to(EA, tA, E_ref)
+    ttB = time_to(EB, tB, E_ref)
     res64, _ = g64.residual(U64)
     resr, _ = gr.residual(Ur)
-    progress(f"refined: {kr} FP64 steps, E={ir['E']:.12f}, |dE|={dE:.2e}, orth={orth_err:.2e}, "
-             f"residual fp64 {res64:.2e} refined {resr:.2e}")
-    return {"fp64_E": i64["E"], "fp64_converged": c64, "fp64_steps": k64 + args.steps + args.warmup,
-            "mixed_E_before_refine": i32["E"], "mixed_steps": k32 + args.steps + args.warmup,
-            "refined_E": ir["E"], "refine_steps": kr, "refine_converged": cr,
-            "abs_delta_E": dE, "orth_err_refined": orth_err,
-            "residual_fp64": res64, "residual_refined": resr,
-            "criterion": "3-step mean of df < 1e-13 (FP64 and refinement), < 1e-10 (mixed phase)"}
+    out = {"fp64_E": E_ref, "fp64_converged": cA, "fp64_steps": len(EA),
+           "mixed_steps": len(EB1), "mixed_E_at_switch": iB1["E"],
+           "mixed_switched_by_rule": cB1,
+           "refined_E": iB2["E"], "refine_steps": len(EB2), "refine_converged": cB2,
+           "abs_delta_E": abs(iB2["E"] - E_ref), "orth_err_refined": orth_err,
+           "residual_fp64": res64, "residual_refined": resr,
+           "time_to_1e-6_s": {"fp64": ttA, "mixed_then_fp64": ttB,
+                              "speedup": (ttA / ttB) if (ttA and ttB) else None},
+           "time_to_converged_s": {"fp64": tA[-1], "mixed_then_fp64": tB[-1]},
+           "criterion": "converged: 3-step mean of df < 1e-13; the mixed phase ends at the first "
+                        "step that exhausts s_max (or a 3-step mean df < 1e-10); time_to_1e-6 = "
+                        "wall time (host loop included) until E stays within 1e-6 Ha of the FP64 "
+                        "route's converged energy"}
+    if not args.no_oracle_energy:
+        from oracle import ks
+        so = ks.System(cfg.n, cfg.L, R, Z, s, occ)
+        Wf = U64.detach().cpu().numpy()
+        E_o = ks.energy(Wf, so).E
+        out["oracle_E_of_fp64_iterate"] = E_o
+        out["abs_E_gpu_minus_oracle_fp64"] = abs(E_ref - E_o)
+        progress(f"oracle energy of the final FP64 iterate {E_o:.12f} (|dE| {abs(E_ref - E_o):.2e})")
+    progress(f"time to |dE|<=1e-6: fp64 {ttA} s, mixed+refine {ttB} s; |dE| refined "
+             f"{out['abs_delta_E']:.2e}, orth {orth_err:.2e}")
+    return out
 
 
 def main():
@@ -373,6 +465,8 @@ def main():
     ap.add_argument("--workload", default="mixed96")
     ap.add_argument("--converge-seconds", type=float, default=40.0)
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--no-oracle-energy", action="store_true",
+                    help="skip the oracle's energy of the final FP64 iterate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-extras", action="store_true",

@@ -1,8 +1,18 @@
-"""Summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of bench.py.
+"""Summarise rocprofv3 counter runs of bench.py.
 
 Usage:
   python -m paper_1510_07230_amd.counters FETCH_CSV WRITE_CSV BLOCK_BYTES \\
       [--json OUT.json] [--md OUT.md] [--norb N --n n]
+  python -m paper_1510_07230_amd.counters --mfma COUNTER_CSV TRACE_CSV \\
+      [--md OUT.md] [--norb N --n n] [--cmd "..."]
+
+The --mfma form reads a run with SQ_INSTS_VALU_MFMA_MOPS_{BF16,F32,F64},
+SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE and the kernel trace of the same
+run, and reports per kernel the matrix-core FLOPs per dispatch (MOPS counters
+count units of 512 FLOPs), the achieved FLOP rate over the traced duration
+and its fraction of the dense MFMA peak of the dominant type, and the MFMA
+busy share of the active cycles (busy cycles over GUI-active cycles times the
+256 CUs x 4 SIMDs).
 
 BLOCK_BYTES is the size of the plain copy (k_convert<float,float>) that the
 --calibrate-copy run of bench.py performs: it reads and writes BLOCK_BYTES
@@ -32,9 +42,65 @@ GROUP_KERNELS = {
 
 
 def algorithmic_bytes(group, N, ng, es=4):
+    """Bytes a launch moves when each operand is read or written once (the
+    accept kernel: the four blocks of the Barzilai-Borwein traces plus the
+    write of the new iterate into the caller's block)."""
     B = N * ng * es
     return {"trial": 3 * B, "apply_gram": B, "apply": 2 * B + 8 * ng,
             "hamiltonian": 2 * B + es * ng, "commit": 5 * B}[group]
+
+
+PEAK_TFLOPS = {"BF16": 2500.0, "F32": 157.3, "F64": 78.6}
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                 "SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def mfma_summary(counter_csv, trace_csv, min_flops=1e9):
+    """Per kernel: mean counters per dispatch, traced mean duration, MFMA FLOPs,
+    achieved TFLOP/s and fraction of the peak of the type with most FLOPs."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(counter_csv)):
+        vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        dur[r["Kernel_Name"]].append((float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9)
+    out = {}
+    for k, cs in vals.items():
+        mean = {c: sum(v) / len(v) for c, v in cs.items()}
+        flops = {t: 512.0 * mean.get("SQ_INSTS_VALU_MFMA_MOPS_" + t, 0.0) for t in PEAK_TFLOPS}
+        total = sum(flops.values())
+        if total < min_flops or not dur.get(k):
+            continue
+        d = sorted(dur[k])[len(dur[k]) // 2]  # median traced duration
+        top = max(flops, key=flops.get)
+        busy = mean.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        gui = mean.get("GRBM_GUI_ACTIVE", 0.0)
+        out[k] = {"dispatches": len(next(iter(cs.values()))), "median_us": d * 1e6,
+                  "mfma_flops": flops, "type": top,
+                  "tflops": total / d / 1e12,
+                  "frac_of_peak": flops[top] / d / 1e12 / PEAK_TFLOPS[top],
+                  "busy_share": busy / (gui * 256 * 4) if gui > 0 else None}
+    return out
+
+
+def mfma_markdown(res, title, cmds):
+    out = [f"# MFMA use per kernel from rocprofv3 counters ({title})", "",
+           "Counter run (the program directly after `--`; $REPO: the repository root, "
+           "$OUT: an output directory):", ""]
+    out += ["    " + x for x in cmds]
+    out += ["", "MOPS counters count units of 512 FLOPs.  Rate = FLOPs per dispatch / median "
+                "traced duration of the same run (counter collection can lengthen a kernel, so "
+                "the rate is a lower bound); peak = dense MFMA peak of the dominant type "
+                "(BF16 2.5 PFLOP/s, FP32 157.3, FP64 78.6 TFLOP/s).  Busy share = "
+                "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 256 CUs x 4 SIMDs).", "",
+            "| kernel | dispatches | median us | type | MFMA GFLOP/dispatch | TFLOP/s | frac of peak | busy share |",
+            "|---|---:|---:|---|---:|---:|---:|---:|"]
+    for k, r in sorted(res.items(), key=lambda kv: -sum(kv[1]["mfma_flops"].values())):
+        b = "" if r["busy_share"] is None else f"{r['busy_share']:.3f}"
+        out.append(f"| `{short(k)}` | {r['dispatches']} | {r['median_us']:.1f} | {r['type']} | "
+                   f"{sum(r['mfma_flops'].values()) / 1e9:.2f} | {r['tflops']:.1f} | "
+                   f"{r['frac_of_peak']:.3f} | {b} |")
+    return "\n".join(out) + "\n"
 
 
 def source_sha(name):
@@ -111,6 +177,19 @@ def markdown(res, cmds):
 
 
 def main():
+    if "--mfma" in sys.argv:
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--mfma", nargs=2, metavar=("COUNTER_CSV", "TRACE_CSV"))
+        ap.add_argument("--md")
+        ap.add_argument("--title", default="")
+        ap.add_argument("--cmd", action="append", default=[])
+        a = ap.parse_args()
+        res = mfma_summary(*a.mfma)
+        if a.md:
+            open(a.md, "w").write(mfma_markdown(res, a.title, a.cmd))
+        else:
+            json.dump(res, sys.stdout, indent=1)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("fetch")
     ap.add_argument("write")

@@ -72,12 +72,39 @@ def stencil_magnitude(U, h):
     return np.maximum(_apply_symbol(a, _abs_symbol(n, h)), 0.0)
 
 
+def _kin_symbol_weights(n, c, mh):
+    th = 2.0 * np.pi * np.arange(n) / n
+    return mh * sum(c[m - 1] * (2.0 * np.cos(m * th) - 2.0) for m in range(1, 5))
+
+
+def kinetic_weight_shift(U, occ, h):
+    """|E_kin with FP32-rounded stencil weights - E_kin|: an FP32 stencil
+    applies K with each weight c_m (m = 1..4, difference form) and the factor
+    -1/(2 h^2) rounded to FP32, a systematic change of the operator that the
+    random-rounding model does not cover."""
+    n = U.shape[-1]
+    c = (8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0)
+    mh = -0.5 * (1.0 / (h * h))
+    c32 = tuple(float(np.float32(x)) for x in c)
+    mh32 = float(np.float32(mh))
+    s_exact = _kin_symbol_weights(n, c, mh)
+    s_32 = _kin_symbol_weights(n, c32, mh32)
+    tot = 0.0
+    for i0 in range(0, U.shape[0], 16):
+        u = np.asarray(U[i0:i0 + 16], dtype=np.float64)
+        d = _apply_symbol(u, s_32 - s_exact)
+        f = np.asarray(occ[i0:i0 + 16], dtype=np.float64)
+        tot += float(np.sum(f * h ** 3 * np.sum(u * d, axis=(-3, -2, -1))))
+    return abs(tot)
+
+
 def kinetic_energy_tolerance(U, occ, h, ops=12):
-    """Bound on |E_kin(FP32 stencil) - E_kin(exact)| for the FP32 block U: per
-    point the kinetic value carries at most ops * U32 * A_g (the depth of the
-    stencil's sum tree with its subtractions) and its product with u_g, the
-    FP32 sum of a thread's four points and the product rounding add 3 U32
-    |u_g K u_g|; each term enters E_kin with weight f_i h^3."""
+    """Bound on |E_kin(FP32 stencil) - E_kin(exact)| for the FP32 block U: the
+    systematic shift of the FP32-rounded weights, plus the random rounding:
+    per point the kinetic value carries at most ops * U32 * A_g (the depth of
+    the stencil's sum tree with its subtractions) and its product with u_g,
+    the FP32 sum of a thread's four points and the product rounding add
+    3 U32 |u_g K u_g|; each term enters E_kin with weight f_i h^3."""
     h3 = h ** 3
     n = U.shape[-1]
     tot = 0.0
@@ -88,7 +115,7 @@ def kinetic_energy_tolerance(U, occ, h, ops=12):
         f = np.asarray(occ[i0:i0 + 16], dtype=np.float64)[:, None, None, None]
         e = f * h3 * np.abs(u) * (ops * A + 3.0 * ku) * U32
         tot += float(np.sum(e * e))
-    return LAM * np.sqrt(tot)
+    return LAM * np.sqrt(tot) + kinetic_weight_shift(U, occ, h)
 
 
 def gram_tolerance(X, h, chunk, u=UBF):
