@@ -27,6 +27,13 @@ def kinetic_matrix(n, h):
     return ks.kinetic(E, h).reshape(ng, ng).T
 
 
+def nonlocal_matrix(sys: ks.System):
+    """Dense V_nloc (section 2.1), Ng x Ng: (V u)_g = sum_l xi_l(g) h^3 sum_g'
+    xi_l(g') u_g', i.e. the matrix h^3 Xi^T Xi of the projector rows."""
+    Xi = ks.projectors(sys).reshape(-1, sys.n ** 3)
+    return sys.h ** 3 * (Xi.T @ Xi)
+
+
 def lowest_eigs(Hmat, k):
     w, v = scipy.linalg.eigh(Hmat, subset_by_index=[0, k])
     return w, v
@@ -40,6 +47,8 @@ def linear_minimum(sys: ks.System, vext=None):
     H = kinetic_matrix(n, h)
     if sys.terms & ks.TERM_EXT:
         H = H + np.diag(vext.reshape(-1))
+    if ks.nonlocal_active(sys):
+        H = H + nonlocal_matrix(sys)
     N = sys.norb
     w, _ = lowest_eigs(H, N)
     return float(np.sum(sys.occ * w[:N])), w

@@ -30,6 +30,12 @@ Potentials:
   * Correlation, opt in with TERM_CORR (the LDA of section 4 cites the
     Perdew-Zunger parametrisation): E_c = h^3 sum rho eps_c(r_s), v_c =
     d(rho eps_c)/d rho, spin-unpolarised; see correlation_density().
+  * Nonlocal pseudopotential, opt in with TERM_NLOC (section 2.1: the nonlocal
+    part V_nloc u = sum_l <xi_l, u> xi_l over projectors xi_l in L^2): here
+    four atom-centred Gaussian projectors per ion, one s-type and three p-type,
+        xi_s(r) = b_s exp(-d^2 / (2 rc^2)),  xi_a(r) = b_p (d_a / rc) exp(-d^2 / (2 rc^2)),
+    d = r - R_I by minimum image, with (rc, b_s, b_p) per ion (System.proj).
+    It adds E_nl = sum_i f_i sum_l <xi_l, u_i>^2 to E and V_nloc u_i to H u_i.
 
 Parity: every function here is pinned by CPU tests (closed forms, continuum
 limits, brute force, finite differences); see tests/test_oracle_ks.py.
@@ -47,6 +53,8 @@ TERM_KIN, TERM_EXT, TERM_HARTREE, TERM_XC = 1, 2, 4, 8
 TERM_ALL = TERM_KIN | TERM_EXT | TERM_HARTREE | TERM_XC
 # LDA correlation (Perdew-Zunger form, spin-unpolarised): opt in, not part of TERM_ALL
 TERM_CORR = 16
+# nonlocal projectors (section 2.1 V_nloc): opt in, needs System.proj
+TERM_NLOC = 32
 
 CX = 0.75 * (3.0 / np.pi) ** (1.0 / 3.0)
 VX = (3.0 / np.pi) ** (1.0 / 3.0)
@@ -61,6 +69,7 @@ class System:
     sigma: np.ndarray      # [M]
     occ: np.ndarray        # [N]
     terms: int = TERM_ALL
+    proj: object = None    # [M, 3] (rc, b_s, b_p) per ion for TERM_NLOC, else None
 
     @property
     def h(self):
@@ -150,6 +159,75 @@ def external_potential(sys: System):
     return -poisson(ion_density(sys), sys.h)
 
 
+def _ion_offsets(sys: System, I):
+    n = sys.n
+    dx, dy, dz = grid_offsets(n, sys.L, sys.R[I])
+    X = np.broadcast_to(dx[None, None, :], (n, n, n))
+    Y = np.broadcast_to(dy[None, :, None], (n, n, n))
+    Zc = np.broadcast_to(dz[:, None, None], (n, n, n))
+    return X, Y, Zc
+
+
+def projectors(sys: System):
+    """The nonlocal projectors xi_l on the grid, [4 M, n, n, n]: for ion I rows
+    4I (s-type) and 4I + 1 + a (p-type along axis a = x, y, z)."""
+    M = len(sys.Z)
+    n = sys.n
+    Xi = np.zeros((4 * M, n, n, n))
+    for I in range(M):
+        rc, bs, bp = sys.proj[I]
+        X, Y, Zc = _ion_offsets(sys, I)
+        g = np.exp(-(X * X + Y * Y + Zc * Zc) / (2.0 * rc * rc))
+        Xi[4 * I] = bs * g
+        for a, D in enumerate((X, Y, Zc)):
+            Xi[4 * I + 1 + a] = bp * (D / rc) * g
+    return Xi
+
+
+def projector_derivatives(sys: System):
+    """d xi_l / d R_{I,a} for the projectors of each ion, [M, 4, 3, n, n, n]
+    (the ion position enters through d = r - R_I, so d/dR = -d/dd)."""
+    M = len(sys.Z)
+    n = sys.n
+    out = np.zeros((M, 4, 3, n, n, n))
+    for I in range(M):
+        rc, bs, bp = sys.proj[I]
+        D = _ion_offsets(sys, I)
+        g = np.exp(-(D[0] ** 2 + D[1] ** 2 + D[2] ** 2) / (2.0 * rc * rc))
+        for a in range(3):
+            # d g / d d_a = -(d_a / rc^2) g
+            dg = -(D[a] / (rc * rc)) * g
+            out[I, 0, a] = -bs * dg
+            for b in range(3):
+                dxi = bp * (D[b] / rc) * dg + (bp / rc * g if a == b else 0.0)
+                out[I, 1 + b, a] = -dxi
+    return out
+
+
+def nonlocal_active(sys: System):
+    return bool(sys.terms & TERM_NLOC) and sys.proj is not None and len(sys.Z) > 0
+
+
+def nonlocal_overlaps(U, Xi, h):
+    """C[l, i] = <xi_l, u_i>."""
+    P = Xi.shape[0]
+    N = U.shape[0]
+    return h ** 3 * (Xi.reshape(P, -1) @ U.reshape(N, -1).T)
+
+
+def nonlocal_apply(U, Xi, h):
+    """V_nloc u_i = sum_l <xi_l, u_i> xi_l for every orbital."""
+    C = nonlocal_overlaps(U, Xi, h)
+    P = Xi.shape[0]
+    return (C.T @ Xi.reshape(P, -1)).reshape(U.shape)
+
+
+def nonlocal_energy(U, Xi, sys: System):
+    """E_nl = sum_i f_i <u_i, V_nloc u_i> = sum_i f_i sum_l <xi_l, u_i>^2."""
+    C = nonlocal_overlaps(U, Xi, sys.h)
+    return float(np.sum(sys.occ[None, :] * C * C))
+
+
 # ---------------------------------------------------------------- density, XC
 
 def density(U, occ):
@@ -210,6 +288,7 @@ class EnergyTerms:
     E_H: float
     E_x: float
     E_c: float = 0.0
+    E_nl: float = 0.0
 
 
 def potentials(U, sys: System, vext=None):
@@ -243,24 +322,30 @@ def energy(U, sys: System, vext=None) -> EnergyTerms:
         ekin = float(np.sum(sys.occ * inner(U, kinetic(U, h), h)))
     eext = float(inner(rho, vext, h)) if sys.terms & TERM_EXT else 0.0
     eh = float(0.5 * inner(rho, VH, h)) if sys.terms & TERM_HARTREE else 0.0
-    E = ekin + eext + eh + ex + ec
-    return EnergyTerms(E, ekin, eext, eh, float(ex), float(ec))
+    enl = nonlocal_energy(U, projectors(sys), sys) if nonlocal_active(sys) else 0.0
+    E = ekin + eext + eh + ex + ec + enl
+    return EnergyTerms(E, ekin, eext, eh, float(ex), float(ec), enl)
 
 
 def hamiltonian_apply(U, sys: System, vext=None):
-    """H(rho) u_i = K u_i + V_eff u_i  (section 2.1), rho from U itself."""
+    """H(rho) u_i = K u_i + V_eff u_i (+ V_nloc u_i)  (section 2.1), rho from U itself."""
     _, _, _, veff, _, _, _ = potentials(U, sys, vext)
     out = veff[None] * U
     if sys.terms & TERM_KIN:
         out = out + kinetic(U, sys.h)
+    if nonlocal_active(sys):
+        out = out + nonlocal_apply(U, projectors(sys), sys.h)
     return out
 
 
-def hamiltonian_apply_fixed(U, veff, h, kin=True):
-    """H u for a given V_eff (no density recomputation)."""
+def hamiltonian_apply_fixed(U, veff, h, kin=True, Xi=None):
+    """H u for a given V_eff (no density recomputation); Xi: projectors of
+    the nonlocal term, if any."""
     out = veff[None] * U
     if kin:
         out = out + kinetic(U, h)
+    if Xi is not None:
+        out = out + nonlocal_apply(U, Xi, h)
     return out
 
 
@@ -299,6 +384,15 @@ def forces(U, sys: System):
             dR[I, a] = -inner(VH, g * 2.0 * D / (s * s), h)
         # d rho_I / d s = g * (2 d^2 / s^3 - 3 / s)
         ds[I] = -inner(VH, g * (2.0 * d2 / s ** 3 - 3.0 / s), h)
+    if nonlocal_active(sys):
+        # dE_nl / dR_Ia = sum_i f_i sum_{l of I} 2 <xi_l, u_i> <d xi_l / dR_Ia, u_i>
+        Xi = projectors(sys)
+        C = nonlocal_overlaps(U, Xi, h)
+        dXi = projector_derivatives(sys)
+        for I in range(M):
+            for a in range(3):
+                Cd = nonlocal_overlaps(U, dXi[I, :, a], h)  # [4, N]
+                dR[I, a] += float(np.sum(sys.occ[None, :] * 2.0 * C[4 * I:4 * I + 4] * Cd))
     return dR, ds
 
 
@@ -318,7 +412,13 @@ def energy_and_h(U, sys: System, vext=None):
     ekin = float(np.sum(sys.occ * inner(U, KU, h)))
     eext = float(inner(rho, vext, h)) if sys.terms & TERM_EXT else 0.0
     eh = float(0.5 * inner(rho, VH, h)) if sys.terms & TERM_HARTREE else 0.0
-    terms = EnergyTerms(ekin + eext + eh + ex + ec, ekin, eext, eh, float(ex), float(ec))
     HU = KU + veff[None] * U
+    enl = 0.0
+    if nonlocal_active(sys):
+        Xi = projectors(sys)
+        HU = HU + nonlocal_apply(U, Xi, h)
+        enl = nonlocal_energy(U, Xi, sys)
+    terms = EnergyTerms(ekin + eext + eh + ex + ec + enl, ekin, eext, eh, float(ex), float(ec),
+                        enl)
     sigma = inner(U, HU, h)
     return terms, HU, sigma

@@ -17,6 +17,10 @@ Recipe (all FP64, numpy PCG64):
     minimum-image pair distance is at least that value;
   * charges Z and Gaussian widths sigma as listed per configuration (the
     differentiation case draws Z from {1, 2, 4} and sigma from U[0.4, 0.7]);
+  * nonlocal projector parameters (opt in), seed 3000+cfg: per ion a width
+    rc ~ U[0.45, 0.6] bohr and amplitudes b_s ~ U[1, 2], b_p ~ U[0.5, 1.5] of
+    one s-type and three p-type Gaussian projectors (stand-ins for the
+    Troullier-Martins nonlocal channels of section 4);
   * orbitals, seed 2000+cfg: either i.i.d. N(0, 1) values on the grid, or an
     atom-centred start  u_i = sum_I sum_b c_{iIb} phi_b(r - R_I) exp(-d^2/2)
     with phi_b in {1, dx, dy, dz} and c ~ N(0, 1), a stand-in for the paper's
@@ -142,6 +146,15 @@ def orbitals(cfg: Config, dtype=np.float64):
         B = B.reshape(4 * M, -1)
         U[:, z0:z1] = (C @ B).reshape(N, z1 - z0, n, n).astype(dtype, copy=False)
     return U
+
+
+def projector_params(cfg: Config, rc=(0.45, 0.6), b_s=(1.0, 2.0), b_p=(0.5, 1.5)):
+    """Per-ion parameters (rc, b_s, b_p) of the synthetic nonlocal projectors,
+    [M, 3], drawn uniformly from the given ranges with seed 3000+cfg."""
+    rng = np.random.default_rng(3000 + cfg.cfg_id)
+    M = cfg.natoms
+    return np.stack([rng.uniform(*rc, size=M), rng.uniform(*b_s, size=M),
+                     rng.uniform(*b_p, size=M)], axis=1)
 
 
 def random_direction(shape, seed):

@@ -371,3 +371,20 @@ def test_nonmonotone_reference_matches_closed_form(eta):
             assert rec.C == rec.E
         if eta == 1.0:
             assert abs(rec.C - np.mean(E)) < 1e-12 * abs(rec.C)
+
+
+def test_linear_problem_with_nonlocal_projectors_reaches_dense_minimum():
+    """K + V_ext + V_nloc on a 10^3 grid: Algorithm M reaches the sum of the
+    lowest eigenvalues of the dense matrix (V_nloc built as h^3 Xi^T Xi)."""
+    cfg = synth.custom("tnl", 10, 6.0, 2, (1.0, 2.0), (0.45, 0.7), 2, seed_id=9)
+    R, Z, s = synth.atoms(cfg)
+    sys_ = ks.System(10, 6.0, R, Z, s, synth.occupations(cfg),
+                     ks.TERM_KIN | ks.TERM_EXT | ks.TERM_NLOC, proj=synth.projector_params(cfg))
+    Emin, w = dense.linear_minimum(sys_)
+    E0, _ = dense.linear_minimum(ks.System(10, 6.0, R, Z, s, synth.occupations(cfg),
+                                           ks.TERM_KIN | ks.TERM_EXT))
+    assert Emin > E0 + 1e-3  # the projectors are repulsive and felt
+    assert w[2] - w[1] > 1e-2
+    A = algm.AlgorithmM(synth.orbitals(cfg), sys_)
+    A.run(4000, tol=1e-15)
+    assert abs(A.E - Emin) < 1e-10

@@ -261,3 +261,68 @@ def test_correlation_fit_has_a_continuous_slope_at_rs_one():
     assert left > 0.0 and right > 0.0
     e = _eps_c_of_rs(np.array([1.0 - 1e-12, 1.0 + 1e-12]))
     assert abs(e[0] - e[1]) < 5e-5
+
+
+# ---- nonlocal projectors (section 2.1, V_nloc u = sum_l <xi_l, u> xi_l)
+
+def _one_ion_nloc(n=48, L=8.0, rc=0.5, bs=1.7, bp=1.2, R=(3.1, 4.4, 2.6)):
+    return ks.System(n, L, np.array([R]), np.array([1.0]), np.array([0.5]), np.array([2.0]),
+                     ks.TERM_ALL | ks.TERM_NLOC, proj=np.array([[rc, bs, bp]]))
+
+
+def test_projector_norms_orthogonality_and_centre():
+    """Closed forms of the continuum Gaussians (the grid sums converge
+    exponentially for these widths): <xi_s, xi_s> = b_s^2 (pi rc^2)^(3/2),
+    <xi_a, xi_a> = b_p^2 / 2 (pi rc^2)^(3/2), the four projectors mutually
+    orthogonal, centred on the ion; and V_nloc xi_s = <xi_s, xi_s> xi_s."""
+    rc, bs, bp = 0.5, 1.7, 1.2
+    so = _one_ion_nloc(rc=rc, bs=bs, bp=bp)
+    Xi = ks.projectors(so)
+    h = so.h
+    G = h ** 3 * Xi.reshape(4, -1) @ Xi.reshape(4, -1).T
+    vol = (np.pi * rc * rc) ** 1.5
+    want = np.diag([bs * bs * vol] + [bp * bp * vol / 2.0] * 3)
+    assert np.max(np.abs(G - want)) < 1e-12 * bs * bs * vol
+    ax = h * np.arange(so.n)
+    for a, X in enumerate((ax[None, None, :], ax[:, None, None] * 0 + ax[None, :, None],
+                           ax[:, None, None])):
+        cen = float(h ** 3 * np.sum(Xi[0] ** 2 * np.broadcast_to(X, Xi[0].shape))) / G[0, 0]
+        assert abs(cen - so.R[0][a]) < 1e-10
+    V = ks.nonlocal_apply(Xi[:1], Xi, h)
+    assert np.max(np.abs(V[0] - G[0, 0] * Xi[0])) < 1e-12 * G[0, 0] * bs
+
+
+def test_nonlocal_energy_gradient_matches_central_differences():
+    cfg = synth.custom("nl", 12, 6.0, 2, 2.0, 0.5, 2, seed_id=61)
+    R, Z, s = synth.atoms(cfg)
+    so = ks.System(cfg.n, cfg.L, R, Z, s, synth.occupations(cfg), ks.TERM_ALL | ks.TERM_NLOC,
+                   proj=synth.projector_params(cfg))
+    U = synth.orbitals(cfg) * 0.1
+    G = ks.energy_gradient(U, so)
+    D = synth.random_direction(U.shape, 62)
+    eps = 1e-5
+    fd = (ks.energy(U + eps * D, so).E - ks.energy(U - eps * D, so).E) / (2 * eps)
+    assert abs(fd - float(np.sum(G * D))) < 1e-8 * abs(fd)
+    # the nonlocal term alone, so a wrong factor in it cannot hide behind the others
+    Xi = ks.projectors(so)
+    enl = lambda V: ks.nonlocal_energy(V, Xi, so)
+    fd = (enl(U + eps * D) - enl(U - eps * D)) / (2 * eps)
+    gnl = 2.0 * so.occ[:, None, None, None] * so.dv * ks.nonlocal_apply(U, Xi, so.h)
+    assert abs(fd - float(np.sum(gnl * D))) < 1e-8 * abs(fd)
+    assert enl(U) > 0.0
+
+
+def test_nonlocal_forces_match_central_differences():
+    cfg = synth.custom("nlf", 12, 6.0, 2, 2.0, 0.5, 2, seed_id=63)
+    R, Z, s = synth.atoms(cfg)
+    pp = synth.projector_params(cfg)
+    mk = lambda RR: ks.System(cfg.n, cfg.L, RR, Z, s, synth.occupations(cfg),
+                              ks.TERM_ALL | ks.TERM_NLOC, proj=pp)
+    U = synth.orbitals(cfg) * 0.1
+    dR, _ = ks.forces(U, mk(R))
+    hstep = 1e-4
+    for I, a in ((0, 0), (1, 2), (0, 1)):
+        Rp = R.copy(); Rp[I, a] += hstep
+        Rm = R.copy(); Rm[I, a] -= hstep
+        fd = (ks.energy(U, mk(Rp)).E - ks.energy(U, mk(Rm)).E) / (2 * hstep)
+        assert abs(fd - dR[I, a]) < 1e-7 * max(1.0, abs(fd)), (I, a, fd, dR[I, a])
