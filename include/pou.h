@@ -222,6 +222,22 @@ pou_status pou_gram(pou_ctx *ctx, const void *U, int mode, double *G);
    state is kept. */
 pou_status pou_trial_point(pou_ctx *ctx, const void *U, double tau, void *Wt, double *G);
 
+/* Gram matrix without a context and without any allocation, for callers
+   that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): the same product as
+   pou_gram, G = dv * U U^T (dv = h^3), by the same kernels, written to the
+   DEVICE buffer G (double [norb][norb], full symmetric) on hip_stream
+   (a hipStream_t, NULL for the null stream).  U: device block [norb][ng] of
+   doubles (prec POU_FP64) or floats (POU_MIXED); mode as in pou_gram.
+   Limits: 1 <= norb <= 128, ng >= norb, dv > 0 (else POU_ERR_ARG; no message,
+   since there is no context).  The partial sums live in a static device array
+   of 32 MiB (256 splits of 128 x 128 doubles) that each GPU holds from the
+   first call on it until the process ends; calls that overlap on one GPU (on
+   different streams) race on it.  The call only enqueues work: G is ready
+   when the stream reaches it.  POU_ERR_HIP if a launch fails. */
+pou_status pou_gram_static(const void *U, int prec, int mode, int norb, long long ng, double dv,
+                           double *G, void *hip_stream);
+
 /* Element-type conversion of a block of count elements between FP32 and
    FP64 device buffers (src_prec, dst_prec in {POU_FP64, POU_MIXED}). */
 pou_status pou_convert(pou_ctx *ctx, const void *src, int src_prec, void *dst,

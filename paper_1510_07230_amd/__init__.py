@@ -80,6 +80,7 @@ _SIGNATURES = {
     "pou_get_fields": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "pou_gram": (_i, [_vp, _vp, _i, _dp]),
     "pou_trial_point": (_i, [_vp, _vp, _d, _vp, _dp]),
+    "pou_gram_static": (_i, [_vp, _i, _i, _i, ctypes.c_longlong, _d, _vp, _vp]),
     "pou_convert": (_i, [_vp, _vp, _i, _vp, _i, ctypes.c_longlong]),
     "pou_reset_history": (_i, [_vp]),
     "pou_profile_enable": (_i, [_vp, ctypes.c_uint]),
@@ -322,6 +323,27 @@ class System:
             self._check(lib().pou_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
             out[name] = (ms.value, n.value)
         return out
+
+
+def gram_static(U, dv, bf16=False, out=None, stream=None):
+    """pou_gram_static: dv * U U^T of a device block U ([N, ...], float64 or
+    float32, N <= 128) into a device [N, N] float64 tensor, with no context
+    and no allocation inside the library (out is allocated here if None)."""
+    import torch
+    if not U.is_cuda or not U.is_contiguous() or U.dtype not in (torch.float64, torch.float32):
+        raise ValueError("U must be a contiguous float64/float32 device tensor")
+    N = U.shape[0]
+    ng = U.numel() // N
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.float64, device=U.device)
+    s = stream if stream is not None else torch.cuda.current_stream(U.device)
+    prec = FP64 if U.dtype == torch.float64 else MIXED
+    rc = lib().pou_gram_static(ctypes.c_void_p(U.data_ptr()), prec,
+                               GRAM_BF16 if bf16 else GRAM_ACCURATE, N, ng, float(dv),
+                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+    if rc != POU_OK:
+        raise PouError(rc, "pou_gram_static failed")
+    return out
 
 
 def _energy_fn():

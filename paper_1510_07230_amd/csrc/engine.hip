@@ -18,6 +18,7 @@
 #include <cstring>
 #include <iterator>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1074,6 +1075,37 @@ pou_status trial_point_impl(pou_ctx *c, const T *U, double tau, T *Wt, double *G
   return POU_OK;
 }
 
+// ---------------------------------------------------------------- non-allocating Gram
+//
+// Scratch of pou_gram_static: the Gram partials [kStaticSplits][128][128] of
+// up to 128 orbitals, 32 MiB per device, held until the process ends.  In host
+// code `scratch` names a host-side stand-in: kernels get the device address
+// that hipGetSymbolAddress returns on each device.
+constexpr int kStaticSplits = 256;
+constexpr int kStaticMaxOrb = 128;
+static __device__ __align__(256) double scratch[(size_t)kStaticSplits * 128 * 128];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved once per device).
+hipError_t scratch_address(double **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1375,6 +1407,36 @@ pou_status pou_trial_point(pou_ctx *c, const void *U, double tau, void *Wt, doub
   if (c->prec == POU_FP64)
     return trial_point_impl<double>(c, (const double *)U, tau, (double *)Wt, G);
   return trial_point_impl<float>(c, (const float *)U, tau, (float *)Wt, G);
+}
+
+pou_status pou_gram_static(const void *U, int prec, int mode, int norb, long long ng, double dv,
+                           double *G, void *hip_stream) {
+  if (!U || !G) return POU_ERR_ARG;
+  if (prec != POU_FP64 && prec != POU_MIXED) return POU_ERR_ARG;
+  if (mode != POU_GRAM_ACCURATE && mode != POU_GRAM_BF16) return POU_ERR_ARG;
+  if (mode == POU_GRAM_BF16 && prec != POU_MIXED) return POU_ERR_ARG;
+  if (norb < 1 || norb > kStaticMaxOrb || ng < norb || !(dv > 0.0) || !std::isfinite(dv))
+    return POU_ERR_ARG;
+  double *part = nullptr;
+  if (scratch_address(&part) != hipSuccess) {
+    (void)hipGetLastError();
+    return POU_ERR_HIP;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nsplit = (int)std::max<i64>(1, std::min<i64>(kStaticSplits, (ng + 31) / 32));
+  hipError_t e;
+  if (prec == POU_FP64)
+    e = pou::launch_gram_partial<double>((const double *)U, norb, ng, nsplit, part, s);
+  else if (mode == POU_GRAM_BF16)
+    e = pou::launch_gram_partial_bf16((const float *)U, norb, ng, nsplit, part, s);
+  else
+    e = pou::launch_gram_partial<float>((const float *)U, norb, ng, nsplit, part, s);
+  if (e == hipSuccess) e = pou::launch_gram_reduce(part, norb, nsplit, dv, G, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return POU_ERR_HIP;
+  }
+  return POU_OK;
 }
 
 pou_status pou_convert(pou_ctx *c, const void *src, int src_prec, void *dst, int dst_prec,
