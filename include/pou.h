@@ -71,7 +71,8 @@ enum {
   POU_TERM_HARTREE = 4,
   POU_TERM_XC = 8,
   POU_TERM_ALL = 15,   /* the default model: exchange-only LDA */
-  POU_TERM_CORR = 16   /* add LDA correlation (not part of POU_TERM_ALL) */
+  POU_TERM_CORR = 16,  /* add LDA correlation (not part of POU_TERM_ALL) */
+  POU_TERM_NLOC = 32   /* nonlocal projectors; switched on by pou_set_projectors */
 };
 
 typedef struct {
@@ -110,6 +111,7 @@ typedef struct {
   double E, E_kin, E_ext, E_H, E_x;
   int cg_iters;     /* iterations of the Hartree solve for this evaluation */
   double E_c;       /* LDA correlation energy (0 unless POU_TERM_CORR) */
+  double E_nl;      /* nonlocal energy sum_i f_i <u_i, V_nloc u_i> (0 without projectors) */
 } pou_energy_terms;
 
 typedef struct {
@@ -149,6 +151,20 @@ pou_status pou_set_system(pou_ctx *ctx, const pou_grid *grid, int natoms,
                           const double *R, const double *Z, const double *sigma,
                           int norb, const double *occ, pou_precision prec,
                           const pou_params *params);
+
+/* Nonlocal part of the pseudopotential (section 2.1): V_nloc u =
+   sum_l <xi_l, u> xi_l with four projectors per ion I centred on R_I,
+     xi_s = b_s g,  xi_a = b_p (d_a / rc) g  (a = x, y, z),
+     g = exp(-|d|^2 / (2 rc^2)),  d = r - R_I (minimum image),
+   params (host double [natoms][3]) = (rc > 0, b_s, b_p) per ion of the last
+   pou_set_system, which this call must follow (pou_set_system clears the
+   projectors).  Adds E_nl = sum_i f_i <u_i, V_nloc u_i> to E, V_nloc u to H u
+   and its derivative to the forces; turns POU_TERM_NLOC on.  params NULL
+   removes the projectors.  Each ion's projectors are evaluated on a cube of
+   grid points reaching past the radius where g < 1e-14 (the whole grid if
+   that does not fit), and nothing outside it.  The library keeps no pointer
+   to params.  POU_ERR_ARG on a bad width or amplitude. */
+pou_status pou_set_projectors(pou_ctx *ctx, const double *params);
 
 /* Total energy E(U) of eq. "energy" for the device block U (not modified).
    Leaves rho, V_H, V_eff and H*U of this U cached in the context. */

@@ -25,6 +25,7 @@ STATUS = {0: "POU_OK", -1: "POU_ERR_ARG", -2: "POU_ERR_STATE", -3: "POU_ERR_HIP"
 FP64, MIXED = 0, 1
 TERM_KIN, TERM_EXT, TERM_HARTREE, TERM_XC, TERM_ALL = 1, 2, 4, 8, 15
 TERM_CORR = 16  # LDA correlation, opt in
+TERM_NLOC = 32  # nonlocal projectors, switched on by set_projectors
 GRAM_ACCURATE, GRAM_BF16 = 0, 1
 
 
@@ -50,7 +51,7 @@ class Params(ctypes.Structure):
 class EnergyTerms(ctypes.Structure):
     _fields_ = [("E", ctypes.c_double), ("E_kin", ctypes.c_double), ("E_ext", ctypes.c_double),
                 ("E_H", ctypes.c_double), ("E_x", ctypes.c_double), ("cg_iters", ctypes.c_int),
-                ("E_c", ctypes.c_double)]
+                ("E_c", ctypes.c_double), ("E_nl", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -72,6 +73,7 @@ _SIGNATURES = {
     "pou_set_system": (_i, [_vp, ctypes.POINTER(Grid), _i, _dp, _dp, _dp, _i, _dp, _i,
                             ctypes.POINTER(Params)]),
     "pou_energy": (_i, [_vp, _vp, ctypes.POINTER(EnergyTerms)]),
+    "pou_set_projectors": (_i, [_vp, _dp]),
     "pou_residual": (_i, [_vp, _vp, _dp, _dp]),
     "pou_orthonormalize": (_i, [_vp, _vp, _dp]),
     "pou_orbital_update_step": (_i, [_vp, _vp, ctypes.POINTER(StepInfo)]),
@@ -137,7 +139,7 @@ class System:
     """
 
     def __init__(self, n, L, R, Z, sigma, occ, precision="fp64", params=None, device=0,
-                 stream=None):
+                 stream=None, proj=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -154,6 +156,7 @@ class System:
         if rc != POU_OK:
             raise PouError(rc, "pou_create failed")
         self._h = h
+        self.proj = None if proj is None else np.ascontiguousarray(np.asarray(proj, np.float64))
         self.set_system(R, Z, sigma, occ)
 
     def _stream_handle(self):
@@ -178,6 +181,17 @@ class System:
         self._check(lib().pou_set_system(self._h, ctypes.byref(g), self.M, _dptr(R), _dptr(Z),
                                          _dptr(sigma), self.N, _dptr(occ), self.prec,
                                          ctypes.byref(self.params)))
+        if getattr(self, "proj", None) is not None:
+            self.set_projectors(self.proj)
+
+    def set_projectors(self, proj):
+        """Nonlocal projectors (section 2.1): proj [M, 3] = (rc, b_s, b_p) per
+        ion, or None to remove them.  Kept across set_system calls."""
+        self.proj = None if proj is None else np.ascontiguousarray(np.asarray(proj, np.float64))
+        if self.proj is not None and self.proj.shape != (self.M, 3):
+            raise ValueError("proj must be [natoms, 3]")
+        ptr = _dptr(self.proj) if self.proj is not None else None
+        self._check(lib().pou_set_projectors(self._h, ptr))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -212,7 +226,7 @@ class System:
         t = EnergyTerms()
         self._check(lib().pou_energy(self._h, self._block(U), ctypes.byref(t)))
         return {"E": t.E, "E_kin": t.E_kin, "E_ext": t.E_ext, "E_H": t.E_H, "E_x": t.E_x,
-                "E_c": t.E_c, "cg_iters": t.cg_iters}
+                "E_c": t.E_c, "E_nl": t.E_nl, "cg_iters": t.cg_iters}
 
     @staticmethod
     def _written(t):

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpou.so")
-SOURCES = ["grid_kernels.hip", "dense_kernels.hip", "engine.hip"]
+SOURCES = ["grid_kernels.hip", "dense_kernels.hip", "nonlocal_kernels.hip", "engine.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

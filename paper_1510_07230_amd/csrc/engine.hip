@@ -28,12 +28,14 @@ namespace {
 
 struct Report {
   // device layout of one evaluation report:
-  // [sigma N | kin N | e4 | orth info 2*kMaxPass | Poisson rr, bb]
-  // e4 = (sum rho^(4/3), sum rho V_ext, sum rho V_H, sum rho eps_c) * h^3
+  // [sigma N | kin N | e4 | orth info 2*kMaxPass | Poisson rr, bb | E_nl]
+  // e4 = (sum rho^(4/3), sum rho V_ext, sum rho V_H, sum rho eps_c) * h^3,
+  // E_nl = sum_i f_i <u_i, V_nloc u_i> (zero without projectors)
   static constexpr int kMaxPass = 4;
   static int orth(int N) { return 2 * N + 4; }
-  static int size(int N) { return 2 * N + 4 + 2 * kMaxPass + 2; }
+  static int size(int N) { return 2 * N + 4 + 2 * kMaxPass + 3; }
   static int rr(int N) { return 2 * N + 4 + 2 * kMaxPass; }
+  static int nl(int N) { return rr(N) + 2; }
 };
 
 // Every admitted grid (9 <= n <= 1024) gets at least one FFT line per
@@ -100,6 +102,18 @@ struct pou_ctx {
   double *d_red = nullptr;     // small reduction outputs
   double *d_S = nullptr, *d_P = nullptr, *d_xpart = nullptr;  // subspace rotation / residual
   double *d_scal = nullptr;    // (tau_BB, zz, ss, sy, yy) of the current step
+  // nonlocal projectors (section 2.1 V_nloc), set by pou_set_projectors
+  bool nl_on = false;
+  int nl_bmax = 0;
+  std::vector<pou::NlIon> nl_ions;
+  std::vector<int> nl_col_off, nl_col_cnt;  // colours: ranges of d_nl_list
+  pou::NlIon *d_nl = nullptr;
+  int *d_nl_list = nullptr;
+  double *d_nlpart = nullptr;  // overlap partials [M][splits][N][12]
+  double *d_nlC = nullptr;     // <xi_l, u_i> of the last evaluation [4M][N]
+  double *d_nlC2 = nullptr;    // the same for pou_hamiltonian_apply
+  double *d_nlD = nullptr;     // derivative overlaps [M][12][N] (forces)
+  std::vector<void *> nl_allocs;
   double *d_diag = nullptr;    // step size of a pou_trial_point call
   double *d_rep[2] = {nullptr, nullptr};  // evaluation reports (current, trial)
   void *d_HW = nullptr, *d_HWt = nullptr, *d_Wt = nullptr, *d_W1 = nullptr, *d_W2 = nullptr;
@@ -186,6 +200,14 @@ void free_all(pou_ctx *c) {
   c->d_red = nullptr;
   c->d_S = c->d_P = c->d_xpart = nullptr;
   c->d_scal = nullptr;
+  c->d_diag = nullptr;
+  for (void *p : c->nl_allocs) (void)hipFree(p);
+  c->nl_allocs.clear();
+  c->nl_on = false;
+  c->nl_ions.clear();
+  c->d_nl = nullptr;
+  c->d_nl_list = nullptr;
+  c->d_nlpart = c->d_nlC = c->d_nlC2 = c->d_nlD = nullptr;
   c->d_D64 = nullptr;
   c->d_D32 = nullptr;
   c->d_fsplit = nullptr;
@@ -352,6 +374,26 @@ pou_status poisson_async(pou_ctx *c, const double *f, double *x, double *rrbb) {
 
 // ------------------------------------------------------------------ energy
 
+bool nl_active(const pou_ctx *c) { return c->nl_on && (c->p.terms & POU_TERM_NLOC); }
+
+// V_nloc of section 2.1 added to H W: the overlaps C = <xi_l, w_i> into C,
+// sigma_ii (rep[0..N)) += sum_l C_li^2, rep[enl_off] = sum_i f_i sum_l C_li^2,
+// then H w_i += sum_l C_li xi_l colour by colour.
+template <typename T>
+pou_status nonlocal_h(pou_ctx *c, const T *W, T *HW, double *C, double *rep, int enl_off) {
+  hipStream_t s = c->stream;
+  const int M = (int)c->nl_ions.size();
+  KL(POU_K_HAMILTONIAN, pou::launch_nl_overlap<T>(W, c->d_nl, M, c->nl_bmax, c->N, c->n, c->L,
+                                                  false, c->d_nlpart, s));
+  KL(POU_K_OTHER, pou::launch_nl_finish(c->d_nlpart, M, c->nl_bmax, c->N, c->dv, c->d_occ, C,
+                                        rep, enl_off, s));
+  for (size_t k = 0; k < c->nl_col_off.size(); ++k)
+    KL(POU_K_HAMILTONIAN, pou::launch_nl_apply<T>(HW, c->d_nl, c->d_nl_list + c->nl_col_off[k],
+                                                  c->nl_col_cnt[k], c->nl_bmax, C, c->N, c->n,
+                                                  c->L, s));
+  return POU_OK;
+}
+
 // V_eff, H W and the energy partials of W for the current rho and V_H; the
 // report (sigma, kin, energy sums) lands in rep on the device.
 template <typename T>
@@ -365,6 +407,7 @@ pou_status potentials_and_h(pou_ctx *c, const T *W, T *HWout, double *rep) {
   const T *veff = sizeof(T) == 4 ? (const T *)c->d_veff32 : (const T *)c->d_veff;
   KL(POU_K_HAMILTONIAN, pou::launch_hamiltonian<T>(W, veff, HWout, c->d_part, N, c->st, s));
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, rep, N, c->st.ntile * c->st.nzc, 2, c->dv, s));
+  if (nl_active(c)) CHK(nonlocal_h<T>(c, W, HWout, c->d_nlC, rep, Report::nl(N)));
   return POU_OK;
 }
 
@@ -438,7 +481,8 @@ void terms_from_report(const pou_ctx *c, const double *rep, pou_energy_terms *t)
   t->E_ext = (c->p.terms & POU_TERM_EXT) ? eext : 0.0;
   t->E_H = (c->p.terms & POU_TERM_HARTREE) ? eh : 0.0;
   t->E_c = (c->p.terms & POU_TERM_CORR) ? rep[2 * N + 3] : 0.0;
-  t->E = t->E_kin + t->E_x + t->E_ext + t->E_H + t->E_c;
+  t->E_nl = (c->p.terms & POU_TERM_NLOC) ? rep[Report::nl(N)] : 0.0;
+  t->E = t->E_kin + t->E_x + t->E_ext + t->E_H + t->E_c + t->E_nl;
   t->cg_iters = c->last_cg_iters;
 }
 
@@ -674,6 +718,9 @@ pou_status rotate_subspace(pou_ctx *c, T *W) {
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 1, c->dv, s));
   KL(POU_K_OTHER, pou::launch_bb_tau(c->d_red, N, 3, c->p.tau_init, c->d_scal, nullptr, s));
   c->eval_HU = c->d_HW;
+  // the projector overlaps of the last evaluation belong to the unrotated
+  // iterate: a backward pass re-evaluates the rotated one
+  if (nl_active(c)) c->eval_ptr = nullptr;
   return POU_OK;
 }
 
@@ -1014,6 +1061,25 @@ pou_status backward_impl(pou_ctx *c, const T *U, double gE, T *dU, double *dR, d
       for (int a = 0; a < 3; ++a) R[3 * I + a] = f[a * c->M + I];
       S[I] = f[3 * c->M + I];
     }
+    if (nl_active(c) && dR) {
+      // dE_nl/dR_Ia = sum_i f_i sum_l 2 <xi_l, u_i> <d xi_l / dR_Ia, u_i>
+      const int M = c->M, N = c->N;
+      KL(POU_K_OTHER, pou::launch_nl_overlap<T>(U, c->d_nl, M, c->nl_bmax, N, c->n, c->L, true,
+                                                c->d_nlpart, s));
+      KL(POU_K_OTHER, pou::launch_nl_sum_deriv(c->d_nlpart, M, c->nl_bmax, N, c->dv, c->d_nlD, s));
+      std::vector<double> Ch((size_t)4 * M * N), Dh((size_t)12 * M * N);
+      CHK(sync_read(c, Ch.data(), c->d_nlC, sizeof(double) * Ch.size()));
+      CHK(sync_read(c, Dh.data(), c->d_nlD, sizeof(double) * Dh.size()));
+      for (int I = 0; I < M; ++I)
+        for (int a = 0; a < 3; ++a) {
+          double acc = 0.0;
+          for (int l = 0; l < 4; ++l)
+            for (int i = 0; i < N; ++i)
+              acc += c->occ[i] * 2.0 * Ch[(size_t)(4 * I + l) * N + i] *
+                     Dh[((size_t)I * 12 + 3 * l + a) * N + i];
+          R[3 * I + a] += gE * acc;
+        }
+    }
     if (dR) HIPCHK(c, hipMemcpyAsync(dR, R.data(), sizeof(double) * R.size(),
                                      hipMemcpyHostToDevice, s));
     if (dsig) HIPCHK(c, hipMemcpyAsync(dsig, S.data(), sizeof(double) * S.size(),
@@ -1031,6 +1097,7 @@ pou_status hamiltonian_impl(pou_ctx *c, const T *U, T *HU, double *sigma) {
   KL(POU_K_HAMILTONIAN, pou::launch_hamiltonian<T>(U, veff, HU, c->d_part, c->N, c->st, s));
   KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, c->N, c->st.ntile * c->st.nzc, 2,
                                     c->dv, s));
+  if (nl_active(c)) CHK(nonlocal_h<T>(c, U, HU, c->d_nlC2, c->d_red, 2 * c->N));
   if (sigma) CHK(sync_read(c, sigma, c->d_red, sizeof(double) * c->N));
   else HIPCHK(c, hipStreamSynchronize(s));
   prof_drain(c);
@@ -1197,7 +1264,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   if (p.n_org <= 0) p.n_org = 1;
   if (!(p.delta > 0.0 && p.delta < 1.0) || !(p.rho1 >= 0.0) || !(p.eta >= 0.0 && p.eta <= 1.0) ||
       p.s_max < 0 || p.s_max > 60 || p.orth_passes > 2 || p.bb_mode < 0 || p.bb_mode > 2 ||
-      !std::isfinite(p.tau_init) || p.n_diag < 0 || (p.terms & ~31u) != 0)
+      !std::isfinite(p.tau_init) || p.n_diag < 0 || (p.terms & ~63u) != 0)
     return fail(c, POU_ERR_ARG, "bad algorithm parameters");
   if (p.n_diag > 0)
     for (int i = 1; i < norb; ++i)
@@ -1330,6 +1397,108 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
     if (!(c)->have_system) return fail((c), POU_ERR_STATE, "call pou_set_system first"); \
     if (hipSetDevice((c)->device) != hipSuccess) return fail((c), POU_ERR_HIP, "hipSetDevice failed"); \
   } while (0)
+
+pou_status pou_set_projectors(pou_ctx *c, const double *params) {
+  NEED_SYSTEM(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->nl_allocs) (void)hipFree(p);
+  c->nl_allocs.clear();
+  c->nl_ions.clear();
+  c->nl_col_off.clear();
+  c->nl_col_cnt.clear();
+  c->nl_on = false;
+  c->d_nl = nullptr;
+  c->d_nl_list = nullptr;
+  c->d_nlpart = c->d_nlC = c->d_nlC2 = c->d_nlD = nullptr;
+  c->p.terms &= ~(unsigned)POU_TERM_NLOC;
+  c->cur_valid = false;  // cached H W no longer describes H
+  c->eval_ptr = nullptr;
+  if (!params || c->M == 0) return POU_OK;
+  const int M = c->M, n = c->n;
+  for (int I = 0; I < M; ++I) {
+    const double rc = params[3 * I], bs = params[3 * I + 1], bp = params[3 * I + 2];
+    if (!(rc > 0.0) || !std::isfinite(rc) || !std::isfinite(bs) || !std::isfinite(bp))
+      return fail(c, POU_ERR_ARG, "projector " + std::to_string(I) + ": bad width or amplitude");
+  }
+  // cube: half width reaching the radius where exp(-r^2 / (2 rc^2)) < 1e-14
+  const double tail = std::sqrt(2.0 * std::log(1e14));
+  c->nl_ions.resize(M);
+  c->nl_bmax = 1;
+  for (int I = 0; I < M; ++I) {
+    pou::NlIon a{};
+    for (int k = 0; k < 3; ++k) a.R[k] = c->atoms[5 * I + k];
+    a.rc = params[3 * I];
+    a.bs = params[3 * I + 1];
+    a.bp = params[3 * I + 2];
+    const int hw = (int)std::ceil(tail * a.rc / c->h);
+    a.b = 2 * hw + 1;
+    for (int k = 0; k < 3; ++k) {
+      if (a.b >= n) {
+        a.o[k] = 0;
+      } else {
+        long long ctr = std::llround(a.R[k] / c->h);
+        a.o[k] = (int)(((ctr - hw) % n + n) % n);
+      }
+    }
+    if (a.b >= n) a.b = n;
+    c->nl_bmax = std::max(c->nl_bmax, a.b);
+    c->nl_ions[I] = a;
+  }
+  // greedy colouring: cubes of one colour share no grid point
+  auto overlap1 = [n](int o1, int b1, int o2, int b2) {
+    return ((o2 - o1) % n + n) % n < b1 || ((o1 - o2) % n + n) % n < b2;
+  };
+  std::vector<int> colour(M, -1);
+  std::vector<std::vector<int>> cols;
+  for (int I = 0; I < M; ++I) {
+    const pou::NlIon &a = c->nl_ions[I];
+    int k = 0;
+    for (; k < (int)cols.size(); ++k) {
+      bool clash = false;
+      for (int J : cols[k]) {
+        const pou::NlIon &b = c->nl_ions[J];
+        if (overlap1(a.o[0], a.b, b.o[0], b.b) && overlap1(a.o[1], a.b, b.o[1], b.b) &&
+            overlap1(a.o[2], a.b, b.o[2], b.b)) {
+          clash = true;
+          break;
+        }
+      }
+      if (!clash) break;
+    }
+    if (k == (int)cols.size()) cols.emplace_back();
+    cols[k].push_back(I);
+  }
+  std::vector<int> list;
+  for (auto &cl : cols) {
+    c->nl_col_off.push_back((int)list.size());
+    c->nl_col_cnt.push_back((int)cl.size());
+    list.insert(list.end(), cl.begin(), cl.end());
+  }
+  auto nalloc = [c](void **p, size_t bytes) -> pou_status {
+    if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, POU_ERR_OOM, "hipMalloc of the projector buffers failed");
+    }
+    c->nl_allocs.push_back(*p);
+    return POU_OK;
+  };
+  const int N = c->N;
+  const size_t nsp = (size_t)pou::nl_splits(c->nl_bmax);
+  CHK(nalloc((void **)&c->d_nl, sizeof(pou::NlIon) * M));
+  CHK(nalloc((void **)&c->d_nl_list, sizeof(int) * M));
+  CHK(nalloc((void **)&c->d_nlpart, sizeof(double) * (size_t)M * nsp * N * 12));
+  CHK(nalloc((void **)&c->d_nlC, sizeof(double) * (size_t)4 * M * N));
+  CHK(nalloc((void **)&c->d_nlC2, sizeof(double) * (size_t)4 * M * N));
+  CHK(nalloc((void **)&c->d_nlD, sizeof(double) * (size_t)12 * M * N));
+  HIPCHK(c, hipMemcpyAsync(c->d_nl, c->nl_ions.data(), sizeof(pou::NlIon) * M,
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_nl_list, list.data(), sizeof(int) * M, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->nl_on = true;
+  c->p.terms |= POU_TERM_NLOC;
+  return POU_OK;
+}
 
 pou_status pou_energy(pou_ctx *c, const void *U, pou_energy_terms *out) {
   NEED_SYSTEM(c);

@@ -1036,6 +1036,7 @@ __global__ void k_armijo(const double *__restrict__ rep, const double *__restric
   E += (terms & 2u) ? rep[2 * N + 1] : 0.0;
   E += (terms & 4u) ? 0.5 * rep[2 * N + 2] : 0.0;
   E += (terms & 16u) ? rep[2 * N + 3] : 0.0;
+  E += (terms & 32u) ? rep[rr_off + 2] : 0.0;  // nonlocal term (zero without projectors)
   ok = ok && isfinite(E);
   const double tau = scal[0] * tscale;
   const bool pass = E <= C - rho1 * tau * scal[1];

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+#include <algorithm>
 #include <cstdint>
 #include <cstddef>
 
@@ -269,5 +270,35 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
                               const double *ginfo = nullptr, void *split_ws = nullptr);
 // BF16 values in each piece of the padded factor split for N > 128
 size_t split_factor_elems(int N);
+
+// ---- nonlocal projectors (nonlocal_kernels.hip)
+// One ion's projectors: position, width and amplitudes of xi_s = bs g,
+// xi_a = bp (d_a / rc) g, and the cube of b^3 grid points (corner o, wrapped
+// modulo n) on which they are evaluated.
+struct NlIon {
+  double R[3];
+  double rc, bs, bp;
+  int o[3];
+  int b;
+};
+// cube splits per ion (parallel partial sums) for cubes of at most bmax^3 points
+int nl_splits(int bmax);
+// partial overlaps <xi_l, u_i> (deriv: <d xi_l / d R_a, u_i>, 12 per ion) into
+// part[((I * nl_splits(bmax) + sp) * N + i) * K + k], K = 4 or 12, unscaled by h^3
+template <typename T>
+hipError_t launch_nl_overlap(const T *U, const NlIon *ions, int M, int bmax, int N, int n,
+                             double L, bool deriv, double *part, hipStream_t s);
+// C[4 M][N] = dv * sums of the partials; rep[i] += sum_l C[l][i]^2 (i < N);
+// rep[enl_off] = sum_i occ_i sum_l C[l][i]^2
+hipError_t launch_nl_finish(const double *part, int M, int bmax, int N, double dv,
+                            const double *occ, double *C, double *rep, int enl_off,
+                            hipStream_t s);
+// out[(I * 12 + k) * N + i] = dv * sums of the derivative partials
+hipError_t launch_nl_sum_deriv(const double *part, int M, int bmax, int N, double dv,
+                               double *out, hipStream_t s);
+// HU += V_nloc U over the cubes of the `count` ions in list (no two overlapping)
+template <typename T>
+hipError_t launch_nl_apply(T *HU, const NlIon *ions, const int *list, int count, int bmax,
+                           const double *C, int N, int n, double L, hipStream_t s);
 
 }  // namespace pou

@@ -6,17 +6,19 @@ import synth
 from oracle import ks
 
 
-def oracle_system(cfg, terms=ks.TERM_ALL):
+def oracle_system(cfg, terms=ks.TERM_ALL, proj=None):
     R, Z, s = synth.atoms(cfg)
-    return ks.System(cfg.n, cfg.L, R, Z, s, synth.occupations(cfg), terms)
+    if proj is not None:
+        terms |= ks.TERM_NLOC
+    return ks.System(cfg.n, cfg.L, R, Z, s, synth.occupations(cfg), terms, proj=proj)
 
 
-def gpu_system(cfg, precision="fp64", **params):
+def gpu_system(cfg, precision="fp64", proj=None, **params):
     import paper_1510_07230_amd as pk
     R, Z, s = synth.atoms(cfg)
     p = pk.default_params(**params)
     return pk.System(cfg.n, cfg.L, R, Z, s, synth.occupations(cfg), precision=precision,
-                     params=p)
+                     params=p, proj=proj)
 
 
 def to_np(t):

@@ -61,12 +61,12 @@ def _direction_error(W, so, vext):
     return dH + dsig[:, None, None, None] * np.abs(W) + 2 * U32 * np.abs(HW)
 
 
-def step_parity(cfg, steps, label):
-    so = oracle_system(cfg)
+def step_parity(cfg, steps, label, proj=None):
+    so = oracle_system(cfg, proj=proj)
     p = algm.Params()
     p.tau_init = 1.0 / algm.lambda_max_kinetic(so.h)
     W0 = _f32(oorth.orth(synth.orbitals(cfg), so.h)[0])
-    g = gpu_system(cfg, "mixed", tau_init=p.tau_init)
+    g = gpu_system(cfg, "mixed", proj=proj, tau_init=p.tau_init)
     U = g.new_block(W0)
     vext = ks.external_potential(so)
     prev, cur = None, W0
