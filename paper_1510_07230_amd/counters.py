@@ -10,9 +10,16 @@ The --mfma form reads a run with SQ_INSTS_VALU_MFMA_MOPS_{BF16,F32,F64},
 SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE and the kernel trace of the same
 run, and reports per kernel the matrix-core FLOPs per dispatch (MOPS counters
 count units of 512 FLOPs), the achieved FLOP rate over the traced duration
-and its fraction of the dense MFMA peak of the dominant type, and the MFMA
-busy share of the active cycles (busy cycles over GUI-active cycles times the
-256 CUs x 4 SIMDs).
+and its fraction of the dense MFMA peak of the dominant type, and the raw
+ratio of SQ_VALU_MFMA_BUSY_CYCLES to GRBM_GUI_ACTIVE (the aggregation of the
+busy counter over CUs and SIMDs is not documented here, so the FLOP-based
+fraction is the utilisation figure).
+
+  python -m paper_1510_07230_amd.counters --stats KERNEL_STATS_CSV --md OUT.md \\
+      [--title T] [--cmd "..."] [--sources]
+
+The --stats form turns a rocprofv3 --stats kernel table into a Markdown
+summary (top kernels by total time) with the hashes of the HIP sources.
 
 BLOCK_BYTES is the size of the plain copy (k_convert<float,float>) that the
 --calibrate-copy run of bench.py performs: it reads and writes BLOCK_BYTES
@@ -79,7 +86,7 @@ def mfma_summary(counter_csv, trace_csv, min_flops=1e9):
                   "mfma_flops": flops, "type": top,
                   "tflops": total / d / 1e12,
                   "frac_of_peak": flops[top] / d / 1e12 / PEAK_TFLOPS[top],
-                  "busy_share": busy / (gui * 256 * 4) if gui > 0 else None}
+                  "busy_per_gui": busy / gui if gui > 0 else None}
     return out
 
 
@@ -88,15 +95,18 @@ def mfma_markdown(res, title, cmds):
            "Counter run (the program directly after `--`; $REPO: the repository root, "
            "$OUT: an output directory):", ""]
     out += ["    " + x for x in cmds]
-    out += ["", "MOPS counters count units of 512 FLOPs.  Rate = FLOPs per dispatch / median "
-                "traced duration of the same run (counter collection can lengthen a kernel, so "
-                "the rate is a lower bound); peak = dense MFMA peak of the dominant type "
-                "(BF16 2.5 PFLOP/s, FP32 157.3, FP64 78.6 TFLOP/s).  Busy share = "
-                "SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 256 CUs x 4 SIMDs).", "",
-            "| kernel | dispatches | median us | type | MFMA GFLOP/dispatch | TFLOP/s | frac of peak | busy share |",
+    out += ["", "MOPS counters count units of 512 FLOPs (checked: the FP64 Gram of 128 "
+                "orbitals over 96^3 points reports 36 tiles x 256 x 2 x 884,736 FLOPs).  Rate = "
+                "FLOPs per dispatch / median traced duration of the same run (counter "
+                "collection can lengthen a kernel, so the rate is a lower bound); peak = dense "
+                "MFMA peak of the dominant type (BF16 2.5 PFLOP/s, FP32 157.3, FP64 78.6 "
+                "TFLOP/s).  The FLOPs are the matrix-core FLOPs the kernel issues (whole "
+                "diagonal tiles, all four split products), not the algorithmic N(N+1) Ng.  "
+                "busy/gui = SQ_VALU_MFMA_BUSY_CYCLES / GRBM_GUI_ACTIVE, raw.", "",
+            "| kernel | dispatches | median us | type | MFMA GFLOP/dispatch | TFLOP/s | frac of peak | busy/gui |",
             "|---|---:|---:|---|---:|---:|---:|---:|"]
     for k, r in sorted(res.items(), key=lambda kv: -sum(kv[1]["mfma_flops"].values())):
-        b = "" if r["busy_share"] is None else f"{r['busy_share']:.3f}"
+        b = "" if r["busy_per_gui"] is None else f"{r['busy_per_gui']:.1f}"
         out.append(f"| `{short(k)}` | {r['dispatches']} | {r['median_us']:.1f} | {r['type']} | "
                    f"{sum(r['mfma_flops'].values()) / 1e9:.2f} | {r['tflops']:.1f} | "
                    f"{r['frac_of_peak']:.3f} | {b} |")
@@ -176,7 +186,36 @@ def markdown(res, cmds):
     return "\n".join(out) + "\n"
 
 
+def sources_line():
+    names = ["grid_kernels.hip", "dense_kernels.hip", "nonlocal_kernels.hip", "engine.hip"]
+    return "Sources: " + ", ".join(f"{n} {source_sha(n)}" for n in names
+                                   if os.path.exists(os.path.join(HERE, "csrc", n))) + "."
+
+
+def stats_markdown(stats_csv, title, cmds, top=24):
+    rows = list(csv.DictReader(open(stats_csv)))
+    out = [f"# rocprofv3 kernel statistics: {title}", "",
+           "Command ($REPO: the repository root, $OUT: an output directory):", ""]
+    out += ["    " + x for x in cmds]
+    out += ["", sources_line(), "",
+            "| kernel | calls | avg us | min us | max us | total % |", "|---|---:|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
+    if "--stats" in sys.argv:
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--stats")
+        ap.add_argument("--md", required=True)
+        ap.add_argument("--title", default="")
+        ap.add_argument("--cmd", action="append", default=[])
+        a = ap.parse_args()
+        open(a.md, "w").write(stats_markdown(a.stats, a.title, a.cmd))
+        return
     if "--mfma" in sys.argv:
         ap = argparse.ArgumentParser()
         ap.add_argument("--mfma", nargs=2, metavar=("COUNTER_CSV", "TRACE_CSV"))
@@ -186,7 +225,8 @@ def main():
         a = ap.parse_args()
         res = mfma_summary(*a.mfma)
         if a.md:
-            open(a.md, "w").write(mfma_markdown(res, a.title, a.cmd))
+            open(a.md, "w").write(mfma_markdown(res, a.title, a.cmd).rstrip("\n") + "\n\n"
+                                  + sources_line() + "\n")
         else:
             json.dump(res, sys.stdout, indent=1)
         return
