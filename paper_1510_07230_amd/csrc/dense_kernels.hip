@@ -75,23 +75,32 @@ __global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict
   d4 acc = d4{0, 0, 0, 0};
   if (J <= I) {
     const int ia = 16 * I + r16, jb = 16 * J + r16;
-    for (int K = J; K <= I; ++K) {
-      double a[4], b[4];
+    // K tiles in batches of eight whose loads are all issued before their
+    // products (the tile is latency-bound: one wave, up to 32 K tiles)
+    for (int K0 = J; K0 <= I; K0 += 8) {
+      double a[8][4], b[8][4];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int k = 16 * K + 4 * s4 + q;
-        a[s4] = (ia < N && k < N) ? A[(i64)ia * N + k] : 0.0;
-        double bv = (jb < N && k < N) ? B[(i64)k * N + jb] : 0.0;
-        if (split_b && jb < N && k < N) {
-          const double dlt = (k == jb) ? 1.0 : 0.0;
-          __bf16 hi, lo;
-          split_bf16((float)(bv - dlt), hi, lo);
-          bv = dlt + ((double)(float)hi + (double)(float)lo);
+      for (int kk = 0; kk < 8; ++kk) {
+        const int K = K0 + kk;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 16 * K + 4 * s4 + q;
+          const bool in = K <= I && k < N;
+          a[kk][s4] = (in && ia < N) ? A[(i64)ia * N + k] : 0.0;
+          double bv = (in && jb < N) ? B[(i64)k * N + jb] : 0.0;
+          if (split_b && in && jb < N) {
+            const double dlt = (k == jb) ? 1.0 : 0.0;
+            __bf16 hi, lo;
+            split_bf16((float)(bv - dlt), hi, lo);
+            bv = dlt + ((double)(float)hi + (double)(float)lo);
+          }
+          b[kk][s4] = bv;
         }
-        b[s4] = bv;
       }
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) acc = mfma(a[s4], b[s4], acc);
+      for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc = mfma(a[kk][s4], b[kk][s4], acc);
     }
   }
 #pragma unroll
@@ -1779,6 +1788,257 @@ void k_gram_big64(const double *__restrict__ A, int N, i64 ng,
         out[(32 * rw + 16 * a + q + 4 * r) * kBB + 64 * cw + 16 * c + r16] = acc[a][c][r];
 }
 
+// Cross product C = A B^T of two orbital blocks (N x ng each, FP64 or FP32
+// values) on FP64 MFMA, for the subspace matrix <(HW)^T W> and the residual
+// of section 3.3: the structure of k_gram_big64 (128 x 128 output blocks over
+// nsplit ranges of kper points, the ranges of one block pair on one XCD,
+// 16-point chunks of both row blocks staged in LDS as doubles, double
+// buffered) with the column block taken from B and every ordered block pair
+// (bi, bj) = (pair / nb, pair % nb) computed in full.  FP32 values are
+// converted exactly on load, so the products and sums are FP64.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(kAB) __attribute__((amdgpu_waves_per_eu(4)))
+void k_cross_big64(const T *__restrict__ A, const T *__restrict__ B, int N, i64 ng, i64 kper,
+                   int nsplit, int npairs, double *__restrict__ part) {
+  constexpr int KC = 16;
+  constexpr int PD = KC + 1;
+  constexpr int NV = 2 * kBB * KC / 2 / kAB;  // point pairs per thread per chunk (4)
+  __shared__ double sd[2][2][kBB][PD];
+  int split, pair;
+  xcd_group(blockIdx.x, npairs, split, pair);
+  if (split >= nsplit) return;
+  const int nb = (N + kBB - 1) / kBB;
+  const int bi = pair / nb, bj = pair % nb;
+  const i64 k_beg = (i64)split * kper;
+  const i64 k_end = min(ng, k_beg + kper);
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int rw = w >> 1, cw = w & 1;
+  // slot e: pair f = t + 512 e, row f / 8 (block bi of A for e < NV / 2, block
+  // bj of B after), points 2 (f % 8) and 2 (f % 8) + 1
+  const int c2 = (t & 7) * 2;
+  double2 v[NV];
+  unsigned voff[VEC ? NV : 1];
+  if (VEC) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int row = (t + kAB * e) >> 3;
+      const int rb = row < kBB ? bi : bj, r = row & (kBB - 1);
+      voff[VEC ? e : 0] = (unsigned)((i64)min(r, N - 1 - rb * kBB) * ng + c2);
+    }
+  }
+  const T *abase = A + (i64)bi * kBB * ng, *bbase = B + (i64)bj * kBB * ng;
+  typedef T pair_t __attribute__((ext_vector_type(2)));
+  auto load = [&](i64 k0) {
+    if (VEC) {
+      const i64 k0c = min(k0, ng - KC);
+      const T *pa = abase + k0c, *pb = bbase + k0c;
+#pragma unroll
+      for (int e = 0; e < NV; ++e) {
+        const pair_t x = *(const pair_t *)((e < NV / 2 ? pa : pb) + voff[VEC ? e : 0]);
+        v[e] = make_double2((double)x[0], (double)x[1]);
+      }
+      const int shift = (int)(k0 - k0c);
+      if (shift > 0) {
+        const bool ok = c2 >= shift;
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+          v[e].x = ok ? v[e].x : 0.0;
+          v[e].y = ok ? v[e].y : 0.0;
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int row = (t + kAB * e) >> 3;
+      const bool first = row < kBB;
+      const int grow = first ? bi * kBB + row : bj * kBB + row - kBB;
+      const T *p = (first ? A : B) + (i64)min(grow, N - 1) * ng;
+      const i64 g = k0 + c2;
+      double2 x;
+      x.x = (double)p[min(g, ng - 1)];
+      x.y = (double)p[min(g + 1, ng - 1)];
+      x.x = (g < k_end) ? x.x : 0.0;
+      x.y = (g + 1 < k_end) ? x.y : 0.0;
+      v[e] = x;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int row = (t + kAB * e) >> 3;
+      const int blk = row >= kBB ? 1 : 0, r = row & (kBB - 1);
+      sd[b][blk][r][c2] = v[e].x;
+      sd[b][blk][r][c2 + 1] = v[e].y;
+    }
+  };
+  d4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = d4{0, 0, 0, 0};
+  auto compute = [&](int b) {
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      double av[2], bv[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = sd[b][0][32 * rw + 16 * a + r16][4 * ks + q];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = sd[b][1][64 * cw + 16 * c + r16][4 * ks + q];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = mfma(av[a], bv[c], acc[a][c]);
+    }
+  };
+  const i64 nchunk = k_end > k_beg ? (k_end - k_beg + KC - 1) / KC : 0;
+  if (nchunk > 0) {
+    load(k_beg);
+    stash(0);
+  }
+  __syncthreads();
+  int b = 0;
+  for (i64 ch = 0; ch + 1 < nchunk; ++ch, b ^= 1) {
+    load(k_beg + KC * (ch + 1));
+    compute(b);
+    __builtin_amdgcn_sched_barrier(0);
+    stash(b ^ 1);
+    __syncthreads();
+  }
+  if (nchunk > 0) compute(b);
+  double *out = part + ((i64)split * npairs + pair) * kBB * kBB;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(32 * rw + 16 * a + q + 4 * r) * kBB + 64 * cw + 16 * c + r16] = acc[a][c][r];
+}
+
+// S[i][j] = dv / 2 (C[i][j] + C[j][i]) from the split partials of k_cross_big64
+// (block pair (i / 128, j / 128) holds C rows i, columns j), fixed order.
+__global__ __launch_bounds__(kBlock) void k_cross_reduce_big(const double *__restrict__ part,
+                                                             int N, int nsplit, int npairs,
+                                                             double dv, double *__restrict__ S) {
+  const int nb = (N + kBB - 1) / kBB;
+  const i64 stride = (i64)npairs * kBB * kBB;
+  for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < (i64)N * N;
+       e += (i64)gridDim.x * kBlock) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    if (j < i) continue;
+    const i64 eij = (i64)((i / kBB) * nb + j / kBB) * kBB * kBB + (i % kBB) * kBB + j % kBB;
+    const i64 eji = (i64)((j / kBB) * nb + i / kBB) * kBB * kBB + (j % kBB) * kBB + i % kBB;
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    int sp = 0;
+    for (; sp + 1 < nsplit; sp += 2) {
+      a0 += part[(i64)sp * stride + eij];
+      a1 += part[(i64)(sp + 1) * stride + eij];
+      b0 += part[(i64)sp * stride + eji];
+      b1 += part[(i64)(sp + 1) * stride + eji];
+    }
+    for (; sp < nsplit; ++sp) {
+      a0 += part[(i64)sp * stride + eij];
+      b0 += part[(i64)sp * stride + eji];
+    }
+    const double v = 0.5 * dv * ((a0 + a1) + (b0 + b1));
+    S[(i64)i * N + j] = v;
+    S[(i64)j * N + i] = v;
+  }
+}
+
+// out = M X for a full N x N matrix M (FP64, row-major) and orbital blocks of
+// FP64 or FP32 values, on FP64 MFMA: the (row block J, 128-point tile)
+// workgroups and 4 x 2 wave grid of k_apply_big64 with the K loop over every
+// 16-orbital chunk and no identity term.  FP32 values are converted exactly
+// on load; the result is rounded to the element type once.  out must not
+// alias X.
+template <typename T>
+__global__ __launch_bounds__(kAB) void k_mult_full64(const double *__restrict__ M,
+                                                     const T *__restrict__ X, T *__restrict__ out,
+                                                     int N, i64 ng) {
+  constexpr int KC = 16;
+  __shared__ double ds[2][kBB][KC + 1];
+  __shared__ double xs[2][KC][kBB];
+  const int nJ = (N + kBB - 1) / kBB;
+  int ptile, J;
+  xcd_group(blockIdx.x, nJ, ptile, J);
+  const i64 g0 = (i64)ptile * kBB;
+  if (g0 >= ng) return;
+  const int nkc = (N + KC - 1) / KC;
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
+  const int rw = w >> 1, cw = w & 1;
+  // loaders: M row dr, columns dc .. dc + 3 of the chunk; X orbital xo, points xq .. xq + 3
+  const int dr = t >> 2, dc = 4 * (t & 3);
+  const int jrow = J * kBB + dr;
+  const double *mrow = M + (i64)min(jrow, N - 1) * N;
+  const int xo = t >> 5, xq = 4 * (t & 31);
+  double dv[4], xv[4];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = KC * kc + dc + e;
+      const double d = mrow[min(i, N - 1)];
+      dv[e] = ((jrow < N) & (i < N)) ? d : 0.0;
+    }
+    const T *xr = X + (i64)min(KC * kc + xo, N - 1) * ng;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xv[e] = (double)xr[min(g0 + xq + e, ng - 1)];
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ds[b][dr][dc + e] = dv[e];
+      xs[b][xo][xq + e] = xv[e];
+    }
+  };
+  d4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = d4{0, 0, 0, 0};
+  auto compute = [&](int b) {
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      double av[2], bv[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = ds[b][32 * rw + 16 * a + r16][4 * ks + q];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = xs[b][4 * ks + q][64 * cw + 16 * c + r16];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = mfma(av[a], bv[c], acc[a][c]);
+    }
+  };
+  load(0);
+  stash(0);
+  __syncthreads();
+  int kc = 0;
+  for (; kc + 1 < nkc; ++kc) {
+    load(kc + 1);
+    compute(kc & 1);
+    __builtin_amdgcn_sched_barrier(0);
+    stash((kc & 1) ^ 1);
+    __syncthreads();
+  }
+  compute(kc & 1);
+  // lane (r16, q) of tile (a, c) holds rows q + 4 r of the tile at point r16
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = J * kBB + 32 * rw + 16 * a + q + 4 * r;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const i64 g = g0 + 64 * cw + 16 * c + r16;
+        if (j < N && g < ng) out[(i64)j * ng + g] = (T)acc[a][c][r];
+      }
+    }
+}
+
 // out = X + D X for lower-triangular D = L^-1 - I (FP64 N x N) and FP64
 // orbitals, N > 128, on FP64 MFMA: the (row block J, 128-point tile)
 // workgroups of k_apply_big, eight waves in a 4 x 2 grid, wave (rw, cw)
@@ -2388,32 +2648,52 @@ template hipError_t launch_apply_lower<float>(const double *, const float *, con
 
 
 int cross_gram_split(int N) {
-  const i64 per = (i64)N * N;
-  i64 sp = (i64)(32 << 20) / (per * 8);  // at most 32 MiB of partials
-  if (sp > 256) sp = 256;
-  if (sp < 1) sp = 1;
+  // k_cross_big64: about two rounds of resident workgroups, a multiple of 8
+  // ranges, at most 128 MiB of partials
+  const int nb = (N + kBB - 1) / kBB;
+  const i64 npairs = (i64)nb * nb;
+  const int res = resident_workgroups((const void *)k_cross_big64<double, true>, kAB);
+  i64 sp = (2 * (i64)res + npairs - 1) / npairs;
+  const i64 cap = ((i64)128 << 20) / (npairs * kBB * kBB * 8);
+  sp = std::min<i64>(sp, std::min<i64>(cap, 1024));
+  sp = std::max<i64>(8, sp / 8 * 8);
   return (int)sp;
+}
+
+size_t cross_partial_doubles(int N) {
+  const int nb = (N + kBB - 1) / kBB;
+  return (size_t)cross_gram_split(N) * nb * nb * kBB * kBB;
 }
 
 template <typename T>
 hipError_t launch_cross_gram(const T *A, const T *B, int N, i64 ng, double dv, double *part,
                              double *S, hipStream_t s) {
   const int nsplit = cross_gram_split(N);
+  const int nb = (N + kBB - 1) / kBB;
+  const int npairs = nb * nb;
   i64 kper = (ng + nsplit - 1) / nsplit;
-  kper = ((kper + 31) / 32) * 32;
-  const int nt = (N + 63) / 64;
-  hipLaunchKernelGGL(k_cross_gram<T>, dim3(nsplit, nt * nt), dim3(kBlock), 0, s, A, B, N, ng, kper,
-                     part);
-  int blocks = (N * N + kBlock - 1) / kBlock;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_cross_reduce, dim3(blocks), dim3(kBlock), 0, s, part, N, nsplit, dv, S);
+  kper = ((kper + 15) / 16) * 16;
+  const int grid = ((nsplit + 7) / 8) * 8 * npairs;
+  const bool vec = (ng & 1) == 0 && ng >= 16 && (i64)kBB * ng * (i64)sizeof(T) < (1LL << 32);
+  if (vec)
+    hipLaunchKernelGGL((k_cross_big64<T, true>), dim3(grid), dim3(kAB), 0, s, A, B, N, ng, kper,
+                       nsplit, npairs, part);
+  else
+    hipLaunchKernelGGL((k_cross_big64<T, false>), dim3(grid), dim3(kAB), 0, s, A, B, N, ng, kper,
+                       nsplit, npairs, part);
+  int blocks = (int)std::min<i64>(1024, ((i64)N * N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_cross_reduce_big, dim3(blocks), dim3(kBlock), 0, s, part, N, nsplit, npairs,
+                     dv, S);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_rotate(const double *P, const T *X, T *out, int N, i64 ng, hipStream_t s) {
-  dim3 grid((unsigned)((ng + kBlock - 1) / kBlock), (unsigned)((N + 15) / 16));
-  hipLaunchKernelGGL(k_rotate<T>, grid, dim3(kBlock), 0, s, P, X, out, N, ng);
+  const int nJ = (N + kBB - 1) / kBB;
+  const i64 npt = (ng + kBB - 1) / kBB;
+  const i64 grid = ((npt + 7) / 8) * 8 * nJ;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mult_full64<T>, dim3((unsigned)grid), dim3(kAB), 0, s, P, X, out, N, ng);
   return hipGetLastError();
 }
 

@@ -704,7 +704,14 @@ pou_status rotate_subspace(pou_ctx *c, T *W) {
   for (double x : A)
     if (!std::isfinite(x)) return fail(c, POU_ERR_NONFINITE, "subspace matrix is not finite");
   symm_eigh(N, A, V, w);
-  HIPCHK(c, hipMemcpyAsync(c->d_P, V.data(), sizeof(double) * V.size(), hipMemcpyHostToDevice, s));
+  // the rotation kernel multiplies by a row-major M with out_j = sum_i M[j][i] x_i,
+  // so it takes P^T (P's columns are the eigenvectors)
+  std::vector<double> &Pt = A;  // A is consumed by the eigensolver
+  Pt.resize((size_t)N * N);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Pt[(size_t)j * N + i] = V[(size_t)i * N + j];
+  HIPCHK(c, hipMemcpyAsync(c->d_P, Pt.data(), sizeof(double) * Pt.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));  // Pt is pageable host memory
   KL(POU_K_OTHER, pou::launch_rotate<T>(c->d_P, (const T *)W, (T *)c->d_W2, N, c->ng, s));
   HIPCHK(c, hipMemcpyAsync(W, c->d_W2, sizeof(T) * (size_t)N * c->ng, hipMemcpyDeviceToDevice, s));
   KL(POU_K_OTHER, pou::launch_rotate<T>(c->d_P, (const T *)c->d_HW, (T *)c->d_HWt, N, c->ng, s));
@@ -1336,8 +1343,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_G, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_S, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_P, sizeof(double) * (size_t)norb * norb));
-  CHK(dalloc(c, &c->d_xpart,
-             sizeof(double) * (size_t)pou::cross_gram_split(norb) * norb * norb));
+  CHK(dalloc(c, &c->d_xpart, sizeof(double) * pou::cross_partial_doubles(norb)));
   CHK(dalloc(c, &c->d_Minv, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Minv2, sizeof(double) * (size_t)norb * norb));
   CHK(dalloc(c, &c->d_Mcomb, sizeof(double) * (size_t)norb * norb));

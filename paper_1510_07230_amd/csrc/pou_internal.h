@@ -241,15 +241,18 @@ size_t chol_workspace_doubles(int N);
 // doubles needed by the Gram partial buffer
 size_t gram_partial_doubles(int N, int nsplit);
 // ---- subspace rotation and residual (rare: every n_diag steps or on request)
-// splits of the cross product; its partial buffer holds split * N * N doubles
+// splits of the cross product and the doubles of its partial buffer
 int cross_gram_split(int N);
-// S = dv/2 (A B^T + B A^T) over the grid (A, B: [N][ng]); part: scratch
+size_t cross_partial_doubles(int N);
+// S = dv/2 (A B^T + B A^T) over the grid (A, B: [N][ng]) on FP64 MFMA; part:
+// scratch of cross_partial_doubles(N)
 template <typename T>
 hipError_t launch_cross_gram(const T *A, const T *B, int N, i64 ng, double dv, double *part,
                              double *S, hipStream_t s);
-// out = P^T X in the orbital index: out[j] = sum_i P[i][j] X[i] (P: FP64 N x N)
+// out = M X in the orbital index: out[j] = sum_i M[j][i] X[i] (M: FP64 N x N,
+// row-major) on FP64 MFMA; out must not alias X
 template <typename T>
-hipError_t launch_rotate(const double *P, const T *X, T *out, int N, i64 ng, hipStream_t s);
+hipError_t launch_rotate(const double *M, const T *X, T *out, int N, i64 ng, hipStream_t s);
 // Number of K splits of the Gram kernels.  N <= 128: as many as are resident
 // on the device at once, clamped to [256, 1024].  N > 128: a multiple of 8
 // ranges sized to whole rounds of resident workgroups.
