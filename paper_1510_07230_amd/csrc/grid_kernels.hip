@@ -45,11 +45,14 @@ __device__ inline double plane_load<double>(__amdgpu_buffer_rsrc_t r, unsigned b
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
 }
 
+// Stores of H U are used once by a later kernel: cache policy 2 marks them
+// non-temporal (the NT bit of gfx940-class buffer stores)
+constexpr int kStoreNT = 2;
 __device__ inline void plane_store(__amdgpu_buffer_rsrc_t r, unsigned boff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, boff, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, boff, 0, kStoreNT);
 }
 __device__ inline void plane_store(__amdgpu_buffer_rsrc_t r, unsigned boff, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(pou_v2u, v), r, boff, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(pou_v2u, v), r, boff, 0, kStoreNT);
 }
 
 // ----------------------------------------------------------------- stencil
