@@ -179,9 +179,15 @@ __device__ inline double rsqrt_nr(double x) {
 // scalar lane reads; lanes 32..63 carry zero columns.  L_pp^-1 goes to Li
 // (lower part; zeros above).  A pivot that is not above 1e-13 times the
 // block's original diagonal entry (dg) flags numerical rank deficiency in
-// *sbad.
-__device__ inline void chol_diag_block(const double *App, double *Li, const double *dg, int l,
-                                       int *sbad) {
+// *sbad.  All operands are in LDS and typed so (the function is not inlined:
+// it keeps its own registers); a failed pivot is replaced without a branch.
+typedef __attribute__((address_space(3))) double lds_double;
+typedef __attribute__((address_space(3))) int lds_int;
+__device__ inline lds_double *lds(double *p) { return (lds_double *)p; }
+__device__ inline lds_int *lds(int *p) { return (lds_int *)p; }
+__device__ __attribute__((noinline)) void chol_diag_block(const lds_double *App, lds_double *Li,
+                                                          const lds_double *dg, int l,
+                                                          lds_int *sbad) {
   const int c = l;
   double v[16];
 #pragma unroll
@@ -189,13 +195,13 @@ __device__ inline void chol_diag_block(const double *App, double *Li, const doub
     if (c < 16) v[r] = (c <= r) ? App[r * kTP + c] : App[c * kTP + r];
     else v[r] = (c - 16 == r) ? 1.0 : 0.0;  // zero for c >= 32
   }
+  bool bad = false;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     double piv = readlane_f64(v[k], k);
-    if (!((piv > 1e-13 * dg[k]) && isfinite(piv))) {
-      if (l == 0) *sbad = 1;
-      piv = 1.0;
-    }
+    const bool ok = (piv > 1e-13 * dg[k]) && isfinite(piv);
+    bad |= !ok;
+    piv = ok ? piv : 1.0;
     const double isp = rsqrt_nr(piv);
     const double rk = v[k];
     const double rki = rk * (isp * isp);
@@ -207,6 +213,7 @@ __device__ inline void chol_diag_block(const double *App, double *Li, const doub
 #pragma unroll
     for (int r = 0; r < 16; ++r) Li[r * kTP + (c - 16)] = (c - 16 <= r) ? v[r] : 0.0;
   }
+  if (bad && l == 0) *sbad = 1;
 }
 
 // Blocked Cholesky G = L L^T and L^-1 in one workgroup (16-wide panels,
@@ -229,7 +236,7 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
                                                        float *__restrict__ D32,
                                                        double *__restrict__ D64,
                                                        double *__restrict__ info,
-                                                       double *__restrict__ ws) {
+                                                       double *__restrict__ ws, int outs) {
   __shared__ double slot_s[LDS_TILES ? 36 * kTile : 1];
   // panel tiles L_ip in LDS (8 for N <= 128, 32 for the workspace variant),
   // and for the workspace variant the current block row B_pj of L^-1 too:
@@ -237,6 +244,8 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
   __shared__ double P_s[(LDS_TILES ? 8 : 32) * kTile];
   __shared__ double Brow_s[LDS_TILES ? 1 : 32 * kTile];
   __shared__ double Li2[2][kTile];
+  // the workspace variant's copy of the diagonal block being factored
+  __shared__ double Ad_s[LDS_TILES ? 1 : kTile];
   __shared__ double sdg[512];
   __shared__ double sred[NTHR / 64];
   __shared__ int sbad;
@@ -277,11 +286,11 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
             x = (r == c) ? 1.0 : 0.0;
           }
           slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] = x;
+          if (r == c) sdg[r] = x;
         }
       }
     }
   }
-  for (int r = t; r < NP; r += NTHR) sdg[r] = (r < N) ? G[(i64)r * N + r] : 1.0;
   m = wave_max(m);
   if (l == 0) sred[w] = m;
   if (t == 0) sbad = 0;
@@ -291,7 +300,14 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
     for (int k = 0; k < NW; ++k) mx = fmax(mx, sred[k]);
     info[1] = mx;
   }
-  if (w == 0) chol_diag_block(slot + tri_slot(0, 0) * kTile, Li2[0], sdg, l, &sbad);
+  if (w == 0) {
+    double *A0 = slot + tri_slot(0, 0) * kTile;
+    if (!LDS_TILES) {
+      for (int e = l; e < 16 * kTP; e += 64) Ad_s[e] = A0[e];
+      A0 = Ad_s;
+    }
+    chol_diag_block(lds(A0), lds(Li2[0]), lds(sdg), l, lds(&sbad));
+  }
   __syncthreads();
   for (int p = 0; p < NT; ++p) {
     const double *Li = Li2[p & 1];
@@ -330,10 +346,13 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
       const int ne = m1 * (p + 1);
       const bool look = (m1 > 0);
       if (look && w == 0) {
+        // the workspace variant factors an LDS copy (the tile in the
+        // workspace is not read again: its slot takes B_{p+1,p+1} next)
         double *A1 = slot + tri_slot(p + 1, p + 1) * kTile;
-        tile_mma(P + (p + 1) * kTile, P + (p + 1) * kTile, 1, -1.0, A1, A1, l);
+        tile_mma(P + (p + 1) * kTile, P + (p + 1) * kTile, 1, -1.0, A1, LDS_TILES ? A1 : Ad_s, l);
         __threadfence_block();
-        chol_diag_block(A1, Li2[(p + 1) & 1], sdg + 16 * (p + 1), l, &sbad);
+        chol_diag_block(lds(LDS_TILES ? A1 : Ad_s), lds(Li2[(p + 1) & 1]), lds(sdg + 16 * (p + 1)),
+                        l, lds(&sbad));
       }
       const int first = look ? 1 : 0;                // task 0 is wave 0's when looking ahead
       const int ww = look ? w - 1 : w, nww = look ? NW - 1 : NW;
@@ -420,15 +439,17 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
     }
     __syncthreads();
   }
+  // outputs named in outs (CHOL_OUT_*): the single workgroup's stores are a
+  // large part of the kernel, so callers ask only for what they read
   for (int r = w; r < N; r += NW) {
     for (int c = l; c < N; c += 64) {
       const double v =
           (c <= r) ? slot[tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15)] : 0.0;
       const i64 e = (i64)r * N + c;
-      Minv[e] = v;
       const double d = v - (r == c ? 1.0 : 0.0);
-      D64[e] = d;
-      D32[e] = (float)d;
+      if (outs & CHOL_OUT_MINV) Minv[e] = v;
+      if (outs & CHOL_OUT_D64) D64[e] = d;
+      if (outs & CHOL_OUT_D32) D32[e] = (float)d;
     }
   }
   if (t == 0) info[0] = sbad ? 1.0 : 0.0;
@@ -2048,9 +2069,11 @@ __global__ __launch_bounds__(kAB) void k_mult_full64(const double *__restrict__ 
 // [orbital][point] layout and D as [row][k] (pitch 17 doubles), 16-orbital
 // chunks, double-buffered.  Loads read clamped addresses: rows of X past N
 // meet zero D columns, points past ng are never stored.  out must not alias X.
-__global__ __launch_bounds__(kAB) void k_apply_big64(const double *__restrict__ D,
-                                                     const double *__restrict__ X,
-                                                     double *__restrict__ out, int N, i64 ng) {
+// With rhop, the block's share of the density as in k_apply_big.
+__global__ __launch_bounds__(kAB) __attribute__((amdgpu_waves_per_eu(4)))
+void k_apply_big64(const double *__restrict__ D, const double *__restrict__ X,
+                   double *__restrict__ out, int N, i64 ng, const double *__restrict__ occ,
+                   double *__restrict__ rhop) {
   constexpr int KC = 16;
   __shared__ double ds[2][kBB][KC + 1];
   __shared__ double xs[2][KC][kBB];
@@ -2122,26 +2145,40 @@ __global__ __launch_bounds__(kAB) void k_apply_big64(const double *__restrict__ 
   }
   compute(kc & 1, kc);
   // lane (r16, q) of tile (a, c) holds rows q + 4 r of the tile at point r16
+  double rp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
-    double xi[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = min(J * kBB + 32 * rw + 16 * a + q + 4 * r, N - 1);
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        xi[r][c] = X[(i64)j * ng + min(g0 + 64 * cw + 16 * c + r16, ng - 1)];
-    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j = J * kBB + 32 * rw + 16 * a + q + 4 * r;
+      const double *xr = X + (i64)min(j, N - 1) * ng;
+      double xi[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xi[c] = xr[min(g0 + 64 * cw + 16 * c + r16, ng - 1)];
+      const double fj = (rhop != nullptr && j < N) ? occ[j] : 0.0;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const i64 g = g0 + 64 * cw + 16 * c + r16;
-        if (j < N && g < ng) out[(i64)j * ng + g] = xi[r][c] + acc[a][c][r];
+        const double o = xi[c] + acc[a][c][r];
+        rp[c] += fj * (o * o);
+        if (j < N && g < ng) out[(i64)j * ng + g] = o;
       }
     }
   }
+  if (rhop == nullptr) return;
+  // sum over the row groups q of a tile (lanes r16 + 16 q), then over the four
+  // row bands rw through LDS; point 64 cw + 16 c + r16
+  __shared__ double srho[4][kBB];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double v = rp[c];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (q == 0) srho[rw][64 * cw + 16 * c + r16] = v;
+  }
+  __syncthreads();
+  if (t < kBB && g0 + t < ng)
+    rhop[(i64)J * ng + g0 + t] = (srho[0][t] + srho[1][t]) + (srho[2][t] + srho[3][t]);
 }
 
 // BF16 hi/lo pieces of the factor for k_apply_big, padded to whole 128-row
@@ -2174,7 +2211,9 @@ __global__ __launch_bounds__(kBlock) void k_split_factor(const float *__restrict
 // shrinks the rows strongly (D near -I: the sum cancels), as in the first pass
 // over an unnormalised block; when ginfo[1] (max |G - I| of the Gram the factor
 // came from) is 0.25 or more, the kernel multiplies by M = I + D itself (the
-// pieces from k_split_factor hold M then) and adds nothing.
+// pieces from k_split_factor hold M then) and adds nothing.  With rhop, the
+// workgroup also writes its rows' share of the density, sum_j occ_j out_j^2
+// (FP64) over the block's 128 orbitals, to rhop[J][g].
 //
 // Workgroup = (row block J of 128 output orbitals, tile of 128 grid points);
 // the row blocks of one point tile share an XCD, heaviest first.  Four waves
@@ -2189,7 +2228,8 @@ template <bool VEC>
 __global__ __launch_bounds__(kAT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
                  const double *__restrict__ ginfo, const float *__restrict__ X,
-                 float *__restrict__ out, int N, i64 ng) {
+                 float *__restrict__ out, int N, i64 ng, const double *__restrict__ occ,
+                 double *__restrict__ rhop) {
   __shared__ __attribute__((aligned(16))) __bf16 xh[2][kBB][kBP];
   __shared__ __attribute__((aligned(16))) __bf16 xl[2][kBB][kBP];
   __shared__ __attribute__((aligned(16))) __bf16 dh[2][kBB][kBP];
@@ -2308,9 +2348,15 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
   }
   // lane (r16, q) of tile (a, c) holds orbital 16 a + r16 at points 4 q .. 4 q + 3;
   // per row tile, the identity loads are issued (clamped) before any store
+  double rp[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rp[c][r] = 0.0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int j = J * kBB + 64 * rw + 16 * a + r16;
+    const double fj = (rhop != nullptr && j < N) ? occ[j] : 0.0;
     float4 xi[4];
     const float *xr = X + (i64)min(j, N - 1) * ng;
 #pragma unroll
@@ -2330,6 +2376,10 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
       const float4 x = xi[c];
       const float4 o = make_float4(wgt * x.x + acc[a][c][0], wgt * x.y + acc[a][c][1],
                                    wgt * x.z + acc[a][c][2], wgt * x.w + acc[a][c][3]);
+      rp[c][0] += fj * ((double)o.x * (double)o.x);
+      rp[c][1] += fj * ((double)o.y * (double)o.y);
+      rp[c][2] += fj * ((double)o.z * (double)o.z);
+      rp[c][3] += fj * ((double)o.w * (double)o.w);
       float *orow = out + (i64)j * ng + g;
       if (j < N) {
         if (VEC) {
@@ -2343,11 +2393,39 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
       }
     }
   }
+  if (rhop == nullptr) return;
+  // sum over the 16 orbitals of a tile (lanes of equal q), then over the two
+  // row halves rw through LDS (stage buffers are free: every wave is past the
+  // loop's last barrier); point 64 cw + 16 c + 4 q + r
+  double(*srho)[kBB] = reinterpret_cast<double(*)[kBB]>(&xh[0][0][0]);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = rp[c][r];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      if (r16 == 0) srho[rw][64 * cw + 16 * c + 4 * q + r] = v;
+    }
+  __syncthreads();
+  if (t < kBB && g0 + t < ng) rhop[(i64)J * ng + g0 + t] = srho[0][t] + srho[1][t];
 }
 
 // Workgroups of `kernel` (`block` threads, static LDS only) that are resident
 // on the current device at once: the grid of a kernel that walks its work in
 // a grid-stride loop.  Cached per kernel and device.
+// rho[g] = sum over the nJ row blocks of rhop[J][g], in block order
+__global__ __launch_bounds__(kBlock) void k_rho_sum(const double *__restrict__ rhop, int nJ,
+                                                    i64 ng, double *__restrict__ rho) {
+  for (i64 g = (i64)blockIdx.x * kBlock + threadIdx.x; g < ng; g += (i64)gridDim.x * kBlock) {
+    double v = 0.0;
+    for (int J = 0; J < nJ; ++J) v += rhop[(i64)J * ng + g];
+    rho[g] = v;
+  }
+}
+
 int resident_workgroups(const void *kernel, int block = kBlock) {
   static std::mutex mu;
   static std::map<std::pair<const void *, int>, int> cache;
@@ -2540,16 +2618,16 @@ hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, 
 }
 
 hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
-                                   double *info, double *ws, hipStream_t s) {
+                                   double *info, double *ws, hipStream_t s, int outs) {
   if (N <= 128) {
     hipLaunchKernelGGL((k_chol_blocked<true, 512>), dim3(1), dim3(512), 0, s, G, N, Minv, D32,
-                       D64, info, ws);
+                       D64, info, ws, outs);
     return hipGetLastError();
   }
   // above 128 orbitals: the workspace variant (the library admits at most 512)
   if (N > 512 || ws == nullptr) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_chol_blocked<false, 1024>), dim3(1), dim3(1024), 0, s, G, N, Minv, D32,
-                     D64, info, ws);
+                     D64, info, ws, outs);
   return hipGetLastError();
 }
 
@@ -2576,7 +2654,7 @@ hipError_t launch_combine_factors(const double *A, const double *B, double *M, d
 template <typename T>
 hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, int N, i64 ng,
                               const double *occ, double *rho, hipStream_t s,
-                              const double *ginfo, void *split_ws) {
+                              const double *ginfo, void *split_ws, double *rho_part) {
   if (N <= 128) {
     const int NT = (N + 15) / 16;
     constexpr int GC = sizeof(T) == 4 ? 32 : 16;
@@ -2599,7 +2677,16 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
 #undef POU_APPLY_SMALL
     return hipGetLastError();
   }
-  if (rho != nullptr) return hipErrorInvalidValue;  // density is fused for N <= 128 only
+  // above 128 orbitals the density goes through the row blocks' partials
+  if (rho != nullptr && rho_part == nullptr) return hipErrorInvalidValue;
+  double *rhop = rho != nullptr ? rho_part : nullptr;
+  const int nJr = (N + kBB - 1) / kBB;
+  auto rho_sum = [&]() {
+    if (rho == nullptr) return;
+    const int blocks = (int)std::min<i64>(2048, (ng + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_rho_sum, dim3(blocks), dim3(kBlock), 0, s, (const double *)rho_part,
+                       nJr, ng, rho);
+  };
   if (sizeof(T) == 4) {
     const int nJ = (N + kBB - 1) / kBB;
     const i64 npt = (ng + kBB - 1) / kBB;
@@ -2612,10 +2699,11 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
                        Dh, Dl);
     if ((ng & 3) == 0)
       hipLaunchKernelGGL(k_apply_big<true>, dim3((unsigned)grid), dim3(kAT), 0, s, Dh, Dl, ginfo,
-                         (const float *)X, (float *)out, N, ng);
+                         (const float *)X, (float *)out, N, ng, occ, rhop);
     else
       hipLaunchKernelGGL(k_apply_big<false>, dim3((unsigned)grid), dim3(kAT), 0, s, Dh, Dl, ginfo,
-                         (const float *)X, (float *)out, N, ng);
+                         (const float *)X, (float *)out, N, ng, occ, rhop);
+    rho_sum();
     return hipGetLastError();
   }
   {
@@ -2624,7 +2712,8 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
     const i64 grid = ((npt + 7) / 8) * 8 * nJ;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_apply_big64, dim3((unsigned)grid), dim3(kAB), 0, s, (const double *)D,
-                       (const double *)X, (double *)out, N, ng);
+                       (const double *)X, (double *)out, N, ng, occ, rhop);
+    rho_sum();
     return hipGetLastError();
   }
 }
@@ -2641,10 +2730,10 @@ template hipError_t launch_gram_partial<float>(const float *, int, i64, int, dou
                                                hipStream_t);
 template hipError_t launch_apply_lower<double>(const double *, const double *, const double *,
                                                double *, int, i64, const double *, double *,
-                                               hipStream_t, const double *, void *);
+                                               hipStream_t, const double *, void *, double *);
 template hipError_t launch_apply_lower<float>(const double *, const float *, const float *,
                                               float *, int, i64, const double *, double *,
-                                              hipStream_t, const double *, void *);
+                                              hipStream_t, const double *, void *, double *);
 
 
 int cross_gram_split(int N) {

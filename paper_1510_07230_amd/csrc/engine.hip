@@ -99,6 +99,7 @@ struct pou_ctx {
   double *d_D64 = nullptr;
   float *d_D32 = nullptr;
   void *d_fsplit = nullptr;  // BF16 pieces of the factor (FP32 orbitals, N > 128)
+  double *d_rhopart = nullptr;  // per-128-row-block density shares (N > 128)
   double *d_cholws = nullptr;  // blocked Cholesky tiles when N > 128
   double *d_red = nullptr;     // small reduction outputs
   double *d_S = nullptr, *d_P = nullptr, *d_xpart = nullptr;  // subspace rotation / residual
@@ -212,6 +213,7 @@ void free_all(pou_ctx *c) {
   c->d_D64 = nullptr;
   c->d_D32 = nullptr;
   c->d_fsplit = nullptr;
+  c->d_rhopart = nullptr;
   c->d_cholws = nullptr;
   c->d_rep[0] = c->d_rep[1] = nullptr;
   c->d_HW = c->d_HWt = c->d_Wt = c->d_W1 = c->d_W2 = nullptr;
@@ -508,14 +510,13 @@ pou_status gram(pou_ctx *c, const T *X, bool bf16) {
 
 // Cholesky-QR passes of X into out (X and out distinct, both not aliasing d_W1).
 // info[2p], info[2p+1] = (not-SPD flag, max|G-I|) of pass p.  The last apply
-// also forms rho when rho != nullptr and the fused path is available.
+// also forms rho when want_rho.
 template <typename T>
 pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info, bool want_rho,
                        bool *rho_done) {
   hipStream_t s = c->stream;
   const bool mixed = sizeof(T) == 4;
   const T *cur = X;
-  const bool fused_ok = ((c->N + 15) / 16 + 7) / 8 == 1;
   *rho_done = false;
   for (int p = 0; p < passes; ++p) {
     // BF16 Gram only for the first of two passes: a single pass must be
@@ -526,9 +527,10 @@ pou_status orth_passes(pou_ctx *c, const T *X, T *out, int passes, double *info,
     const bool last = (p == passes - 1);
     T *dst = last ? out : (T *)c->d_W1;
     if (cur == dst) return fail(c, POU_ERR_ARG, "internal: aliasing orth buffers");
-    double *rho = (last && want_rho && fused_ok) ? c->d_rho : nullptr;
+    double *rho = (last && want_rho) ? c->d_rho : nullptr;
     KL(POU_K_APPLY, pou::launch_apply_lower<T>(c->d_Minv, dmat<T>(c), cur, dst, c->N, c->ng, c->d_occ,
-                                               rho, s, info + 2 * p, c->d_fsplit));
+                                               rho, s, info + 2 * p, c->d_fsplit,
+                                               c->d_rhopart));
     if (rho) *rho_done = true;
     cur = dst;
   }
@@ -548,8 +550,12 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
                                            (T *)c->d_Wt, c->N, c->ng, c->nsplit,
                                            mixed && passes == 2, c->d_gpart, s));
   KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
+  // with two passes the first factor feeds the second pass's Gram (FP32 D
+  // for the mixed fused apply, FP64 D otherwise) and the factor product (M)
+  const int outs1 = passes == 2 ? pou::CHOL_OUT_MINV | (mixed ? pou::CHOL_OUT_D32 : pou::CHOL_OUT_D64)
+                                : pou::CHOL_OUT_ALL;
   KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv, c->d_D32, c->d_D64, c->N,
-                                                  info, c->d_cholws, s));
+                                                  info, c->d_cholws, s, outs1));
   if (passes == 2) {
     if (mixed) {
       // W1 = Wt L1^-T stays on chip: only its Gram leaves the kernel
@@ -564,7 +570,8 @@ pou_status trial_orth_fused(pou_ctx *c, const T *W, double tscale, double *info)
     }
     KL(POU_K_CHOLESKY, pou::launch_gram_reduce(c->d_gpart, c->N, c->nsplit, c->dv, c->d_G, s));
     KL(POU_K_CHOLESKY, pou::launch_cholesky_inverse(c->d_G, c->d_Minv2, c->d_D32, c->d_D64, c->N,
-                                                    info + 2, c->d_cholws, s));
+                                                    info + 2, c->d_cholws, s,
+                                                    pou::CHOL_OUT_MINV));
     KL(POU_K_CHOLESKY, pou::launch_combine_factors(c->d_Minv2, c->d_Minv, c->d_Mcomb, c->d_D64,
                                                    c->d_D32, c->N, mixed, s));
   }
@@ -1343,6 +1350,8 @@ pou_status pou_set_system(pou_ctx *c, const pou_grid *grid, int natoms, const do
   CHK(dalloc(c, &c->d_D32, sizeof(float) * (size_t)norb * norb));
   if (c->es == 4 && norb > 128)
     CHK(dalloc(c, &c->d_fsplit, 2 * sizeof(uint16_t) * pou::split_factor_elems(norb)));
+  if (norb > 128)
+    CHK(dalloc(c, &c->d_rhopart, sizeof(double) * (size_t)((norb + 127) / 128) * c->ng));
   if (pou::chol_workspace_doubles(norb) > 0)
     CHK(dalloc(c, &c->d_cholws, sizeof(double) * pou::chol_workspace_doubles(norb)));
   CHK(dalloc(c, &c->d_G, sizeof(double) * (size_t)norb * norb));

@@ -231,11 +231,14 @@ hipError_t launch_combine_factors(const double *A, const double *B, double *M, d
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s);
 // Cholesky G = L L^T and Minv = L^-1 (lower), plus D = Minv - I in FP64 and
-// FP32.  info[0] = 1.0 if G is not numerically SPD else 0.0; info[1] =
-// max |G - I|.  Single workgroup; N <= 512, and above 128 the global
-// workspace ws of chol_workspace_doubles(N) doubles is required.
+// FP32; outs (CHOL_OUT_* bits) names the outputs written.  info[0] = 1.0 if G
+// is not numerically SPD else 0.0; info[1] = max |G - I|.  Single workgroup;
+// N <= 512, and above 128 the global workspace ws of chol_workspace_doubles(N)
+// doubles is required.
+enum { CHOL_OUT_MINV = 1, CHOL_OUT_D64 = 2, CHOL_OUT_D32 = 4, CHOL_OUT_ALL = 7 };
 hipError_t launch_cholesky_inverse(double *G, double *Minv, float *D32, double *D64, int N,
-                                   double *info, double *ws, hipStream_t s);
+                                   double *info, double *ws, hipStream_t s,
+                                   int outs = CHOL_OUT_ALL);
 // doubles of global workspace the blocked Cholesky needs for N > 128
 size_t chol_workspace_doubles(int N);
 // doubles needed by the Gram partial buffer
@@ -261,7 +264,9 @@ int gram_split(int N, bool fp32);
 // X + D X from D = M - I in the element type (FP32 with N > 128 multiplies on
 // split-BF16 MFMA, FP64 on FP64 MFMA); M itself is read only for the
 // split-BF16 kernel's far-from-identity form below.
-// When rho is non-null (N <= 128 only) also rho[g] = sum_j occ_j out[j][g]^2.
+// When rho is non-null also rho[g] = sum_j occ_j out[j][g]^2 (FP64); for
+// N > 128 this needs rho_part, device memory for ceil(N / 128) * ng doubles
+// (each 128-row block's share, summed in block order).
 // ginfo (device, nullable): the Cholesky report of the Gram M came from; the
 // split-BF16 kernel multiplies by M itself instead of adding D X to X when
 // ginfo[1] = max |G - I| >= 0.25 (a factor far from the identity).  split_ws:
@@ -270,7 +275,8 @@ int gram_split(int N, bool fp32);
 template <typename T>
 hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, int N, i64 ng,
                               const double *occ, double *rho, hipStream_t s,
-                              const double *ginfo = nullptr, void *split_ws = nullptr);
+                              const double *ginfo = nullptr, void *split_ws = nullptr,
+                              double *rho_part = nullptr);
 // BF16 values in each piece of the padded factor split for N > 128
 size_t split_factor_elems(int N);
 
