@@ -42,7 +42,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GROUP_KERNELS = {
     "trial": ("k_gram_small_bf16<8, 32, true>", "dense_kernels.hip"),
     "apply_gram": ("k_apply_gram8<8>", "dense_kernels.hip"),
-    "apply": ("k_apply_small<float, 8, 32>", "dense_kernels.hip"),
+    "apply": ("k_apply_s3<8>", "dense_kernels.hip"),
     "hamiltonian": ("k_hamiltonian<float>", "grid_kernels.hip"),
     "commit": ("k_commit<float>", "grid_kernels.hip"),
 }

@@ -440,7 +440,37 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
     __syncthreads();
   }
   // outputs named in outs (CHOL_OUT_*): the single workgroup's stores are a
-  // large part of the kernel, so callers ask only for what they read
+  // large part of the kernel, so callers ask only for what they read.  For
+  // even N <= 128 each lane takes a column pair of four rows at a time, all
+  // LDS reads ahead of the stores.
+  if (LDS_TILES && (N & 1) == 0) {
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
+    typedef float flt2 __attribute__((ext_vector_type(2)));
+    const int c = 2 * l;
+    for (int r0 = w; r0 < N; r0 += 4 * NW) {
+      dbl2 vv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + NW * u;
+        const double *tp = slot + tri_slot(r >> 4, c >> 4) * kTile + (r & 15) * kTP + (c & 15);
+        const bool in = r < N && c < N;
+        vv[u][0] = (in && c <= r) ? tp[0] : 0.0;
+        vv[u][1] = (in && c + 1 <= r) ? tp[1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + NW * u;
+        if (r >= N || c >= N) continue;
+        const i64 e = (i64)r * N + c;
+        const dbl2 d = dbl2{vv[u][0] - (r == c ? 1.0 : 0.0), vv[u][1] - (r == c + 1 ? 1.0 : 0.0)};
+        if (outs & CHOL_OUT_MINV) *(dbl2 *)(Minv + e) = vv[u];
+        if (outs & CHOL_OUT_D64) *(dbl2 *)(D64 + e) = d;
+        if (outs & CHOL_OUT_D32) *(flt2 *)(D32 + e) = flt2{(float)d[0], (float)d[1]};
+      }
+    }
+    if (t == 0) info[0] = sbad ? 1.0 : 0.0;
+    return;
+  }
   for (int r = w; r < N; r += NW) {
     for (int c = l; c < N; c += 64) {
       const double v =
@@ -758,75 +788,99 @@ __device__ inline void apply_load_a(const T *__restrict__ D, int N, T (&a0)[4 * 
   }
 }
 
-// out[j][g] = X[j][g] + sum_{i<=j} D[j][i] X[i][g] with D = L^-1 - I (lower
-// triangular, N <= 128).  Wave W owns the row tiles W and 7 - W; the whole
-// block loop is instantiated per wave so the wave keeps in registers only
-// the D fragments of its triangle (4(W+1) + 4(8-W) = 36 k-steps for NT = 8)
-// for the whole launch.  The workgroup walks over blocks of GC grid points,
-// staging each X block in LDS while the next one is loaded into registers.
-// Blocks with every row and point inside the problem take a path with no
-// per-element tests; the tail block tests each element.  Optional fused
-// density rho[g] = sum_j occ_j out[j][g]^2 (FP64 accumulation): each wave
-// leaves its partial of a block in LDS and the partials are summed after the
-// next block's first barrier, so the density adds no barrier of its own.
-template <typename T, int NT, int GC, int W>
-__device__ __attribute__((always_inline)) inline void apply_small_body(const T *__restrict__ D, const T *__restrict__ X,
-                                        T *__restrict__ out, int N, i64 ng,
-                                        const double *__restrict__ occ, double *__restrict__ rho,
-                                        T (*xs)[GC + 1], double (*srho)[4][GC]) {
-  constexpr int ROWS = 16 * NT;
-  constexpr int RSTEP = kBlock / GC;
-  constexpr int PER = ROWS / RSTEP;  // ROWS is a multiple of 16 and RSTEP divides 16
-  static_assert(PER * RSTEP == ROWS, "loader rows must tile the block");
-  constexpr int NC = GC / 16;
+// FP32 value as three BF16 pieces, v = hi + mid + lo exactly (each split
+// takes the next 8 significant bits; barring underflow of lo, the three carry
+// all 24 bits of the FP32 significand).
+__device__ inline void split3_bf16(float v, __bf16 &hi, __bf16 &mid, __bf16 &lo) {
+  hi = (__bf16)v;
+  const float r1 = v - (float)hi;
+  mid = (__bf16)r1;
+  lo = (__bf16)(r1 - (float)mid);
+}
+
+constexpr int kS3P = 136;  // LDS pitch (BF16) of a point's 128 orbitals: 16-byte aligned rows
+constexpr int kS3X = 36;   // LDS pitch (FP32) of an orbital's 32 points
+
+// FP32 apply for N <= 128 on BF16 MFMA: out = X + D X with D = L^-1 - I
+// (FP32, lower triangular), both operands split into three BF16 pieces.  Of
+// the nine piece products the six down to 2^-16 of the leading one are
+// summed (smallest first) in the FP32 accumulator; the three dropped are at
+// most 2^-24 relative, so the product keeps the accuracy of an FP32
+// contraction at 3/8 of the FP32 matrix-core cycles (six 16x16x32 BF16
+// products against eight 16x16x4 FP32 ones per 32 orbitals).  Four waves,
+// wave W owning row tiles W and 7 - W (which balances the triangle); the
+// workgroup walks 32-point blocks staged in LDS (FP32 for the identity term
+// and the three pieces transposed to [point][orbital] for the MFMA B operand)
+// while the next block is loaded.  Optional fused density rho[g] = sum_j
+// occ_j out[j][g]^2 (FP64): each wave leaves its partial of a block in LDS and
+// the partials are summed after the next block's first barrier.  The FP32
+// block has a row pitch of 36 floats: the epilogue's reads (four rows apart
+// across lane groups) then fall in distinct banks, and so do the loader's
+// writes, whose wave halves take rows eight apart.
+template <int NT, int W>
+__device__ __attribute__((always_inline)) inline void apply_s3_body(
+    const float *__restrict__ D, const float *__restrict__ X, float *__restrict__ out, int N,
+    i64 ng, const double *__restrict__ occ, double *__restrict__ rho, float (*xs)[kS3X],
+    __bf16 (*xp)[32][kS3P], double (*srho)[4][32]) {
+  constexpr int GC = 32, NC = 2;
+  constexpr int NOG = 2 * ((NT + 1) / 2);  // 16-orbital loader groups: whole 32-orbital chunks
   constexpr int jt0 = W, jt1 = 7 - W;
-  constexpr int ke0 = jt0 < NT ? 4 * (jt0 + 1) : 0;
-  constexpr int ke1 = jt1 < NT ? 4 * (jt1 + 1) : 0;
-  constexpr int ke = ke0 > ke1 ? ke0 : ke1;
-  typedef typename AccOf<T>::type Acc;
+  constexpr int kc0 = jt0 < NT ? (16 * jt0 + 15) / 32 + 1 : 0;  // chunks reaching row tile jt0
+  constexpr int kc1 = jt1 < NT ? (16 * jt1 + 15) / 32 + 1 : 0;
+  constexpr int kcm = kc0 > kc1 ? kc0 : kc1;
   const int t = threadIdx.x;
   const int l = t & 63, r16 = l & 15, q = l >> 4;
-  // D fragments: a0[ks] = D[16 jt0 + r16][4 ks + q], only k-steps of the triangle
-  T a0[ke0 > 0 ? ke0 : 1], a1[ke1 > 0 ? ke1 : 1];
+  // D fragments (A operand): row 16 jt + r16, orbitals 32 kc + 8 q .. + 7
+  bf8 d0[kc0 > 0 ? kc0 : 1][3], d1[kc1 > 0 ? kc1 : 1][3];
+  auto load_d = [&](bf8 (*d)[3], int jt, int nkc) __attribute__((always_inline)) {
+    const int j = 16 * jt + r16;
+    for (int kc = 0; kc < nkc; ++kc) {
 #pragma unroll
-  for (int ks = 0; ks < ke0; ++ks) {
-    const int i = 4 * ks + q, j = 16 * jt0 + r16;
-    a0[ks] = (j < N && i < N) ? D[(i64)j * N + i] : (T)0;
-  }
-#pragma unroll
-  for (int ks = 0; ks < ke1; ++ks) {
-    const int i = 4 * ks + q, j = 16 * jt1 + r16;
-    a1[ks] = (j < N && i < N) ? D[(i64)j * N + i] : (T)0;
-  }
-  // occupations of the rows this lane writes
+      for (int e = 0; e < 8; ++e) {
+        const int i = 32 * kc + 8 * q + e;
+        const float v = (j < N && i < N) ? D[(i64)j * N + i] : 0.0f;
+        __bf16 a, b, c;
+        split3_bf16(v, a, b, c);
+        d[kc][0][e] = a;
+        d[kc][1][e] = b;
+        d[kc][2][e] = c;
+      }
+    }
+  };
+  if (kc0 > 0) load_d(d0, jt0, kc0);
+  if (kc1 > 0) load_d(d1, jt1, kc1);
   double occv[2][4];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int jt = u == 0 ? jt0 : jt1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j = 16 * jt + out_row<T>(q, r);
+      const int j = 16 * jt + 4 * q + r;
       occv[u][r] = (rho != nullptr && jt < NT && j < N) ? occ[j] : 0.0;
     }
   }
-  const bool all_rows = N == ROWS;
+  // loader: point col; orbitals 32 wv + 8 hf + e and 32 wv + 16 + 8 hf + e
+  // (e < 8) for wave wv and wave half hf; rows past N load as zero
+  const bool all_rows = N == 16 * NOG;
   const i64 nblk = (ng + GC - 1) / GC;
-  const int col = t % GC, row0 = t / GC;
-  T nxt[PER];
-  auto load = [&](i64 blk) __attribute__((always_inline)) {
+  const int col = t & 31, hf = (t >> 5) & 1, wv = t >> 6;
+  const bool loader = 2 * wv < NOG;
+  auto lrow = [&](int e) { return 32 * wv + 8 * hf + (e < 8 ? e : e + 8); };
+  float na[16];
+  auto load = [&](float (&dst)[16], i64 blk) __attribute__((always_inline)) {
+    if (!loader) return;
     const i64 g = blk * GC + col;
     if (all_rows && blk * GC + GC <= ng) {
 #pragma unroll
-      for (int e = 0; e < PER; ++e) nxt[e] = X[(i64)(row0 + RSTEP * e) * ng + g];
+      for (int e = 0; e < 16; ++e) dst[e] = X[(i64)lrow(e) * ng + g];
     } else {
 #pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int row = row0 + RSTEP * e;
-        nxt[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : (T)0;
+      for (int e = 0; e < 16; ++e) {
+        const int row = lrow(e);
+        dst[e] = (row < N && g < ng) ? X[(i64)row * ng + g] : 0.0f;
       }
     }
   };
-  // density of the previous block still to be summed from srho[buf ^ 1]
   auto flush_rho = [&](i64 pblk, int pbuf) __attribute__((always_inline)) {
     if (t < GC) {
       const i64 g = pblk * GC + t;
@@ -837,32 +891,56 @@ __device__ __attribute__((always_inline)) inline void apply_small_body(const T *
   i64 pending = -1;
   int buf = 0;
   i64 blk = blockIdx.x;
-  if (blk < nblk) load(blk);
-  for (; blk < nblk; blk += gridDim.x) {
+  const i64 G = gridDim.x;
+  if (blk < nblk) load(na, blk);
+  for (; blk < nblk; blk += G) {
     __syncthreads();
     if (rho != nullptr && pending >= 0) flush_rho(pending, buf ^ 1);
+    if (loader) {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) xs[row0 + RSTEP * e][col] = nxt[e];
+      for (int e = 0; e < 16; ++e) xs[lrow(e)][col] = na[e];
+#pragma unroll
+      for (int hlf = 0; hlf < 2; ++hlf) {
+        bf8 vh, vm, vl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 a, b, c;
+          split3_bf16(na[8 * hlf + e], a, b, c);
+          vh[e] = a;
+          vm[e] = b;
+          vl[e] = c;
+        }
+        const int o = lrow(8 * hlf);
+        *(bf8 *)&xp[0][col][o] = vh;
+        *(bf8 *)&xp[1][col][o] = vm;
+        *(bf8 *)&xp[2][col][o] = vl;
+      }
+    }
     __syncthreads();
-    if (blk + gridDim.x < nblk) load(blk + gridDim.x);
-    Acc acc0[NC], acc1[NC];
+    if (blk + G < nblk) load(na, blk + G);
+    f4 acc0[NC], acc1[NC];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
-      acc0[cc] = Acc{0, 0, 0, 0};
-      acc1[cc] = Acc{0, 0, 0, 0};
+      acc0[cc] = f4{0, 0, 0, 0};
+      acc1[cc] = f4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int ks = 0; ks < ke; ++ks) {
-      T b[NC];
+    for (int kc = 0; kc < kcm; ++kc) {
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) b[cc] = xs[4 * ks + q][16 * cc + r16];
-      if (ks < ke0) {
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) acc0[cc] = mfma(a0[ks], b[cc], acc0[cc]);
-      }
-      if (ks < ke1) {
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) acc1[cc] = mfma(a1[ks], b[cc], acc1[cc]);
+      for (int cc = 0; cc < NC; ++cc) {
+        const bf8 bh = *(const bf8 *)&xp[0][16 * cc + r16][32 * kc + 8 * q];
+        const bf8 bm = *(const bf8 *)&xp[1][16 * cc + r16][32 * kc + 8 * q];
+        const bf8 bl = *(const bf8 *)&xp[2][16 * cc + r16][32 * kc + 8 * q];
+        auto prod = [&](const bf8 (&a)[3], f4 c) __attribute__((always_inline)) {
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bm, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], bh, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bl, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], bh, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bm, c, 0, 0, 0);
+          return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bh, c, 0, 0, 0);
+        };
+        if (kc < kc0) acc0[cc] = prod(d0[kc], acc0[cc]);
+        if (kc < kc1) acc1[cc] = prod(d1[kc], acc1[cc]);
       }
     }
     const i64 g0 = blk * GC;
@@ -879,8 +957,8 @@ __device__ __attribute__((always_inline)) inline void apply_small_body(const T *
           const i64 g = g0 + 16 * cc + r16;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int j = 16 * jt + out_row<T>(q, r);
-            const T v = xs[j][16 * cc + r16] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
+            const int j = 16 * jt + 4 * q + r;
+            const float v = xs[j][16 * cc + r16] + (u == 0 ? acc0[cc][r] : acc1[cc][r]);
             if (!decltype(tested)::value || (j < N && g < ng)) {
               out[(i64)j * ng + g] = v;
               rp[cc] += occv[u][r] * ((double)v * (double)v);
@@ -911,20 +989,20 @@ __device__ __attribute__((always_inline)) inline void apply_small_body(const T *
   }
 }
 
-template <typename T, int NT, int GC>
-__global__ __launch_bounds__(kBlock) void k_apply_small(const T *__restrict__ D,
-                                                        const T *__restrict__ X,
-                                                        T *__restrict__ out, int N, i64 ng,
-                                                        const double *__restrict__ occ,
-                                                        double *__restrict__ rho) {
-  __shared__ T xs[16 * NT][GC + 1];
-  __shared__ double srho[2][4][GC];
-  // every wave runs the same block loop with the same barriers
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_apply_s3(const float *__restrict__ D,
+                                                     const float *__restrict__ X,
+                                                     float *__restrict__ out, int N, i64 ng,
+                                                     const double *__restrict__ occ,
+                                                     double *__restrict__ rho) {
+  __shared__ float xs[16 * 2 * ((NT + 1) / 2)][kS3X];
+  __shared__ __attribute__((aligned(16))) __bf16 xp[3][32][kS3P];
+  __shared__ double srho[2][4][32];
   switch (threadIdx.x >> 6) {
-    case 0: apply_small_body<T, NT, GC, 0>(D, X, out, N, ng, occ, rho, xs, srho); break;
-    case 1: apply_small_body<T, NT, GC, 1>(D, X, out, N, ng, occ, rho, xs, srho); break;
-    case 2: apply_small_body<T, NT, GC, 2>(D, X, out, N, ng, occ, rho, xs, srho); break;
-    default: apply_small_body<T, NT, GC, 3>(D, X, out, N, ng, occ, rho, xs, srho); break;
+    case 0: apply_s3_body<NT, 0>(D, X, out, N, ng, occ, rho, xs, xp, srho); break;
+    case 1: apply_s3_body<NT, 1>(D, X, out, N, ng, occ, rho, xs, xp, srho); break;
+    case 2: apply_s3_body<NT, 2>(D, X, out, N, ng, occ, rho, xs, xp, srho); break;
+    default: apply_s3_body<NT, 3>(D, X, out, N, ng, occ, rho, xs, xp, srho); break;
   }
 }
 
@@ -952,8 +1030,8 @@ __device__ inline void apply_cc(const T (*xs)[PITCH], const T (&a0)[4 * NT],
   }
 }
 
-// The 8-wave form of k_apply_small: out[j][g] = X[j][g] + sum_{i<=j} D[j][i]
-// X[i][g], D = L^-1 - I (N <= 128), optional fused density.  Wave w = (pair
+// FP64 apply for N <= 128: out[j][g] = X[j][g] + sum_{i<=j} D[j][i] X[i][g],
+// D = L^-1 - I, on FP64 MFMA, optional fused density.  Wave w = (pair
 // p = w % 4, half h = w / 4) owns row tiles p and 7 - p (36 k-steps of 4 for
 // every pair) and the 16-point column group h of each 32-point block, so a
 // wave keeps half the accumulators of the 4-wave form and twice as many
@@ -1120,11 +1198,13 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
                                                      double *__restrict__ part) {
   constexpr int GC = 32;
   constexpr int ROWS = 16 * NT;
-  constexpr int PITCH = GC + 1;
+  // FP32 pitch 36: the loader's writes (wave halves eight rows apart) and the
+  // 16-byte identity reads below fall in distinct banks
+  constexpr int PITCH = GC + 4;
   constexpr int PB = GC + 8;        // W1 pieces: [orbital][point]
   constexpr int NCH = (ROWS + 31) / 32;  // K chunks of 32 orbitals
   constexpr int PX = 32 * NCH + 8;       // X pieces: [point][orbital], 16-byte aligned rows
-  __shared__ float xs[ROWS][PITCH];
+  __shared__ __attribute__((aligned(16))) float xs[ROWS][PITCH];
   __shared__ __attribute__((aligned(16))) __bf16 xh[GC][PX];
   __shared__ __attribute__((aligned(16))) __bf16 xl[GC][PX];
   __shared__ __attribute__((aligned(16))) __bf16 hs[ROWS][PB];
@@ -1237,8 +1317,10 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
       const int j = 16 * jt + r16;
       const int p0 = 16 * h + 4 * q;
       __bf16 h4[4], l4[4];
+      const float4 x4 = *(const float4 *)&xs[j][p0];
+      const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) split_bf16(xs[j][p0 + r] + acc[u][r], h4[r], l4[r]);
+      for (int r = 0; r < 4; ++r) split_bf16(xv[r] + acc[u][r], h4[r], l4[r]);
       typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
       *(bf4 *)&hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
       *(bf4 *)&ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
@@ -2662,10 +2744,10 @@ hipError_t launch_apply_lower(const double *M, const T *D, const T *X, T *out, i
     // FP32: the 4-wave kernel (measured faster); FP64: the 8-wave kernel
 #define POU_APPLY_SMALL(K)                                                                    \
   if (sizeof(T) == 4) {                                                                       \
-    const int grid = (int)std::min<i64>(                                                      \
-        nblk, resident_workgroups((const void *)k_apply_small<T, K, GC>));                    \
-    hipLaunchKernelGGL((k_apply_small<T, K, GC>), dim3(grid), dim3(kBlock), 0, s, D, X, out,   \
-                       N, ng, occ, rho);                                                      \
+    const int grid =                                                                          \
+        (int)std::min<i64>(nblk, resident_workgroups((const void *)k_apply_s3<K>));           \
+    hipLaunchKernelGGL((k_apply_s3<K>), dim3(grid), dim3(kBlock), 0, s, (const float *)D,     \
+                       (const float *)X, (float *)out, N, ng, occ, rho);                      \
   } else {                                                                                    \
     const i64 nb8 = (ng + 31) / 32;                                                           \
     const int grid =                                                                          \
