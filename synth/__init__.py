@@ -115,9 +115,10 @@ def occupations(cfg: Config):
     return np.full(cfg.norb, float(cfg.occ))
 
 
-def orbitals(cfg: Config, dtype=np.float64):
-    """Raw (not orthonormal) start block, shape [N, n, n, n] (z, y, x; x fastest)."""
-    rng = np.random.default_rng(2000 + cfg.cfg_id)
+def orbitals(cfg: Config, dtype=np.float64, variant=0):
+    """Raw (not orthonormal) start block, shape [N, n, n, n] (z, y, x; x fastest).
+    variant > 0 draws another start of the same kind (other coefficients)."""
+    rng = np.random.default_rng(2000 + cfg.cfg_id + 7919 * variant)
     n, N = cfg.n, cfg.norb
     if cfg.start == "random":
         U = rng.standard_normal((N, n, n, n))
