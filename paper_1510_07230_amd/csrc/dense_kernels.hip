@@ -1146,50 +1146,54 @@ __global__ __launch_bounds__(kAB) void k_apply8(const T *__restrict__ D, const T
 
 // Gram tiles u in [U0, U1) of pair W (GramTile ownership: row tile W with
 // column tiles W..7, then row tile 7 - W with 7 - W..7) over one 32-point
-// chunk of W1 held in LDS as two BF16 pieces, W1 = hi + lo (hi = bf16(W1),
-// lo = bf16(W1 - hi)).  Each tile sums the four products lo lo^T, hi lo^T,
-// lo hi^T, hi hi^T in FP32 on BF16 MFMA (exact products, FP32 accumulation),
-// which leaves only the rounding of lo (2^-18 relative) and the FP32 sums; it
-// is flushed into FP64 per chunk.  All fragments are read first and the
-// products are issued product by product across the tiles, so the tiles'
-// accumulation chains are in flight together.
+// chunk of W1 held in LDS as three BF16 pieces, W1 = hi + mid + lo exactly
+// (split3_bf16).  Each tile sums the six piece products down to 2^-16 of the
+// leading one (mid mid^T, lo hi^T, hi lo^T, mid hi^T, hi mid^T, hi hi^T,
+// smallest first) in FP32 on BF16 MFMA, flushed into FP64 per chunk; the
+// dropped products are 2^-24 relative and uncorrelated from point to point.
+// Two pieces (16 significant bits) are not enough here: the residual's
+// correlation with W1 over the few thousand points where an orbital lives
+// leaves each diagonal entry off by ~5e-8 (1e-7 for the worst of 128
+// orbitals), which the factor then turns into the same departure of the new
+// block from orthonormality.  The fragments of two tiles are read ahead of
+// their products, so two accumulation chains are in flight together.
 template <int NT, int W, int U0, int U1, int PB>
-__device__ inline void gram_tiles_split(const __bf16 (*hs)[PB], const __bf16 (*ls)[PB],
-                                        double (&gd)[U1 - U0][4], int r16, int q) {
+__device__ inline void gram_tiles_split(const __bf16 (*hs)[PB], const __bf16 (*ms)[PB],
+                                        const __bf16 (*ls)[PB], double (&gd)[U1 - U0][4],
+                                        int r16, int q) {
   constexpr int NU = U1 - U0;
   constexpr int nfirst = 8 - W;
-  bf8 rh[NU], rl[NU], ch[NU], cl[NU];
-  bool ok[NU];
 #pragma unroll
-  for (int u = 0; u < NU; ++u) {
-    const int rt = U0 + u < nfirst ? W : 7 - W;
-    const int ct = U0 + u < nfirst ? W + U0 + u : (7 - W) + (U0 + u - nfirst);
-    ok[u] = rt < NT && ct < NT;
-    const int ri = ok[u] ? rt : 0, ci = ok[u] ? ct : 0;  // unused tiles read tile 0
-    rh[u] = *(const bf8 *)&hs[16 * ri + r16][8 * q];
-    rl[u] = *(const bf8 *)&ls[16 * ri + r16][8 * q];
-    ch[u] = *(const bf8 *)&hs[16 * ci + r16][8 * q];
-    cl[u] = *(const bf8 *)&ls[16 * ci + r16][8 * q];
+  for (int u0 = 0; u0 < NU; u0 += 2) {
+    bf8 rh[2], rm[2], rl[2], ch[2], cm[2], cl[2];
+    bool ok[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int u = u0 + v;
+      const int rt = U0 + u < nfirst ? W : 7 - W;
+      const int ct = U0 + u < nfirst ? W + U0 + u : (7 - W) + (U0 + u - nfirst);
+      ok[v] = u < NU && rt < NT && ct < NT;
+      const int ri = ok[v] ? rt : 0, ci = ok[v] ? ct : 0;  // unused tiles read tile 0
+      rh[v] = *(const bf8 *)&hs[16 * ri + r16][8 * q];
+      rm[v] = *(const bf8 *)&ms[16 * ri + r16][8 * q];
+      rl[v] = *(const bf8 *)&ls[16 * ri + r16][8 * q];
+      ch[v] = *(const bf8 *)&hs[16 * ci + r16][8 * q];
+      cm[v] = *(const bf8 *)&ms[16 * ci + r16][8 * q];
+      cl[v] = *(const bf8 *)&ls[16 * ci + r16][8 * q];
+    }
+    f4 c[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+#define POU_GP(A, B)                                                                   \
+  _Pragma("unroll") for (int v = 0; v < 2; ++v) if (ok[v]) c[v] =                     \
+      __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[v], B[v], c[v], 0, 0, 0);
+    POU_GP(rm, cm) POU_GP(rl, ch) POU_GP(rh, cl) POU_GP(rm, ch) POU_GP(rh, cm) POU_GP(rh, ch)
+#undef POU_GP
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      if (u0 + v >= NU) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gd[u0 + v][r] += (double)c[v][r];
+    }
   }
-  f4 c[NU];
-#pragma unroll
-  for (int u = 0; u < NU; ++u) c[u] = f4{0, 0, 0, 0};
-#pragma unroll
-  for (int u = 0; u < NU; ++u)
-    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl[u], cl[u], c[u], 0, 0, 0);
-#pragma unroll
-  for (int u = 0; u < NU; ++u)
-    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh[u], cl[u], c[u], 0, 0, 0);
-#pragma unroll
-  for (int u = 0; u < NU; ++u)
-    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rl[u], ch[u], c[u], 0, 0, 0);
-#pragma unroll
-  for (int u = 0; u < NU; ++u)
-    if (ok[u]) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rh[u], ch[u], c[u], 0, 0, 0);
-#pragma unroll
-  for (int u = 0; u < NU; ++u)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) gd[u][r] += (double)c[u][r];
 }
 
 template <int NT>
@@ -1208,6 +1212,7 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   __shared__ __attribute__((aligned(16))) __bf16 xh[GC][PX];
   __shared__ __attribute__((aligned(16))) __bf16 xl[GC][PX];
   __shared__ __attribute__((aligned(16))) __bf16 hs[ROWS][PB];
+  __shared__ __attribute__((aligned(16))) __bf16 ms[ROWS][PB];
   __shared__ __attribute__((aligned(16))) __bf16 ls[ROWS][PB];
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
@@ -1309,27 +1314,28 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
         acc[u] = c;
       }
     }
-    // W1 = X + (D X) as BF16 hi/lo pieces (rows beyond N are zero: X and D are)
+    // W1 = X + (D X) as three BF16 pieces (rows beyond N are zero: X and D are)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int jt = u == 0 ? jt0 : jt1;
       if (jt >= NT) continue;
       const int j = 16 * jt + r16;
       const int p0 = 16 * h + 4 * q;
-      __bf16 h4[4], l4[4];
+      __bf16 h4[4], m4[4], l4[4];
       const float4 x4 = *(const float4 *)&xs[j][p0];
       const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) split_bf16(xv[r] + acc[u][r], h4[r], l4[r]);
+      for (int r = 0; r < 4; ++r) split3_bf16(xv[r] + acc[u][r], h4[r], m4[r], l4[r]);
       typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
       *(bf4 *)&hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
+      *(bf4 *)&ms[j][p0] = bf4{m4[0], m4[1], m4[2], m4[3]};
       *(bf4 *)&ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
     }
     __syncthreads();
 #define POU_G8(P)                                                                      \
   case P:                                                                              \
-    if (h == 0) gram_tiles_split<NT, P, 0, 5, PB>(hs, ls, gd, r16, q);                 \
-    else gram_tiles_split<NT, P, 5, 9, PB>(hs, ls, *(double(*)[4][4]) & gd, r16, q); \
+    if (h == 0) gram_tiles_split<NT, P, 0, 5, PB>(hs, ms, ls, gd, r16, q);             \
+    else gram_tiles_split<NT, P, 5, 9, PB>(hs, ms, ls, *(double(*)[4][4]) & gd, r16, q); \
     break;
     switch (pw) { POU_G8(0) POU_G8(1) POU_G8(2) POU_G8(3) }
 #undef POU_G8

@@ -219,7 +219,12 @@ hipError_t launch_trial_gram(const T *W, const T *HW, const double *sig, const d
                              double tscale, T *Wt, int N, i64 ng, int nsplit, bool bf16,
                              double *part, hipStream_t s);
 // First Cholesky-QR pass fused with the second Gram (FP32, N <= 128): the
-// partial Gram of X + D32 X over nsplit workgroups into part (nothing else written)
+// partial Gram of W1 = X + D~ X over nsplit workgroups into part (nothing else
+// written), D~ the BF16 hi/lo split of D32, X in hi/lo pieces.  W1 enters the
+// Gram as three BF16 pieces, so the Gram is that of the on-chip W1 to FP32
+// accuracy; with two pieces (16 bits) the representation's residual leaves
+// the diagonal off by ~1e-7 for localised orbitals, and with it the
+// orthonormality of the block the combined factor produces.
 hipError_t launch_apply_gram(const float *D32, const float *X, int N, i64 ng, int nsplit,
                              double *part, hipStream_t s);
 // M = A B (lower-triangular), D64 = M - I, D32 = (float) D64; with split_b, B is
