@@ -241,8 +241,8 @@ def main():
     a = ap.parse_args()
     res = summarise(a.fetch, a.write, a.block, a.norb, a.n)
     cmds = [
-        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/fetch -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
-        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/write -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy",
+        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/fetch -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy --no-extras",
+        "cd /tmp && TMPDIR=/tmp rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/write -o run -- python3 $REPO/bench.py --steps 3 --warmup 1 --no-converge --no-cpu-baseline --calibrate-copy --no-extras",
         f"python -m paper_1510_07230_amd.counters $OUT/fetch/run_counter_collection.csv $OUT/write/run_counter_collection.csv {int(a.block)} --json profiles/traffic_mixed96.json --md profiles/traffic_mixed96.md",
     ]
     if a.json:
