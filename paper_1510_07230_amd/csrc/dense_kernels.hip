@@ -1208,12 +1208,22 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   constexpr int PB = GC + 8;        // W1 pieces: [orbital][point]
   constexpr int NCH = (ROWS + 31) / 32;  // K chunks of 32 orbitals
   constexpr int PX = 32 * NCH + 8;       // X pieces: [point][orbital], 16-byte aligned rows
-  __shared__ __attribute__((aligned(16))) float xs[ROWS][PITCH];
-  __shared__ __attribute__((aligned(16))) __bf16 xh[GC][PX];
-  __shared__ __attribute__((aligned(16))) __bf16 xl[GC][PX];
-  __shared__ __attribute__((aligned(16))) __bf16 hs[ROWS][PB];
-  __shared__ __attribute__((aligned(16))) __bf16 ms[ROWS][PB];
-  __shared__ __attribute__((aligned(16))) __bf16 ls[ROWS][PB];
+  // Two stages of each kind: block i is multiplied out of one X stage while
+  // block i + 1 is staged in the other, and the Gram of block i - 1 reads one
+  // W1 stage while block i's pieces go to the other, so one barrier per block
+  // separates every write from the reads of the same stage.
+  struct XStage {
+    float xs[ROWS][PITCH];
+    __bf16 xh[GC][PX];
+    __bf16 xl[GC][PX];
+  };
+  struct PStage {
+    __bf16 hs[ROWS][PB];
+    __bf16 ms[ROWS][PB];
+    __bf16 ls[ROWS][PB];
+  };
+  __shared__ __attribute__((aligned(16))) XStage xa, xb;
+  __shared__ __attribute__((aligned(16))) PStage pa, pb;
   const int t = threadIdx.x;
   const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
   const int pw = w & 3, h = w >> 2;
@@ -1223,8 +1233,10 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   if (32 * NCH > ROWS) {
     constexpr int PAD = 32 * NCH - ROWS;
     for (int e = t; e < GC * PAD; e += kAB) {
-      xh[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
-      xl[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
+      xa.xh[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
+      xa.xl[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
+      xb.xh[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
+      xb.xl[e / PAD][ROWS + e % PAD] = (__bf16)0.0f;
     }
   }
   // B operands: D^T fragments, lane = (output orbital 16 jt + r16, orbitals 32 kc + 8q .. +7)
@@ -1273,34 +1285,30 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
       }
     }
   };
-  i64 blk = blockIdx.x;
-  if (blk < nblk) load(na, blk);
-  if (blk + G < nblk) load(nb, blk + G);
-  for (; blk < nblk; blk += G) {
-    __syncthreads();
-    if (loader) {
-      bf8 vh, vl;
+  // X of one block into a stage: FP32 [orbital][point] for the identity term,
+  // BF16 hi/lo [point][orbital] for the products
+  auto stash = [&](XStage &xd) __attribute__((always_inline)) {
+    if (!loader) return;
+    bf8 vh, vl;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        xs[8 * rg + e][col] = na[e];
-        __bf16 a, b;
-        split_bf16(na[e], a, b);
-        vh[e] = a;
-        vl[e] = b;
-      }
-      *(bf8 *)&xh[col][8 * rg] = vh;
-      *(bf8 *)&xl[col][8 * rg] = vl;
+    for (int e = 0; e < 8; ++e) {
+      xd.xs[8 * rg + e][col] = na[e];
+      __bf16 a, b;
+      split_bf16(na[e], a, b);
+      vh[e] = a;
+      vl[e] = b;
     }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 8; ++e) na[e] = nb[e];
-    if (blk + 2 * G < nblk) load(nb, blk + 2 * G);
-    // (D X)^T for this wave's row tiles and points 16 h .. 16 h + 15
+    *(bf8 *)&xd.xh[col][8 * rg] = vh;
+    *(bf8 *)&xd.xl[col][8 * rg] = vl;
+  };
+  // W1 = X + (D X) for this wave's row tiles and points 16 h .. 16 h + 15, as
+  // three BF16 pieces (rows beyond N are zero: X and D are)
+  auto apply = [&](const XStage &xc, PStage &pd) __attribute__((always_inline)) {
     f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
 #pragma unroll
     for (int kc = 0; kc < NCH; ++kc) {
-      const bf8 ah = *(const bf8 *)&xh[16 * h + r16][32 * kc + 8 * q];
-      const bf8 al = *(const bf8 *)&xl[16 * h + r16][32 * kc + 8 * q];
+      const bf8 ah = *(const bf8 *)&xc.xh[16 * h + r16][32 * kc + 8 * q];
+      const bf8 al = *(const bf8 *)&xc.xl[16 * h + r16][32 * kc + 8 * q];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int jt = u == 0 ? jt0 : jt1;
@@ -1314,7 +1322,6 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
         acc[u] = c;
       }
     }
-    // W1 = X + (D X) as three BF16 pieces (rows beyond N are zero: X and D are)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int jt = u == 0 ? jt0 : jt1;
@@ -1322,23 +1329,64 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
       const int j = 16 * jt + r16;
       const int p0 = 16 * h + 4 * q;
       __bf16 h4[4], m4[4], l4[4];
-      const float4 x4 = *(const float4 *)&xs[j][p0];
+      const float4 x4 = *(const float4 *)&xc.xs[j][p0];
       const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
       for (int r = 0; r < 4; ++r) split3_bf16(xv[r] + acc[u][r], h4[r], m4[r], l4[r]);
       typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
-      *(bf4 *)&hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
-      *(bf4 *)&ms[j][p0] = bf4{m4[0], m4[1], m4[2], m4[3]};
-      *(bf4 *)&ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
+      *(bf4 *)&pd.hs[j][p0] = bf4{h4[0], h4[1], h4[2], h4[3]};
+      *(bf4 *)&pd.ms[j][p0] = bf4{m4[0], m4[1], m4[2], m4[3]};
+      *(bf4 *)&pd.ls[j][p0] = bf4{l4[0], l4[1], l4[2], l4[3]};
     }
-    __syncthreads();
-#define POU_G8(P)                                                                      \
-  case P:                                                                              \
-    if (h == 0) gram_tiles_split<NT, P, 0, 5, PB>(hs, ms, ls, gd, r16, q);             \
-    else gram_tiles_split<NT, P, 5, 9, PB>(hs, ms, ls, *(double(*)[4][4]) & gd, r16, q); \
+  };
+  auto gram = [&](const PStage &pc) __attribute__((always_inline)) {
+#define POU_G8(P)                                                                        \
+  case P:                                                                                \
+    if (h == 0) gram_tiles_split<NT, P, 0, 5, PB>(pc.hs, pc.ms, pc.ls, gd, r16, q);      \
+    else                                                                                 \
+      gram_tiles_split<NT, P, 5, 9, PB>(pc.hs, pc.ms, pc.ls, *(double(*)[4][4]) & gd, r16, q); \
     break;
     switch (pw) { POU_G8(0) POU_G8(1) POU_G8(2) POU_G8(3) }
 #undef POU_G8
+  };
+  // Invariant at the top of a step on block b: stage xc holds block b, na
+  // holds block b + G and nb has block b + 2G in flight; the other W1 stage
+  // holds block b - G when that exists.
+  auto step = [&](const XStage &xc, XStage &xn, PStage &pd, const PStage &pp, i64 b,
+                  bool prev) __attribute__((always_inline)) {
+    if (b + G < nblk) {
+      stash(xn);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) na[e] = nb[e];
+      if (b + 3 * G < nblk) load(nb, b + 3 * G);
+    }
+    apply(xc, pd);
+    if (prev) gram(pp);
+    __syncthreads();
+  };
+  i64 b = blockIdx.x;
+  if (b < nblk) {
+    load(na, b);
+    if (b + G < nblk) load(nb, b + G);
+    stash(xa);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) na[e] = nb[e];
+    if (b + 2 * G < nblk) load(nb, b + 2 * G);
+    __syncthreads();
+    for (bool prev = false;; prev = true) {
+      step(xa, xb, pa, pb, b, prev);
+      b += G;
+      if (b >= nblk) {
+        gram(pa);
+        break;
+      }
+      step(xb, xa, pb, pa, b, true);
+      b += G;
+      if (b >= nblk) {
+        gram(pb);
+        break;
+      }
+    }
   }
   double *outp = part + (i64)blockIdx.x * 128 * 128;
   const int u0 = h == 0 ? 0 : 5, nu = h == 0 ? 5 : 4;
