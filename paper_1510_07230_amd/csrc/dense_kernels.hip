@@ -1267,7 +1267,7 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   const int col = t % GC, rg = t / GC;  // rg < 16: orbitals 8 rg .. 8 rg + 7
   const bool loader = 8 * rg < ROWS;
   const i64 G = gridDim.x;
-  float na[8], nb[8];
+  float na[8] = {}, nb[8] = {};  // zero where no block is loaded into them
   // blocks with every row and point inside the problem load with no
   // per-element tests (the tests would put each load in a branch of its own)
   const bool all_rows = N == ROWS;
