@@ -643,6 +643,103 @@ __device__ inline void fft_stage(const double2 *a, double2 *b, int n, int lb, in
   }
 }
 
+// The same radix plan at compile time, for the transforms specialised on n.
+constexpr Radices factorize_c(int n) {
+  Radices f{};
+  f.nr = 0;
+  int m = n;
+  while (m % 4 == 0) { f.r[f.nr++] = 4; m /= 4; }
+  while (m % 2 == 0) { f.r[f.nr++] = 2; m /= 2; }
+  while (m % 3 == 0) { f.r[f.nr++] = 3; m /= 3; }
+  while (m % 5 == 0) { f.r[f.nr++] = 5; m /= 5; }
+  for (int p = 7; p * p <= m; p += 2)
+    while (m % p == 0) { f.r[f.nr++] = p; m /= p; }
+  if (m > 1) f.r[f.nr++] = m;
+  return f;
+}
+constexpr int radix_span(const Radices &f, int st) {
+  int p = 1;
+  for (int i = 0; i < st; ++i) p *= f.r[i];
+  return p;
+}
+
+// fft_stage with the line length, the batch, the radix and the span Ns known
+// at compile time: the same butterflies and twiddle indices, with the index
+// arithmetic folded into constants instead of run-time divisions.
+template <int N, int LB, int R, int NS>
+__device__ inline void fft_stage_c(const double2 *a, double2 *b, double sign, const double2 *tw) {
+  constexpr int NBF = N / R;
+  constexpr int STEP = N / (NS * R);
+  auto twid = [&](int idx) {
+    const double2 w = tw[idx];
+    return sign > 0.0 ? make_double2(w.x, -w.y) : w;
+  };
+#pragma unroll
+  for (int t0 = 0; t0 < LB * NBF; t0 += kBlock) {
+    const int t = t0 + (int)threadIdx.x;
+    if (LB * NBF % kBlock != 0 && t >= LB * NBF) break;
+    const int line = t / NBF;
+    const int j = t - line * NBF;
+    const double2 *src = a + line * N;
+    double2 *dst = b + line * N;
+    const int k = j % NS;
+    const int base = (j / NS) * NS * R + k;
+    const int m = k * STEP;
+    if constexpr (R == 4) {
+      double2 x0 = src[j], x1 = src[j + NBF], x2 = src[j + 2 * NBF], x3 = src[j + 3 * NBF];
+      if (k) {
+        x1 = cmul(x1, twid(m));
+        x2 = cmul(x2, twid(2 * m));
+        x3 = cmul(x3, twid(3 * m));
+      }
+      const double2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
+      const double2 s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3), sign);
+      dst[base] = cadd(s02, s13);
+      dst[base + NS] = cadd(d02, d13);
+      dst[base + 2 * NS] = csub(s02, s13);
+      dst[base + 3 * NS] = csub(d02, d13);
+    } else if constexpr (R == 2) {
+      double2 x0 = src[j], x1 = src[j + NBF];
+      if (k) x1 = cmul(x1, twid(m));
+      dst[base] = cadd(x0, x1);
+      dst[base + NS] = csub(x0, x1);
+    } else if constexpr (R == 3) {
+      double2 x0 = src[j], x1 = src[j + NBF], x2 = src[j + 2 * NBF];
+      if (k) {
+        x1 = cmul(x1, twid(m));
+        x2 = cmul(x2, twid(2 * m));
+      }
+      const double2 t1 = cadd(x1, x2);
+      const double2 t2 = cmuli(csub(x1, x2), sign * 0.86602540378443864676);
+      const double2 mm = make_double2(x0.x - 0.5 * t1.x, x0.y - 0.5 * t1.y);
+      dst[base] = cadd(x0, t1);
+      dst[base + NS] = cadd(mm, t2);
+      dst[base + 2 * NS] = csub(mm, t2);
+    } else {
+      for (int s = 0; s < R; ++s) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int tt = 0; tt < R; ++tt) {
+          const double2 x = src[j + tt * NBF];
+          acc = cadd(acc, cmul(x, twid((tt * m + ((s * tt) % R) * (N / R)) % N)));
+        }
+        dst[base + s * NS] = acc;
+      }
+    }
+  }
+}
+
+template <int N, int LB, int ST>
+__device__ inline double2 *fft_lines_c(double2 *a, double2 *b, double sign, const double2 *tw) {
+  constexpr Radices F = factorize_c(N);
+  if constexpr (ST == F.nr) {
+    return a;
+  } else {
+    fft_stage_c<N, LB, F.r[ST], radix_span(F, ST)>(a, b, sign, tw);
+    __syncthreads();
+    return fft_lines_c<N, LB, ST + 1>(b, a, sign, tw);
+  }
+}
+
 // Transform lb lines in LDS buffers a/b; returns the buffer holding the result.
 __device__ inline double2 *fft_lines(double2 *a, double2 *b, int n, int lb, Radices f,
                                      double sign, const double2 *tw) {
@@ -661,20 +758,29 @@ __device__ inline double2 *fft_lines(double2 *a, double2 *b, int n, int lb, Radi
 // mode 0: complex -> complex forward; 1: real input, forward; 2: inverse, real
 // output scaled by `scale`; 3: forward, multiply by scale / (Laplacian symbol),
 // inverse (z lines only); 4: complex -> complex inverse.  axis: 0 = x, 1 = y, 2 = z.
+// NC > 0: a transform specialised on n = NC (the n and lb arguments are then
+// NC and its batch); NC = 0: any n.
+template <int NC>
 __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
-                                                void *__restrict__ out, int n, int axis,
-                                                int lb, int mode, Radices f,
+                                                void *__restrict__ out, int n_arg, int axis,
+                                                int lb_arg, int mode, Radices f,
                                                 const double *__restrict__ lam1,
                                                 double scale, double *__restrict__ dc) {
+  constexpr int LBC = NC > 0 ? fft_lines_per_group(NC) : 0;
+  const int n = NC > 0 ? NC : n_arg;
+  const int lb = NC > 0 ? LBC : lb_arg;
   extern __shared__ double2 lds[];
   double2 *a = lds;
   double2 *b = lds + lb * n;
   double2 *tw = lds + 2 * lb * n;  // tw[m] = exp(-2 pi i m / n)
-  for (int m = threadIdx.x; m < n; m += blockDim.x) {
-    double sv, cv;
-    sincospi(-2.0 * (double)m / (double)n, &sv, &cv);
-    tw[m] = make_double2(cv, sv);
-  }
+  auto twiddles = [&]() {
+    for (int m = threadIdx.x; m < n; m += kBlock) {
+      double sv, cv;
+      sincospi(-2.0 * (double)m / (double)n, &sv, &cv);
+      tw[m] = make_double2(cv, sv);
+    }
+  };
+  if (NC == 0) twiddles();
   const i64 n2 = (i64)n * n;
   // batch decoding: for x lines the batch is lb consecutive y rows of one z;
   // for y and z lines the batch is lb consecutive x of one (z) or (y).
@@ -699,7 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
   }
   const double sign = (mode == 2 || mode == 4) ? 1.0 : -1.0;
   // load: element index e over lines, consecutive threads take consecutive lines
-  for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
+  auto load_elem = [&](int t) -> double2 {
     int line, e;
     if (axis == 0) { line = t / n; e = t % n; } else { e = t / lb; line = t % lb; }
     double2 v = make_double2(0.0, 0.0);
@@ -708,13 +814,37 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
       if (mode == 1) v = make_double2(((const double *)in)[gi], 0.0);
       else v = ((const double2 *)in)[gi];
     }
-    a[line * n + e] = v;
+    return v;
+  };
+  auto lds_index = [&](int t) {
+    return axis == 0 ? t : (t % lb) * n + t / lb;
+  };
+  double2 *res;
+  if constexpr (NC > 0) {
+    // every load of the batch in flight before the twiddle table is computed
+    constexpr int PER = (LBC * NC + kBlock - 1) / kBlock;
+    double2 v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = (int)threadIdx.x + i * kBlock;
+      v[i] = (t < LBC * NC) ? load_elem(t) : make_double2(0.0, 0.0);
+    }
+    twiddles();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = (int)threadIdx.x + i * kBlock;
+      if (t < LBC * NC) a[lds_index(t)] = v[i];
+    }
+    __syncthreads();
+    res = fft_lines_c<NC, LBC, 0>(a, b, sign, tw);
+  } else {
+    for (int t = threadIdx.x; t < lb * n; t += kBlock) a[lds_index(t)] = load_elem(t);
+    __syncthreads();
+    res = fft_lines(a, b, n, lb, f, sign, tw);
   }
-  __syncthreads();
-  double2 *res = fft_lines(a, b, n, lb, f, sign, tw);
   if (mode == 3) {
     // z lines: element e is kz; the line is (kx = first + line, ky = outer)
-    for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
+    for (int t = threadIdx.x; t < lb * n; t += kBlock) {
       const int line = t / n, e = t % n;
       double2 v = res[t];
       if (line < nl) {
@@ -730,9 +860,10 @@ __global__ __launch_bounds__(kBlock) void k_fft(const void *__restrict__ in,
     }
     __syncthreads();
     double2 *other = (res == a) ? b : a;
-    res = fft_lines(res, other, n, lb, f, 1.0, tw);
+    if constexpr (NC > 0) res = fft_lines_c<NC, LBC, 0>(res, other, 1.0, tw);
+    else res = fft_lines(res, other, n, lb, f, 1.0, tw);
   }
-  for (int t = threadIdx.x; t < lb * n; t += blockDim.x) {
+  for (int t = threadIdx.x; t < lb * n; t += kBlock) {
     int line, e;
     if (axis == 0) { line = t / n; e = t % n; } else { e = t / lb; line = t % lb; }
     if (line < nl) {
@@ -1174,17 +1305,29 @@ hipError_t launch_spectral_inverse(const double *r, double *out, double2 *w0, do
   const int groups = (n + lb - 1) / lb;
   const dim3 grid(groups * n), block(kBlock);
   const double invn3 = scale / ((double)n * n * n);
-  // x forward (real in) -> y forward -> z forward, divide, z inverse -> y inverse -> x inverse
-  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)r, (void *)w0, n, 0, lb, 1, f,
-                     lam1, 1.0, (double *)nullptr);
-  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 0, f,
-                     lam1, 1.0, (double *)nullptr);
-  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w1, (void *)w0, n, 2, lb, 3, f,
-                     lam1, invn3, sum_r);
-  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 4, f,
-                     lam1, 1.0, (double *)nullptr);
-  hipLaunchKernelGGL(k_fft, grid, block, lds, s, (const void *)w1, (void *)out, n, 0, lb, 2, f,
-                     lam1, 1.0, (double *)nullptr);
+  // x forward (real in) -> y forward -> z forward, divide, z inverse -> y inverse -> x inverse;
+  // the grid sizes of the workloads have transforms specialised on n
+  auto run = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, block, lds, s, (const void *)r, (void *)w0, n, 0, lb, 1, f,
+                       lam1, 1.0, (double *)nullptr);
+    hipLaunchKernelGGL(kern, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 0, f,
+                       lam1, 1.0, (double *)nullptr);
+    hipLaunchKernelGGL(kern, grid, block, lds, s, (const void *)w1, (void *)w0, n, 2, lb, 3, f,
+                       lam1, invn3, sum_r);
+    hipLaunchKernelGGL(kern, grid, block, lds, s, (const void *)w0, (void *)w1, n, 1, lb, 4, f,
+                       lam1, 1.0, (double *)nullptr);
+    hipLaunchKernelGGL(kern, grid, block, lds, s, (const void *)w1, (void *)out, n, 0, lb, 2, f,
+                       lam1, 1.0, (double *)nullptr);
+  };
+  switch (n) {
+    case 16: run(k_fft<16>); break;
+    case 32: run(k_fft<32>); break;
+    case 48: run(k_fft<48>); break;
+    case 64: run(k_fft<64>); break;
+    case 96: run(k_fft<96>); break;
+    case 128: run(k_fft<128>); break;
+    default: run(k_fft<0>); break;
+  }
   return hipGetLastError();
 }
 
