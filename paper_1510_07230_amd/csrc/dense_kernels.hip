@@ -75,8 +75,12 @@ __global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict
   d4 acc = d4{0, 0, 0, 0};
   if (J <= I) {
     const int ia = 16 * I + r16, jb = 16 * J + r16;
+    const int iac = min(ia, N - 1), jbc = min(jb, N - 1);
     // K tiles in batches of eight whose loads are all issued before their
-    // products (the tile is latency-bound: one wave, up to 32 K tiles)
+    // products (the tile is latency-bound: one wave, up to 32 K tiles).  The
+    // loads read clamped, always-valid addresses and the values outside the
+    // tile's range are replaced afterwards: a guarded load would sit in a
+    // branch of its own and be waited on before the next one is issued.
     for (int K0 = J; K0 <= I; K0 += 8) {
       double a[8][4], b[8][4];
 #pragma unroll
@@ -85,11 +89,22 @@ __global__ __launch_bounds__(64) void k_combine_factors(const double *__restrict
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           const int k = 16 * K + 4 * s4 + q;
-          const bool in = K <= I && k < N;
-          a[kk][s4] = (in && ia < N) ? A[(i64)ia * N + k] : 0.0;
-          double bv = (in && jb < N) ? B[(i64)k * N + jb] : 0.0;
-          if (split_b && in && jb < N) {
-            const double dlt = (k == jb) ? 1.0 : 0.0;
+          const int kc = min(k, N - 1);
+          a[kk][s4] = A[(i64)iac * N + kc];
+          b[kk][s4] = B[(i64)kc * N + jbc];
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int K = K0 + kk;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 16 * K + 4 * s4 + q;
+          const bool in = (K <= I) & (k < N);
+          a[kk][s4] = (in & (ia < N)) ? a[kk][s4] : 0.0;
+          double bv = (in & (jb < N)) ? b[kk][s4] : 0.0;
+          if (split_b) {
+            const double dlt = (in & (k == jb)) ? 1.0 : 0.0;
             __bf16 hi, lo;
             split_bf16((float)(bv - dlt), hi, lo);
             bv = dlt + ((double)(float)hi + (double)(float)lo);

@@ -1155,6 +1155,8 @@ __global__ __launch_bounds__(64) void k_bb_tau(const double *__restrict__ red, i
   out[4] = yy;
 }
 
+constexpr int kArmijoMaxN = 512;  // the library admits at most 512 orbitals
+
 // Test of eq. "ene-de" for a trial on the device, so that the accept can be
 // enqueued before the host has read the trial's energy.  rep is the trial's
 // evaluation report (sigma N | kin N | e4 | orth info 2*npass at orth_off |
@@ -1170,15 +1172,23 @@ __global__ void k_armijo(const double *__restrict__ rep, const double *__restric
                          unsigned terms, int npass, int orth_off, int rr_off, double rtol2,
                          const double *__restrict__ scal, double tscale, double C, double rho1,
                          int force, double *__restrict__ ext) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // no fused multiply-adds: the energy is rounded step by step as the host
+  // rounds it when it reports the trial's terms
+#pragma clang fp contract(off)
+  // the wave forms the N products f_i t_i (N <= kArmijoMaxN) in LDS; lane 0
+  // sums them in orbital order and takes the decision
+  __shared__ double sp[kArmijoMaxN];
+  if (blockIdx.x != 0) return;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) sp[i] = occ[i] * rep[N + i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   for (int k = 0; k < 5; ++k) ext[k] = scal[k];
   double *flags = ext + 5;
   const double rr = rep[rr_off], bb = rep[rr_off + 1];
   bool ok = isfinite(rr) && isfinite(bb) && rr <= rtol2 * bb;
   for (int p = 0; p < npass; ++p) ok = ok && rep[orth_off + 2 * p] == 0.0;
   double ekin = 0.0;
-#pragma unroll 16
-  for (int i = 0; i < N; ++i) ekin += occ[i] * rep[N + i];
+  for (int i = 0; i < N; ++i) ekin += sp[i];
   const double cx = 0.73855876638202240;  // 3/4 (3/pi)^(1/3)
   double E = (terms & 1u) ? ekin : 0.0;
   E += (terms & 8u) ? -cx * rep[2 * N + 0] : 0.0;
@@ -1397,6 +1407,7 @@ hipError_t launch_armijo(const double *rep, const double *occ, int N, unsigned t
                          int orth_off, int rr_off, double rtol2, const double *scal,
                          double tscale, double C, double rho1, int force, double *ext,
                          hipStream_t s) {
+  if (N < 1 || N > kArmijoMaxN) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_armijo, dim3(1), dim3(64), 0, s, rep, occ, N, terms, npass, orth_off,
                      rr_off, rtol2, scal, tscale, C, rho1, force, ext);
   return hipGetLastError();
