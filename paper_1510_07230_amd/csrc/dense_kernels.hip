@@ -282,8 +282,11 @@ __global__ __launch_bounds__(NTHR) void k_chol_blocked(const double *__restrict_
       const int r = r0 + NW * u;
 #pragma unroll
       for (int j = 0; j < CPR; ++j) {
+        // clamped, always-valid address; the value is zeroed below the test
+        // (a guarded load would be issued in a branch of its own)
         const int c = l + 64 * j;
-        v[u][j] = (r < N && c <= r) ? G[(i64)r * N + c] : 0.0;
+        const double g = G[(i64)min(r, N - 1) * N + min(c, N - 1)];
+        v[u][j] = ((r < N) & (c <= r)) ? g : 0.0;
       }
     }
 #pragma unroll
@@ -1532,29 +1535,32 @@ __global__ __launch_bounds__(kBlock) void k_rotate(const double *__restrict__ P,
 }
 
 // G = dv * sum over splits of the 128 x 128 partial upper triangles; both
-// halves.  Lane = element (coalesced over the 128 x 128 partial), the four
-// waves of a workgroup take every fourth split and combine through LDS.
-__global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__restrict__ part,
-                                                              int N, int nsplit, double dv,
-                                                              double *__restrict__ G) {
-  __shared__ double sacc[4][64];
+// halves.  Lane = element (coalesced over the 128 x 128 partial), the
+// sixteen waves of a workgroup take every sixteenth split and combine
+// through LDS in wave order.
+constexpr int kRedW = 16;  // waves of the small Gram reduction
+__global__ __launch_bounds__(64 * kRedW) void k_gram_reduce_small(const double *__restrict__ part,
+                                                                  int N, int nsplit, double dv,
+                                                                  double *__restrict__ G) {
+  __shared__ double sacc[kRedW][64];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int e = blockIdx.x * 64 + lane;  // element of the 128 x 128 partial
   // the partials hold the upper triangle only: skip ranges entirely below it
   if (((blockIdx.x * 64) & 127) + 63 < (int)((blockIdx.x * 64) >> 7)) return;
   // 16 independent loads in flight per lane (the sum is latency-bound: few
-  // workgroups, each reading one 64-element column of every partial)
+  // workgroups, each reading one 64-element column of every partial); with
+  // sixteen waves, 256 splits take one round of loads
   constexpr int U = 16;
   double acc[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) acc[u] = 0.0;
   int sp = w;
-  for (; sp + 4 * (U - 1) < nsplit; sp += 4 * U) {
+  for (; sp + kRedW * (U - 1) < nsplit; sp += kRedW * U) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] += part[(i64)(sp + 4 * u) * 128 * 128 + e];
+    for (int u = 0; u < U; ++u) acc[u] += part[(i64)(sp + kRedW * u) * 128 * 128 + e];
   }
-  for (; sp < nsplit; sp += 4) acc[0] += part[(i64)sp * 128 * 128 + e];
+  for (; sp < nsplit; sp += kRedW) acc[0] += part[(i64)sp * 128 * 128 + e];
 #pragma unroll
   for (int h = U / 2; h >= 1; h /= 2)
 #pragma unroll
@@ -1562,7 +1568,10 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce_small(const double *__re
   sacc[w][lane] = acc[0];
   __syncthreads();
   if (w == 0) {
-    const double v = (sacc[0][lane] + sacc[1][lane] + sacc[2][lane] + sacc[3][lane]) * dv;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRedW; ++k) v += sacc[k][lane];
+    v *= dv;
     const int r = e >> 7, c = e & 127;
     if (r <= c && c < N) {
       G[(i64)r * N + c] = v;
@@ -2756,8 +2765,8 @@ return hipErrorInvalidValue;
 hipError_t launch_gram_reduce(const double *part, int N, int nsplit, double dv, double *G,
                               hipStream_t s) {
   if (N <= 128) {
-    hipLaunchKernelGGL(k_gram_reduce_small, dim3(128 * 128 / 64), dim3(kBlock), 0, s, part, N,
-                       nsplit, dv, G);
+    hipLaunchKernelGGL(k_gram_reduce_small, dim3(128 * 128 / 64), dim3(64 * kRedW), 0, s, part,
+                       N, nsplit, dv, G);
     return hipGetLastError();
   }
   const int nbb = (N + kBB - 1) / kBB;
