@@ -608,7 +608,9 @@ __global__ __launch_bounds__(kBlock) void k_gram_small(const T *__restrict__ A, 
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
-      ca[e] = (row < N) ? (T)(1.0 + tau * sig[row]) : (T)0;
+      // clamped load, then the test: a guarded load would wait in a branch of its own
+      const double sv = sig[min(row, N - 1)];
+      ca[e] = (row < N) ? (T)(1.0 + tau * sv) : (T)0;
     }
   }
   auto load = [&](i64 k0) {
@@ -706,7 +708,8 @@ __global__ __launch_bounds__(kBlock) void k_gram_small_bf16(const float *__restr
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
-      ca[e] = (row < N) ? (float)(1.0 + tau * sig[row]) : 0.0f;
+      const double sv = sig[min(row, N - 1)];  // clamped load, then the test
+      ca[e] = (row < N) ? (float)(1.0 + tau * sv) : 0.0f;
     }
   }
   // chunks with every row and point inside the range load and store with no
@@ -856,7 +859,9 @@ __device__ __attribute__((always_inline)) inline void apply_s3_body(
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int i = 32 * kc + 8 * q + e;
-        const float v = (j < N && i < N) ? D[(i64)j * N + i] : 0.0f;
+        // clamped load, zeroed outside the factor (no branch per load)
+        const float dv = D[(i64)min(j, N - 1) * N + min(i, N - 1)];
+        const float v = ((j < N) & (i < N)) ? dv : 0.0f;
         __bf16 a, b, c;
         split3_bf16(v, a, b, c);
         d[kc][0][e] = a;
@@ -867,14 +872,19 @@ __device__ __attribute__((always_inline)) inline void apply_s3_body(
   };
   if (kc0 > 0) load_d(d0, jt0, kc0);
   if (kc1 > 0) load_d(d1, jt1, kc1);
-  double occv[2][4];
+  // occupations of the lane's output rows (clamped loads under one uniform
+  // test; zero for rows outside the problem)
+  double occv[2][4] = {};
+  if (rho != nullptr) {
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int jt = u == 0 ? jt0 : jt1;
+    for (int u = 0; u < 2; ++u) {
+      const int jt = u == 0 ? jt0 : jt1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = 16 * jt + 4 * q + r;
-      occv[u][r] = (rho != nullptr && jt < NT && j < N) ? occ[j] : 0.0;
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * jt + 4 * q + r;
+        const double o = occ[min(j, N - 1)];
+        occv[u][r] = ((jt < NT) & (j < N)) ? o : 0.0;
+      }
     }
   }
   // loader: point col; orbitals 32 wv + 8 hf + e and 32 wv + 16 + 8 hf + e
@@ -1079,14 +1089,19 @@ __global__ __launch_bounds__(kAB) void k_apply8(const T *__restrict__ D, const T
     default: apply_load_a<T, NT, 3>(D, N, a0, a1, r16, q); break;
   }
   const int jt0 = pw, jt1 = 7 - pw;
-  double occv[2][4];
+  // occupations of the lane's output rows (clamped loads under one uniform
+  // test; zero for rows outside the problem)
+  double occv[2][4] = {};
+  if (rho != nullptr) {
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int jt = u == 0 ? jt0 : jt1;
+    for (int u = 0; u < 2; ++u) {
+      const int jt = u == 0 ? jt0 : jt1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = 16 * jt + out_row<T>(q, r);
-      occv[u][r] = (rho != nullptr && jt < NT && j < N) ? occ[j] : 0.0;
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * jt + out_row<T>(q, r);
+        const double o = occ[min(j, N - 1)];
+        occv[u][r] = ((jt < NT) & (j < N)) ? o : 0.0;
+      }
     }
   }
   const i64 nblk = (ng + GC - 1) / GC;
@@ -1268,7 +1283,9 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int i = 32 * kc + 8 * q + e;
-        const float d = (jt < NT && j < N && i < N) ? D[(i64)j * N + i] : 0.0f;
+        // clamped load, zeroed outside the factor (no branch per load)
+        const float dv = D[(i64)min(j, N - 1) * N + min(i, N - 1)];
+        const float d = ((jt < NT) & (j < N) & (i < N)) ? dv : 0.0f;
         __bf16 a, b;
         split_bf16(d, a, b);
         dh[u][kc][e] = a;
