@@ -2478,8 +2478,7 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = f4{0, 0, 0, 0};
-  auto compute = [&](int b, int kc) {
-    if (kc >= wkc) return;
+  auto compute = [&](int b) __attribute__((always_inline)) {
     bf8 bh[4], bl[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -2501,6 +2500,23 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
       }
     }
   };
+  // The staging of the next chunk (the split of X into BF16 pieces and the
+  // LDS stores) is spread over the products of this one: an MFMA holds the
+  // matrix pipe for 16 cycles, in which the wave can issue a few independent
+  // vector instructions.
+  auto interleave = [&]() __attribute__((always_inline)) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // factor fragment reads
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // X fragment reads
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two vector instructions
+        if (i % 8 == 7) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // an LDS store
+      }
+    }
+  };
   // Two chunks per trip, every load and store unconditional (chunk indices
   // beyond the last are clamped to it: their stages are never multiplied), so
   // the compiler cannot merge them ahead of the products.  Invariant at the
@@ -2513,14 +2529,23 @@ void k_apply_big(const __bf16 *__restrict__ Dh, const __bf16 *__restrict__ Dl,
   load(sa, min(1, nkc - 1));
   for (int kc = 0; kc < nkc; kc += 2) {
     load(sb, min(kc + 2, nkc - 1));
-    compute(0, kc);
-    __builtin_amdgcn_sched_barrier(0);
-    stash(sa, 1);
+    // the chunk test is uniform: products and staging stay in one block
+    if (kc < wkc) {
+      compute(0);
+      stash(sa, 1);
+      interleave();
+    } else {
+      stash(sa, 1);
+    }
     __syncthreads();
     load(sa, min(kc + 3, nkc - 1));
-    compute(1, kc + 1);
-    __builtin_amdgcn_sched_barrier(0);
-    stash(sb, 0);
+    if (kc + 1 < wkc) {
+      compute(1);
+      stash(sb, 0);
+      interleave();
+    } else {
+      stash(sb, 0);
+    }
     __syncthreads();
   }
   // lane (r16, q) of tile (a, c) holds orbital 16 a + r16 at points 4 q .. 4 q + 3;
