@@ -1229,38 +1229,47 @@ __device__ inline void gram_tiles_split(const __bf16 (*hs)[PB], const __bf16 (*m
   }
 }
 
+// LDS stages of k_apply_gram8 for NT row tiles: X of one 32-point block as
+// FP32 [orbital][point] (identity term) and BF16 hi/lo [point][orbital]
+// (products); W1 of one block as three BF16 pieces [orbital][point].  FP32
+// pitch 36: the loader's writes (wave halves eight rows apart) and the
+// 16-byte identity reads fall in distinct banks.
 template <int NT>
-__global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D,
-                                                     const float *__restrict__ X, int N, i64 ng,
-                                                     double *__restrict__ part) {
+struct Ag8X {
+  static constexpr int NCH = (16 * NT + 31) / 32;  // K chunks of 32 orbitals
+  static constexpr int PX = 32 * NCH + 8;         // 16-byte aligned rows
+  float xs[16 * NT][36];
+  __bf16 xh[32][PX];
+  __bf16 xl[32][PX];
+};
+template <int NT>
+struct Ag8P {
+  __bf16 hs[16 * NT][40];
+  __bf16 ms[16 * NT][40];
+  __bf16 ls[16 * NT][40];
+};
+
+// The body of k_apply_gram8 for wave (pair PW, half H), with the wave's row
+// tiles and Gram tiles known at compile time, so that one block's apply and
+// the previous block's Gram lie in one basic block the scheduler can
+// interleave.  Two stages of each kind: block i is multiplied out of one X
+// stage while block i + 1 is staged in the other, and the Gram of block i - 1
+// reads one W1 stage while block i's pieces go to the other, so one barrier
+// per block separates every write from the reads of the same stage.
+template <int NT, int PW, int H>
+__device__ __attribute__((always_inline)) inline void apply_gram8_body(
+    const float *__restrict__ D, const float *__restrict__ X, int N, i64 ng,
+    double *__restrict__ part, Ag8X<NT> &xa, Ag8X<NT> &xb, Ag8P<NT> &pa, Ag8P<NT> &pb) {
+  typedef Ag8X<NT> XStage;
+  typedef Ag8P<NT> PStage;
   constexpr int GC = 32;
   constexpr int ROWS = 16 * NT;
-  // FP32 pitch 36: the loader's writes (wave halves eight rows apart) and the
-  // 16-byte identity reads below fall in distinct banks
-  constexpr int PITCH = GC + 4;
-  constexpr int PB = GC + 8;        // W1 pieces: [orbital][point]
-  constexpr int NCH = (ROWS + 31) / 32;  // K chunks of 32 orbitals
-  constexpr int PX = 32 * NCH + 8;       // X pieces: [point][orbital], 16-byte aligned rows
-  // Two stages of each kind: block i is multiplied out of one X stage while
-  // block i + 1 is staged in the other, and the Gram of block i - 1 reads one
-  // W1 stage while block i's pieces go to the other, so one barrier per block
-  // separates every write from the reads of the same stage.
-  struct XStage {
-    float xs[ROWS][PITCH];
-    __bf16 xh[GC][PX];
-    __bf16 xl[GC][PX];
-  };
-  struct PStage {
-    __bf16 hs[ROWS][PB];
-    __bf16 ms[ROWS][PB];
-    __bf16 ls[ROWS][PB];
-  };
-  __shared__ __attribute__((aligned(16))) XStage xa, xb;
-  __shared__ __attribute__((aligned(16))) PStage pa, pb;
+  constexpr int PB = 40;
+  constexpr int NCH = XStage::NCH;
   const int t = threadIdx.x;
-  const int w = t >> 6, l = t & 63, r16 = l & 15, q = l >> 4;
-  const int pw = w & 3, h = w >> 2;
-  const int jt0 = pw, jt1 = 7 - pw;
+  const int l = t & 63, r16 = l & 15, q = l >> 4;
+  constexpr int pw = PW, h = H;
+  constexpr int jt0 = pw, jt1 = 7 - pw;
   // orbitals ROWS .. 32 NCH - 1 of the last K chunk are never loaded: keep their
   // pieces zero (an uninitialised NaN pattern times a zero D entry is NaN)
   if (32 * NCH > ROWS) {
@@ -1375,14 +1384,10 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
     }
   };
   auto gram = [&](const PStage &pc) __attribute__((always_inline)) {
-#define POU_G8(P)                                                                        \
-  case P:                                                                                \
-    if (h == 0) gram_tiles_split<NT, P, 0, 5, PB>(pc.hs, pc.ms, pc.ls, gd, r16, q);      \
-    else                                                                                 \
-      gram_tiles_split<NT, P, 5, 9, PB>(pc.hs, pc.ms, pc.ls, *(double(*)[4][4]) & gd, r16, q); \
-    break;
-    switch (pw) { POU_G8(0) POU_G8(1) POU_G8(2) POU_G8(3) }
-#undef POU_G8
+    if constexpr (H == 0)
+      gram_tiles_split<NT, PW, 0, 5, PB>(pc.hs, pc.ms, pc.ls, gd, r16, q);
+    else
+      gram_tiles_split<NT, PW, 5, 9, PB>(pc.hs, pc.ms, pc.ls, *(double(*)[4][4]) & gd, r16, q);
   };
   // Invariant at the top of a step on block b: stage xc holds block b, na
   // holds block b + G and nb has block b + 2G in flight; the other W1 stage
@@ -1435,6 +1440,27 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
       for (int r = 0; r < 4; ++r)
         outp[(16 * rt + 4 * q + r) * 128 + 16 * ct + r16] = gd[uu][r];
     }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D,
+                                                     const float *__restrict__ X, int N, i64 ng,
+                                                     double *__restrict__ part) {
+  __shared__ __attribute__((aligned(16))) Ag8X<NT> xa, xb;
+  __shared__ __attribute__((aligned(16))) Ag8P<NT> pa, pb;
+  // the wave index as a scalar: a divergent branch would put EXEC masks
+  // around the MFMA instructions of each path
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  switch (w) {
+    case 0: apply_gram8_body<NT, 0, 0>(D, X, N, ng, part, xa, xb, pa, pb); break;
+    case 1: apply_gram8_body<NT, 1, 0>(D, X, N, ng, part, xa, xb, pa, pb); break;
+    case 2: apply_gram8_body<NT, 2, 0>(D, X, N, ng, part, xa, xb, pa, pb); break;
+    case 3: apply_gram8_body<NT, 3, 0>(D, X, N, ng, part, xa, xb, pa, pb); break;
+    case 4: apply_gram8_body<NT, 0, 1>(D, X, N, ng, part, xa, xb, pa, pb); break;
+    case 5: apply_gram8_body<NT, 1, 1>(D, X, N, ng, part, xa, xb, pa, pb); break;
+    case 6: apply_gram8_body<NT, 2, 1>(D, X, N, ng, part, xa, xb, pa, pb); break;
+    default: apply_gram8_body<NT, 3, 1>(D, X, N, ng, part, xa, xb, pa, pb); break;
   }
 }
 
