@@ -16,6 +16,7 @@ in the same JSON line.
 """
 import argparse
 import json
+import statistics
 import math
 import os
 import sys
@@ -83,17 +84,17 @@ def mfma_floor(group, N, ng, es):
 
     A triangular apply L^-1 X and a symmetric Gram X X^T each take N(N+1)
     flops per grid point.  The mixed first Gram runs on BF16 MFMA; the fused
-    apply + second Gram does both contractions as four BF16 products each
-    (hi/lo split), so its floor is eight BF16 products.  Above 128 FP32
-    orbitals the apply and the second Gram are four split-BF16 products
-    each."""
+    apply + second Gram does the apply as four BF16 products (hi/lo pieces of
+    both operands) and the Gram of the three-piece W1 as six, so its floor is
+    ten BF16 products.  Above 128 FP32 orbitals the apply and the second Gram
+    are four split-BF16 products each."""
     tri = float(N * (N + 1) * ng)
     wide = "f64" if es == 8 else "f32"
     big = es == 4 and N > 128  # FP32 orbitals above 128: split-BF16 kernels
     if group == "apply":
         return tri, (4 * tri / PEAK_FLOPS["bf16"]) if big else tri / PEAK_FLOPS[wide]
     if group == "apply_gram":
-        return 2 * tri, 8 * tri / PEAK_FLOPS["bf16"]
+        return 2 * tri, 10 * tri / PEAK_FLOPS["bf16"]
     if group == "trial":
         if N > 128:  # the trial point alone; its Gram is the "gram" group
             return 0.0, 0.0
@@ -364,8 +365,9 @@ def run(args):
                  "speedup": r["time_to_1e-6_s"]["speedup"], "mixed_steps": r["mixed_steps"],
                  "refine_steps": r["refine_steps"], "fp64_steps": r["fp64_steps"]}
                 for r in runs]
-            ok = sorted(x for x in sp if x is not None)
-            out["delta_E"]["median_speedup"] = ok[len(ok) // 2] if ok else None
+            ok = [x for x in sp if x is not None]
+            # the median proper: the mean of the two middle values for an even count
+            out["delta_E"]["median_speedup"] = statistics.median(ok) if ok else None
     if not args.no_cpu_baseline:
         progress("oracle CPU baseline")
         del g64, g32, U64, U32, W0
