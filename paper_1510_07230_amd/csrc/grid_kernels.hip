@@ -564,7 +564,9 @@ struct Radices {
   int r[16];
 };
 
-__host__ inline Radices factorize(int n) {
+// Radix plan of a length-n transform (4s first, then 2, 3, 5, other primes);
+// constexpr, so the transforms specialised on n take it at compile time.
+constexpr Radices factorize(int n) {
   Radices f{};
   f.nr = 0;
   int m = n;
@@ -643,20 +645,6 @@ __device__ inline void fft_stage(const double2 *a, double2 *b, int n, int lb, in
   }
 }
 
-// The same radix plan at compile time, for the transforms specialised on n.
-constexpr Radices factorize_c(int n) {
-  Radices f{};
-  f.nr = 0;
-  int m = n;
-  while (m % 4 == 0) { f.r[f.nr++] = 4; m /= 4; }
-  while (m % 2 == 0) { f.r[f.nr++] = 2; m /= 2; }
-  while (m % 3 == 0) { f.r[f.nr++] = 3; m /= 3; }
-  while (m % 5 == 0) { f.r[f.nr++] = 5; m /= 5; }
-  for (int p = 7; p * p <= m; p += 2)
-    while (m % p == 0) { f.r[f.nr++] = p; m /= p; }
-  if (m > 1) f.r[f.nr++] = m;
-  return f;
-}
 constexpr int radix_span(const Radices &f, int st) {
   int p = 1;
   for (int i = 0; i < st; ++i) p *= f.r[i];
@@ -730,7 +718,7 @@ __device__ inline void fft_stage_c(const double2 *a, double2 *b, double sign, co
 
 template <int N, int LB, int ST>
 __device__ inline double2 *fft_lines_c(double2 *a, double2 *b, double sign, const double2 *tw) {
-  constexpr Radices F = factorize_c(N);
+  constexpr Radices F = factorize(N);
   if constexpr (ST == F.nr) {
     return a;
   } else {
