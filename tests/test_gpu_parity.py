@@ -51,6 +51,35 @@ def test_fields_energy_hamiltonian(cfg):
     assert np.max(np.abs(sig - ks.inner(W, HU_o, so.h))) < 1e-10
 
 
+# grid sizes with a transform specialised on n (16, 48 and 96 are covered
+# above and by the full-size test)
+FFT_CASES = [
+    synth.custom("fft32", 32, 9.0, 3, 2.0, 0.5, 3, min_sep=1.5, seed_id=231),
+    synth.custom("fft64", 64, 16.0, 4, (1.0, 2.0), (0.45, 0.7), 2, min_sep=1.5, seed_id=232),
+    synth.custom("fft128", 128, 32.0, 4, 2.0, 0.5, 2, min_sep=1.5, seed_id=233),
+]
+
+
+@pytest.mark.parametrize("cfg", FFT_CASES, ids=lambda c: c.name)
+def test_hartree_on_specialised_fft_grids(cfg):
+    """rho, V_H (spectral inverse through the n-specialised FFT passes), V_eff
+    and the energy terms against the oracle on the remaining specialised n."""
+    print(f"[fft] {cfg.name} n={cfg.n} N={cfg.norb}", flush=True)
+    so = oracle_system(cfg)
+    W = _start(cfg, so)
+    g = gpu_system(cfg)
+    U = g.new_block(W)
+    e = g.energy(U)
+    rho, VH, vx, veff, ex, vext, _ = ks.potentials(W, so)
+    terms = ks.energy(W, so, vext)
+    f = g.fields()
+    assert rel(to_np(f["rho"]), rho) < 1e-13
+    assert rel(to_np(f["vh"]), VH) < 1e-11
+    assert rel(to_np(f["veff"]), veff) < 1e-11
+    for k in ("E", "E_H", "E_x"):
+        assert abs(e[k] - getattr(terms, k)) < 1e-9 * max(1.0, abs(terms.E)), (k, e[k], getattr(terms, k))
+
+
 @pytest.mark.parametrize("N", [1, 5, 70, 130])
 def test_gram_and_orthonormalize(N):
     cfg = synth.custom("orth", 16, 7.0, 1, 1.0, 0.5, N, seed_id=50 + N)
