@@ -1464,118 +1464,7 @@ __global__ __launch_bounds__(kAB) void k_apply_gram8(const float *__restrict__ D
   }
 }
 
-// ---------------------------------------------------------------- subspace rotation
-
-// Partial cross products C = A B^T over a contiguous range of grid points for
-// one 64 x 64 output tile (blockIdx.y = tile, row-major over the N x N
-// tiles): part[split][i][j] = sum_g A[i][g] B[j][g], FP64 accumulation; each
-// thread keeps a 4 x 4 block of the tile.  A plain tiled kernel: it serves
-// the subspace diagonalisation and the residual, which run every n_diag
-// steps or on request.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cross_gram(const T *__restrict__ A,
-                                                       const T *__restrict__ B, int N, i64 ng,
-                                                       i64 kper, double *__restrict__ part) {
-  constexpr int TB = 64, KC = 32;
-  __shared__ double sa[KC][TB + 1];
-  __shared__ double sb[KC][TB + 1];
-  const int nt = (N + TB - 1) / TB;
-  const int ti = blockIdx.y / nt, tj = blockIdx.y % nt;
-  const int t = threadIdx.x;
-  const int r0 = 4 * (t / 16), c0 = 4 * (t % 16);  // this thread: rows r0.., columns c0..
-  const i64 k_beg = (i64)blockIdx.x * kper;
-  const i64 k_end = min(ng, k_beg + kper);
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (i64 k0 = k_beg; k0 < k_end; k0 += KC) {
-    for (int e = t; e < TB * KC; e += kBlock) {
-      const int r = e / KC, k = e % KC;
-      const i64 g = k0 + k;
-      const int ia = TB * ti + r, jb = TB * tj + r;
-      sa[k][r] = (ia < N && g < k_end) ? (double)A[(i64)ia * ng + g] : 0.0;
-      sb[k][r] = (jb < N && g < k_end) ? (double)B[(i64)jb * ng + g] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < KC; ++k) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = sa[k][r0 + u];
-        b[u] = sb[k][c0 + u];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int i = TB * ti + r0 + x;
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int j = TB * tj + c0 + y;
-      if (i < N && j < N) part[((i64)blockIdx.x * N + i) * N + j] = acc[x][y];
-    }
-  }
-}
-
-// S_ij = dv/2 sum over splits (part_ij + part_ji): the symmetrised product.
-__global__ __launch_bounds__(kBlock) void k_cross_reduce(const double *__restrict__ part, int N,
-                                                         int nsplit, double dv,
-                                                         double *__restrict__ S) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
-    const int i = e / N, j = e % N;
-    double a = 0.0, b = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) {
-      a += part[((i64)sp * N + i) * N + j];
-      b += part[((i64)sp * N + j) * N + i];
-    }
-    S[e] = 0.5 * dv * (a + b);
-  }
-}
-
-// out[j][g] = sum_i P[i][j] X[i][g] (out = P^T X, i.e. the block X times P in
-// the orbital index), FP64 accumulation.  Thread: one grid point, 16 output
-// orbitals; P's 16 columns staged in LDS in chunks of 64 rows.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_rotate(const double *__restrict__ P,
-                                                   const T *__restrict__ X, T *__restrict__ out,
-                                                   int N, i64 ng) {
-  constexpr int JB = 16, IC = 64;
-  __shared__ double sp[IC][JB];
-  const i64 g = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = blockIdx.y * JB;
-  double acc[JB];
-#pragma unroll
-  for (int u = 0; u < JB; ++u) acc[u] = 0.0;
-  for (int i0 = 0; i0 < N; i0 += IC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < IC * JB; e += blockDim.x) {
-      const int i = i0 + e / JB, j = j0 + e % JB;
-      sp[e / JB][e % JB] = (i < N && j < N) ? P[(i64)i * N + j] : 0.0;
-    }
-    __syncthreads();
-    if (g < ng) {
-      const int ie = min(IC, N - i0);
-      for (int ii = 0; ii < ie; ++ii) {
-        const double x = (double)X[(i64)(i0 + ii) * ng + g];
-#pragma unroll
-        for (int u = 0; u < JB; ++u) acc[u] += sp[ii][u] * x;
-      }
-    }
-  }
-  if (g < ng) {
-#pragma unroll
-    for (int u = 0; u < JB; ++u)
-      if (j0 + u < N) out[(i64)(j0 + u) * ng + g] = (T)acc[u];
-  }
-}
+// ---------------------------------------------------------------- Gram reduction
 
 // G = dv * sum over splits of the 128 x 128 partial upper triangles; both
 // halves.  Lane = element (coalesced over the 128 x 128 partial), the
