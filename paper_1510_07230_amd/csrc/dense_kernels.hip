@@ -800,12 +800,17 @@ template <typename T, int NT, int W>
 __device__ inline void apply_load_a(const T *__restrict__ D, int N, T (&a0)[4 * NT],
                                     T (&a1)[4 * NT], int r16, int q) {
   constexpr int jt0 = W, jt1 = 7 - W;
+  // clamped, always-valid addresses; entries outside the factor's triangle
+  // or size are zeroed after the load (no branch per load)
 #pragma unroll
   for (int ks = 0; ks < 4 * NT; ++ks) {
     const int i = 4 * ks + q;
     const int j0 = 16 * jt0 + r16, j1 = 16 * jt1 + r16;
-    a0[ks] = (jt0 < NT && ks < 4 * (jt0 + 1) && j0 < N && i < N) ? D[(i64)j0 * N + i] : (T)0;
-    a1[ks] = (jt1 < NT && ks < 4 * (jt1 + 1) && j1 < N && i < N) ? D[(i64)j1 * N + i] : (T)0;
+    const int ic = min(i, N - 1);
+    const T v0 = D[(i64)min(j0, N - 1) * N + ic];
+    const T v1 = D[(i64)min(j1, N - 1) * N + ic];
+    a0[ks] = ((jt0 < NT) & (ks < 4 * (jt0 + 1)) & (j0 < N) & (i < N)) ? v0 : (T)0;
+    a1[ks] = ((jt1 < NT) & (ks < 4 * (jt1 + 1)) & (j1 < N) & (i < N)) ? v1 : (T)0;
   }
 }
 
@@ -1107,9 +1112,17 @@ __global__ __launch_bounds__(kAB) void k_apply8(const T *__restrict__ D, const T
   const i64 nblk = (ng + GC - 1) / GC;
   const int col = t % GC, row0 = t / GC;
   const i64 G = gridDim.x;
-  T na[PER], nb[PER];
+  T na[PER] = {}, nb[PER] = {};
+  // blocks with every row and point inside the problem load with no
+  // per-element tests (the tests would put each load in a branch of its own)
+  const bool all_rows = N == ROWS && ROWS % RSTEP == 0;
   auto load = [&](T (&dst)[PER], i64 blk) {
     const i64 g = blk * GC + col;
+    if (all_rows && blk * GC + GC <= ng) {
+#pragma unroll
+      for (int e = 0; e < PER; ++e) dst[e] = X[(i64)(row0 + RSTEP * e) * ng + g];
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int row = row0 + RSTEP * e;
@@ -1149,20 +1162,27 @@ __global__ __launch_bounds__(kAB) void k_apply8(const T *__restrict__ D, const T
     }
     const i64 g = blk * GC + 16 * h + r16;
     double rp = 0.0;
+    auto epilogue = [&](auto tested) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int jt = u == 0 ? jt0 : jt1;
-      if (jt >= NT) continue;
+      for (int u = 0; u < 2; ++u) {
+        const int jt = u == 0 ? jt0 : jt1;
+        if (jt >= NT) continue;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = 16 * jt + out_row<T>(q, r);
-        if (j < N && g < ng) {
-          const T v = xs[j][16 * h + r16] + (u == 0 ? acc0[r] : acc1[r]);
-          out[(i64)j * ng + g] = v;
-          rp += occv[u][r] * ((double)v * (double)v);
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * jt + out_row<T>(q, r);
+          if (!decltype(tested)::value || (j < N && g < ng)) {
+            const T v = xs[j][16 * h + r16] + (u == 0 ? acc0[r] : acc1[r]);
+            out[(i64)j * ng + g] = v;
+            rp += occv[u][r] * ((double)v * (double)v);
+          }
         }
       }
-    }
+    };
+    // a full block stores without per-element tests
+    if (all_rows && blk * GC + GC <= ng)
+      epilogue(std::false_type());
+    else
+      epilogue(std::true_type());
     if (rho != nullptr) {
       rp += __shfl_xor(rp, 16, 64);
       rp += __shfl_xor(rp, 32, 64);
