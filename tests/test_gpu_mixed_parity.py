@@ -109,7 +109,10 @@ def test_trial_point_matches_oracle(prec, norb, n):
     assert rG <= 1.0
 
 
-@pytest.mark.parametrize("norb,n", [(16, 32), (48, 27), (128, 33), (144, 20), (512, 16)])
+# N = 20, 64, 72, 90 take the remaining row-tile counts (2, 4, 5, 6) of the
+# N <= 128 fused apply + Gram and FP32 apply kernels
+@pytest.mark.parametrize("norb,n", [(16, 32), (48, 27), (128, 33), (144, 20), (512, 16),
+                                    (20, 24), (64, 22), (72, 21), (90, 24)])
 def test_mixed_steps_from_same_state(norb, n):
     cfg = _cfg(norb, n, 800 + norb)
     print(f"[mixed step] N={norb} n={n}", flush=True)
