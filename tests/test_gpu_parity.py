@@ -331,6 +331,36 @@ def test_fp64_more_than_128_orbitals_follow_oracle(norb, n):
     assert rel(to_np(U), A.W) < 1e-8
 
 
+@pytest.mark.parametrize("norb,n", [(60, 20), (96, 21), (110, 23), (128, 20)])
+def test_fp64_row_tile_counts_follow_oracle(norb, n):
+    """N <= 128 in FP64 with 4, 6, 7 and 8 row tiles of 16 orbitals (the
+    FP64 trial point + Gram and apply kernels are instantiated per tile
+    count): Gram, orthonormalisation and three steps against the oracle at
+    FP64 tolerances, on grids whose point count is not a multiple of 32."""
+    cfg = synth.custom(f"fp64_nt_N{norb}", n, 0.6 * n, max(1, norb // 2), 2.0, 0.5, norb,
+                       min_sep=0.5, seed_id=550 + norb)
+    print(f"[fp64 tiles] N={norb} n={n}", flush=True)
+    so = oracle_system(cfg)
+    X = synth.orbitals(cfg)
+    p = algm.Params()
+    p.tau_init = 1.0 / algm.lambda_max_kinetic(so.h)
+    g = gpu_system(cfg, "fp64", tau_init=p.tau_init)
+    U = g.new_block(X)
+    assert rel(g.gram(U), oorth.gram(X, so.h)) < 1e-13
+    err = g.orthonormalize_(U)
+    W_o, _ = oorth.orth(X, so.h)
+    assert err < 1e-12
+    assert rel(to_np(U), W_o) < 1e-9
+    A = algm.AlgorithmM(W_o, so, p, orthonormalize_start=False)
+    U = g.new_block(W_o)
+    for k in range(3):
+        r = A.step()
+        info = g.step_(U)
+        assert info["s"] == r.s, (k, info["s"], r.s)
+        assert abs(info["E"] - r.E) < 1e-9 * max(1, abs(r.E)), (k, info["E"], r.E)
+    assert rel(to_np(U), A.W) < 1e-8
+
+
 def test_plain_cg_matches_oracle():
     """cg_precond = 0: the Hartree potential by plain warm-started conjugate
     gradients (the solve as first stated for the method) matches the oracle's
